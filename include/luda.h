@@ -1,0 +1,172 @@
+/*
+ * luda.h -- GPU compaction of LSM-tree tables on AMD Instinct MI355X (gfx950).
+ *
+ * One compaction job merges the selected table of level i with the tables of
+ * level i+1 whose key ranges overlap it, drops stale versions, and writes new
+ * tables for level i+1 (paper Sec. II-A, "LSM-tree Compaction"; Phases 1-3:
+ * unpack, delete-and-sort, pack).  The whole path runs on the GPU: block
+ * checksums and prefix-shared key restoration, the merge and drop, and the
+ * re-encoding into data blocks, index block, Bloom filter block and footer
+ * (Sec. III-A overview, Sec. III-C kernels).
+ *
+ * Table format: LevelDB's table layout (the paper's prototype is built on
+ * LevelDB 1.22, Sec. IV-A), uncompressed blocks (Sec. IV-A), with:
+ *   - block trailer: type byte 0 + masked CRC32C of (contents || type);
+ *   - internal key = user key || fixed64 LE tag, tag = (seq << 8) | type,
+ *     type 1 = value, 0 = deletion;
+ *   - index entry key = the block's last internal key, verbatim;
+ *   - filter block named "filter.luda.bloom.xxh64": one Bloom filter per
+ *     2 KiB window of block start offsets (base_lg 11), bits = max(64, n*b),
+ *     k = clamp(b*69/100, 1, 30), probes from XXH64(user key, seed 0).
+ * Output tables are byte-for-byte those of the sequential writer rules:
+ *   - a data block is finished right after the entry that makes
+ *     (entry bytes + 4 * restart points + 4) >= block_size;
+ *   - a table is finished right after the block that makes its data bytes
+ *     (blocks + 5-byte trailers) >= target_file_size.
+ * Drop rule (no snapshots): the newest version of each user key survives
+ * (largest tag; equal tags: the earlier input, then the earlier position);
+ * a surviving deletion is dropped only when `bottommost` is set.
+ *
+ * Threading: a context is used by one thread at a time.  Errors are returned
+ * as status codes; no exception crosses this interface.
+ */
+#ifndef LUDA_H
+#define LUDA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LUDA_OK 0
+#define LUDA_INVALID_ARG (-1)      /* null pointer, zero block size, ... */
+#define LUDA_CORRUPT_FORMAT (-2)   /* bad magic, handle, varint, restart array, key */
+#define LUDA_CORRUPT_CHECKSUM (-3) /* a block's masked CRC32C does not match */
+#define LUDA_UNSORTED_INPUT (-4)   /* internal keys of one table not strictly increasing */
+#define LUDA_UNSUPPORTED (-5)      /* compressed block, or a size beyond the GPU path's limits */
+#define LUDA_NOMEM (-6)            /* device or host allocation failed */
+#define LUDA_DEVICE (-7)           /* HIP runtime error or a device-side wait gave up */
+
+/* where a reported corruption lies */
+#define LUDA_WHERE_FOOTER 0
+#define LUDA_WHERE_INDEX 1
+#define LUDA_WHERE_DATA 2
+
+typedef struct luda_ctx luda_ctx;
+
+/* A borrowed byte range: host memory for luda_compact, device memory for the
+ * *_dev entry points.  Must stay valid and unchanged until the call returns. */
+typedef struct {
+  const uint8_t *data;
+  uint64_t size;
+} luda_buf;
+
+typedef struct {
+  uint32_t block_size;         /* data block target bytes (> 0), e.g. 4096 */
+  uint32_t restart_interval;   /* entries per restart point (> 0), e.g. 16 */
+  uint32_t bloom_bits_per_key; /* Bloom filter bits per key (> 0), e.g. 10 */
+  uint32_t bottommost;         /* 1: the output level is the last level */
+  uint64_t target_file_size;   /* output table cut threshold in bytes (> 0) */
+} luda_options;
+
+/* The first corruption in reading order: inputs in order; inside an input the
+ * footer, the index block, then data blocks in index order; inside a block
+ * the trailer (phase 0), the restart array (1), then entries in order (2). */
+typedef struct {
+  int32_t status;
+  uint32_t input;  /* input index inside its job */
+  uint32_t where;  /* LUDA_WHERE_* */
+  uint32_t phase;  /* 0 trailer, 1 restart array, 2 entries (footer: 0) */
+  uint64_t block;  /* data block number inside the input (where == DATA) */
+  uint64_t offset; /* byte offset inside the block contents; for the footer,
+                      inside the file; saturates at 2^23 - 1 */
+} luda_error;
+
+typedef struct {
+  uint64_t offset;      /* start of this table inside luda_result.data */
+  uint64_t size;        /* bytes */
+  uint64_t num_entries; /* entries written to it */
+} luda_file;
+
+/* Result of one job.  `data` holds every output table back to back; it and
+ * `files` are owned by the library until luda_result_free(). */
+typedef struct {
+  int32_t status;
+  luda_error error;
+  uint32_t num_files;
+  luda_file *files;
+  uint8_t *data;       /* host memory (luda_compact), device memory (*_dev) */
+  uint64_t data_size;
+  uint64_t entries_in, entries_out, dropped_shadowed, dropped_tombstones;
+  uint64_t bytes_in, bytes_out;
+  double ms_total;     /* wall time of the call */
+  void *internal;      /* library bookkeeping */
+} luda_result;
+
+/* One job of a batch: inputs[0] is the upper (newest) table. */
+typedef struct {
+  const luda_buf *inputs;
+  uint32_t n_inputs;
+  luda_options options;
+} luda_job;
+
+/* Create a context on a HIP device.  Returns LUDA_OK or LUDA_DEVICE. */
+int luda_ctx_create(int device, luda_ctx **out);
+void luda_ctx_destroy(luda_ctx *ctx);
+
+/* Use a caller-owned HIP stream (hipStream_t) for all work; NULL restores
+ * the context's own stream.  The caller keeps ownership of the stream. */
+int luda_set_stream(luda_ctx *ctx, void *hip_stream);
+
+/* Compact one job whose inputs are in host memory (inputs[0] = upper, newest
+ * table).  Output tables are returned in host memory.  Zero inputs, or all
+ * entries dropped, give LUDA_OK with zero files.  On error no file is
+ * returned and out->error locates the first corruption. */
+int luda_compact(luda_ctx *ctx, const luda_buf *inputs, uint32_t n_inputs, const luda_options *opt,
+                 luda_result *out);
+
+/* As luda_compact, with inputs already in device memory; the output tables
+ * stay in device memory (out->data is a device pointer). */
+int luda_compact_dev(luda_ctx *ctx, const luda_buf *dev_inputs, uint32_t n_inputs,
+                     const luda_options *opt, luda_result *out);
+
+/* Compact many independent jobs in one pass: every stage runs once over all
+ * jobs together.  `device_inputs` selects device (1) or host (0) memory for
+ * the inputs and outputs.  results[] receives one result per job; a job that
+ * fails never changes another job's bytes.  Returns LUDA_OK unless the batch
+ * as a whole could not run. */
+int luda_compact_batch(luda_ctx *ctx, const luda_job *jobs, uint32_t n_jobs, int device_inputs,
+                       luda_result *results);
+
+/* Write ordered entries into tables with the same writer as the compaction
+ * (a memtable flush).  Entries are struct-of-arrays in device memory: user
+ * keys back to back with n + 1 offsets, tags, values back to back with n + 1
+ * offsets; internal keys must be strictly increasing.  Output tables stay in
+ * device memory.  Used to build input tables on the device. */
+int luda_build_tables_dev(luda_ctx *ctx, uint64_t n, const uint8_t *keys, const uint64_t *koff,
+                          const uint64_t *tags, const uint8_t *vals, const uint64_t *voff,
+                          const luda_options *opt, luda_result *out);
+
+void luda_result_free(luda_ctx *ctx, luda_result *r);
+
+const char *luda_status_str(int status);
+const char *luda_last_error(luda_ctx *ctx);
+
+/* Per-stage device times (milliseconds) of the last call, measured with HIP
+ * events on the context's stream; names[] and ms[] receive up to `cap`
+ * entries.  Returns the number of stages. */
+int luda_stage_times(luda_ctx *ctx, const char **names, double *ms, int cap);
+
+/* Diagnostics: copy `bytes` bytes at `offset` of the named internal device
+ * buffer of the last call into host memory `dst` (e.g. "tu_kp0", "surv").
+ * Returns LUDA_OK, or LUDA_INVALID_ARG for an unknown name or range. */
+int luda_debug_read(luda_ctx *ctx, const char *name, void *dst, uint64_t offset, uint64_t bytes);
+
+/* Host-side self check of the CRC32C shift tables (no device needed). */
+int luda_selftest_crc(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

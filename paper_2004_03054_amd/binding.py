@@ -1,0 +1,291 @@
+"""ctypes binding of libluda.so (include/luda.h): argument marshalling only.
+
+Every step of a compaction runs in the library's HIP kernels; this module
+turns Python buffers into luda_buf arrays and results back into bytes or
+device tensors.  It raises if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libluda.so")
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "CORRUPT_FORMAT", -3: "CORRUPT_CHECKSUM",
+          -4: "UNSORTED_INPUT", -5: "UNSUPPORTED", -6: "NOMEM", -7: "DEVICE"}
+
+
+class LudaBuf(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("size", C.c_uint64)]
+
+
+class LudaOptions(C.Structure):
+    _fields_ = [("block_size", C.c_uint32), ("restart_interval", C.c_uint32),
+                ("bloom_bits_per_key", C.c_uint32), ("bottommost", C.c_uint32),
+                ("target_file_size", C.c_uint64)]
+
+
+class LudaError(C.Structure):
+    _fields_ = [("status", C.c_int32), ("input", C.c_uint32), ("where", C.c_uint32),
+                ("phase", C.c_uint32), ("block", C.c_uint64), ("offset", C.c_uint64)]
+
+
+class LudaFile(C.Structure):
+    _fields_ = [("offset", C.c_uint64), ("size", C.c_uint64), ("num_entries", C.c_uint64)]
+
+
+class LudaResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("error", LudaError), ("num_files", C.c_uint32),
+                ("files", C.POINTER(LudaFile)), ("data", C.c_void_p), ("data_size", C.c_uint64),
+                ("entries_in", C.c_uint64), ("entries_out", C.c_uint64),
+                ("dropped_shadowed", C.c_uint64), ("dropped_tombstones", C.c_uint64),
+                ("bytes_in", C.c_uint64), ("bytes_out", C.c_uint64), ("ms_total", C.c_double),
+                ("internal", C.c_void_p)]
+
+
+class LudaJob(C.Structure):
+    _fields_ = [("inputs", C.POINTER(LudaBuf)), ("n_inputs", C.c_uint32), ("options", LudaOptions)]
+
+
+EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compact", "luda_compact_dev",
+           "luda_compact_batch", "luda_build_tables_dev", "luda_result_free", "luda_status_str",
+           "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read"]
+
+_lib = None
+
+
+def lib():
+    """Load libluda.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2004_03054_amd.build_lib.build()")
+    L = C.CDLL(LIB_PATH)
+    L.luda_ctx_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+    L.luda_ctx_create.restype = C.c_int
+    L.luda_ctx_destroy.argtypes = [C.c_void_p]
+    L.luda_ctx_destroy.restype = None
+    L.luda_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+    L.luda_set_stream.restype = C.c_int
+    for name in ("luda_compact", "luda_compact_dev"):
+        f = getattr(L, name)
+        f.argtypes = [C.c_void_p, C.POINTER(LudaBuf), C.c_uint32, C.POINTER(LudaOptions), C.POINTER(LudaResult)]
+        f.restype = C.c_int
+    L.luda_compact_batch.argtypes = [C.c_void_p, C.POINTER(LudaJob), C.c_uint32, C.c_int, C.POINTER(LudaResult)]
+    L.luda_compact_batch.restype = C.c_int
+    L.luda_build_tables_dev.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.POINTER(LudaOptions), C.POINTER(LudaResult)]
+    L.luda_build_tables_dev.restype = C.c_int
+    L.luda_result_free.argtypes = [C.c_void_p, C.POINTER(LudaResult)]
+    L.luda_result_free.restype = None
+    L.luda_status_str.argtypes = [C.c_int]
+    L.luda_status_str.restype = C.c_char_p
+    L.luda_last_error.argtypes = [C.c_void_p]
+    L.luda_last_error.restype = C.c_char_p
+    L.luda_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int]
+    L.luda_stage_times.restype = C.c_int
+    L.luda_debug_read.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_uint64, C.c_uint64]
+    L.luda_debug_read.restype = C.c_int
+    L.luda_selftest_crc.argtypes = []
+    L.luda_selftest_crc.restype = C.c_int
+    _lib = L
+    return L
+
+
+def options(d: dict) -> LudaOptions:
+    return LudaOptions(int(d["block_size"]), int(d["restart_interval"]), int(d["bloom_bits_per_key"]),
+                       int(d["bottommost"]), int(d["target_file_size"]))
+
+
+@dataclass
+class Error:
+    status: int
+    input: int = 0
+    where: int = 0
+    phase: int = 0
+    block: int = 0
+    offset: int = 0
+
+    @property
+    def name(self) -> str:
+        return STATUS.get(self.status, str(self.status))
+
+
+@dataclass
+class Result:
+    status: int
+    error: Error
+    files: list = field(default_factory=list)   # bytes (host) or torch uint8 tensors (device)
+    file_entries: List[int] = field(default_factory=list)
+    entries_in: int = 0
+    entries_out: int = 0
+    dropped_shadowed: int = 0
+    dropped_tombstones: int = 0
+    bytes_in: int = 0
+    bytes_out: int = 0
+    ms_total: float = 0.0
+
+    @property
+    def name(self) -> str:
+        return STATUS.get(self.status, str(self.status))
+
+
+class _DevView:
+    """A __cuda_array_interface__ view of device bytes owned by the library."""
+
+    def __init__(self, ptr: int, n: int):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "|u1", "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+def _take(ctx, r: LudaResult, device: bool) -> Result:
+    e = r.error
+    res = Result(r.status, Error(e.status, e.input, e.where, e.phase, e.block, e.offset),
+                 entries_in=r.entries_in, entries_out=r.entries_out, dropped_shadowed=r.dropped_shadowed,
+                 dropped_tombstones=r.dropped_tombstones, bytes_in=r.bytes_in, bytes_out=r.bytes_out,
+                 ms_total=r.ms_total)
+    if r.status == 0 and r.num_files:
+        import torch  # device memory plumbing only
+        for i in range(r.num_files):
+            f = r.files[i]
+            res.file_entries.append(f.num_entries)
+            if device:
+                if f.size:
+                    t = torch.as_tensor(_DevView(r.data + f.offset, f.size), device="cuda")
+                    res.files.append(t.clone())
+                else:
+                    res.files.append(torch.empty(0, dtype=torch.uint8, device="cuda"))
+            else:
+                res.files.append(C.string_at(r.data + f.offset, f.size))
+    lib().luda_result_free(ctx, C.byref(r))
+    return res
+
+
+def _bufs(inputs) -> tuple:
+    """Host inputs: bytes / bytearray / numpy uint8 arrays (kept alive by the caller)."""
+    arrs = []
+    bufs = (LudaBuf * max(1, len(inputs)))()
+    for i, b in enumerate(inputs):
+        a = b if isinstance(b, np.ndarray) else np.frombuffer(bytes(b), dtype=np.uint8)
+        a = np.ascontiguousarray(a, dtype=np.uint8)
+        arrs.append(a)
+        bufs[i].data = a.ctypes.data if a.size else None
+        bufs[i].size = a.size
+    return bufs, arrs
+
+
+def _torch_sync():
+    """Device inputs written on torch's streams must be complete before the
+    library's own stream reads them."""
+    import torch
+    torch.cuda.synchronize()
+
+
+def _dev_bufs(inputs) -> LudaBuf:
+    _torch_sync()
+    bufs = (LudaBuf * max(1, len(inputs)))()
+    for i, t in enumerate(inputs):
+        bufs[i].data = t.data_ptr() if t.numel() else None
+        bufs[i].size = t.numel()
+    return bufs
+
+
+class Context:
+    """A library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        rc = lib().luda_ctx_create(device, C.byref(self._h))
+        if rc != 0:
+            raise RuntimeError(f"luda_ctx_create failed: {STATUS.get(rc, rc)}")
+
+    def close(self):
+        if self._h:
+            lib().luda_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle: Optional[int]):
+        lib().luda_set_stream(self._h, C.c_void_p(stream_handle) if stream_handle else None)
+
+    def last_error(self) -> str:
+        return lib().luda_last_error(self._h).decode()
+
+    def compact(self, inputs: Sequence, opts: dict) -> Result:
+        """Host tables in, host tables out."""
+        bufs, _keep = _bufs(inputs)
+        o = options(opts)
+        r = LudaResult()
+        lib().luda_compact(self._h, bufs, len(inputs), C.byref(o), C.byref(r))
+        return _take(self._h, r, device=False)
+
+    def compact_dev(self, inputs: Sequence, opts: dict) -> Result:
+        """Device (torch uint8 cuda tensors) tables in, device tensors out."""
+        bufs = _dev_bufs(inputs)
+        o = options(opts)
+        r = LudaResult()
+        lib().luda_compact_dev(self._h, bufs, len(inputs), C.byref(o), C.byref(r))
+        return _take(self._h, r, device=True)
+
+    def compact_batch(self, jobs: Sequence, device_inputs: bool) -> List[Result]:
+        """jobs: sequence of (inputs, options dict)."""
+        J = len(jobs)
+        cjobs = (LudaJob * max(1, J))()
+        keep = []
+        for j, (inputs, opts) in enumerate(jobs):
+            if device_inputs:
+                bufs = _dev_bufs(inputs)
+            else:
+                bufs, arrs = _bufs(inputs)
+                keep.append(arrs)
+            keep.append(bufs)
+            cjobs[j].inputs = C.cast(bufs, C.POINTER(LudaBuf))
+            cjobs[j].n_inputs = len(inputs)
+            cjobs[j].options = options(opts)
+        res = (LudaResult * max(1, J))()
+        rc = lib().luda_compact_batch(self._h, cjobs, J, 1 if device_inputs else 0, res)
+        out = [_take(self._h, res[j], device=device_inputs) for j in range(J)]
+        if rc != 0 and J:
+            for o in out:
+                if o.status == 0:
+                    o.status = rc
+        return out
+
+    def build_tables_dev(self, keys, koff, tags, vals, voff, opts: dict) -> Result:
+        """Write ordered entries (device tensors) into tables on the device."""
+        o = options(opts)
+        r = LudaResult()
+        n = tags.numel()
+        _torch_sync()
+        lib().luda_build_tables_dev(self._h, n, keys.data_ptr(), koff.data_ptr(), tags.data_ptr(),
+                                    vals.data_ptr(), voff.data_ptr(), C.byref(o), C.byref(r))
+        return _take(self._h, r, device=True)
+
+    def debug_read(self, name: str, dtype, count: int, offset: int = 0) -> np.ndarray:
+        """Copy `count` elements of an internal device buffer of the last call."""
+        a = np.zeros(count, dtype=dtype)
+        rc = lib().luda_debug_read(self._h, name.encode(), a.ctypes.data, offset * a.itemsize, a.nbytes)
+        if rc != 0:
+            raise RuntimeError(f"debug_read({name}) failed: {STATUS.get(rc, rc)}")
+        return a
+
+    def stage_times(self) -> List[tuple]:
+        names = (C.c_char_p * 64)()
+        ms = (C.c_double * 64)()
+        n = lib().luda_stage_times(self._h, names, ms, 64)
+        return [(names[i].decode(), ms[i]) for i in range(min(n, 64))]
+
+
+def selftest_crc() -> int:
+    return lib().luda_selftest_crc()

@@ -1,0 +1,106 @@
+// Small bookkeeping kernels between the pipeline stages: totals, ranges,
+// maxima and type conversions the host reads back or the next stage needs.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace luda {
+
+__global__ void k_decode_total(Blocks blk, uint64_t* total) {
+  if (blockIdx.x || threadIdx.x) return;
+  *total = blk.n ? blk.e0[blk.n - 1] + blk.ne[blk.n - 1] : 0;
+}
+
+// first decoded entry of every job and every input (J + 1 and NG + 1 values);
+// a job or input without blocks starts where the next one does
+__global__ void k_ranges(Blocks blk, const uint32_t* job_b0, uint32_t J, const uint32_t* in_blk0, uint32_t NG,
+                         uint64_t N, uint64_t* job_e0, uint64_t* in_e0) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= J) job_e0[i] = job_b0[i] < blk.n ? blk.e0[job_b0[i]] : N;
+  if (i <= NG) in_e0[i] = in_blk0[i] < blk.n ? blk.e0[in_blk0[i]] : N;
+}
+
+__global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j <= J) job_s0[j] = kpos[job_e0[j]];
+}
+
+__global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats) {
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t sz = 0, cn = 0;
+  if (b < cap && b < job_ob0[J]) {
+    sz = ob.size[b];
+    cn = ob.cnt[b];
+  }
+  sz = wave_max(sz);
+  cn = wave_max(cn);
+  if (lane_id() == 0) {
+    atomicMax(&stats[0], sz);
+    atomicMax(&stats[1], cn);
+  }
+}
+
+__global__ void k_u32_to_u64(const uint32_t* a, uint64_t* b, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_file_entries(OutFiles of, OutBlocks ob, uint64_t nf) {
+  const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const uint64_t b0 = of.b0[f], last = b0 + of.nb[f] - 1;
+  of.entries[f] = ob.s0[last] + ob.cnt[last] - ob.s0[b0];
+}
+
+}  // namespace luda
+
+namespace luda {
+
+// table writer input: ordered entries given as struct-of-arrays on the device
+__global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t v = 0;
+  if (i < n) {
+    const uint64_t l = koff[i + 1] - koff[i];
+    v = l > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)l;
+  }
+  v = wave_max(v);
+  if (lane_id() == 0) atomicMax(maxlen, v);
+}
+
+__global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,
+                         const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k0 = koff[i];
+  const uint32_t ulen = (uint32_t)(koff[i + 1] - k0);
+  uint64_t* slot = tu.heap + i * kw8;
+  uint64_t kp0 = 0, kp1 = 0;
+  for (uint32_t w = 0; w < kw8; w++) {
+    uint64_t word = 0;
+    for (uint32_t b = 0; b < 8; b++) {
+      const uint32_t q = w * 8 + b;
+      if (q < ulen) {
+        const uint64_t byte = keys[k0 + q];
+        word |= byte << (8 * b);
+        if (q < 8) kp0 |= byte << (8 * (7 - q));
+        else if (q < 16) kp1 |= byte << (8 * (15 - q));
+      }
+    }
+    slot[w] = word;
+  }
+  tu.kp0[i] = kp0;
+  tu.kp1[i] = kp1;
+  tu.tag[i] = tags[i];
+  tu.ulen[i] = ulen;
+  tu.vp[i] = (uint64_t)(uintptr_t)(vals + voff[i]);
+  tu.vlen[i] = (uint32_t)(voff[i + 1] - voff[i]);
+  surv[i] = (uint32_t)i;
+}
+
+__global__ void k_check_sorted(Tuples tu, uint32_t kw8, uint64_t n, uint32_t* bad) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 || i >= n) return;
+  if (cmp_ikeys(tu, kw8, i - 1, i) >= 0) atomicOr(bad, 1u);
+}
+
+}  // namespace luda

@@ -1,0 +1,180 @@
+// Kernel interfaces shared between the kernel sources and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "luda_internal.h"
+
+namespace luda {
+
+struct MergeTask {
+  uint32_t a0, la, b0, lb;  // runs A and B as ranges of the source order array
+  uint64_t out0;            // first output position
+};
+
+constexpr uint32_t SEG_C = 2048;  // items per segmentation chunk
+
+struct SegJob {
+  uint64_t base;     // first global item of the job
+  uint32_t m;        // items of the job
+  uint32_t chunk0;   // first chunk of the job
+  uint32_t nchunks;
+  uint32_t pad;
+};
+
+struct SegChunk {
+  uint32_t job;
+  uint32_t start, end;  // job-local item range
+  uint32_t pad;
+};
+
+struct OutBlocks {
+  uint64_t* s0;      // first survivor (global)
+  uint32_t* cnt;     // entries
+  uint32_t* size;    // contents bytes (trailer excluded)
+  uint64_t* full;    // contents + 5
+  uint32_t* job;
+  uint32_t* file;
+  uint64_t* off;     // offset inside its file
+  uint32_t* ie_size; // bytes of its index block entry
+};
+
+struct OutFiles {
+  uint32_t* job;
+  uint64_t* b0;        // first output block
+  uint32_t* nb;        // blocks
+  uint64_t* data;      // data bytes (blocks + trailers)
+  uint64_t* nwin;      // filter windows
+  uint64_t* w0;        // first global filter window
+  uint64_t* filter_off, *filter_size, *meta_off, *meta_size, *index_off, *index_size;
+  uint64_t* size;      // whole file
+  uint64_t* out;       // offset in the output buffer
+  uint64_t* entries;
+};
+
+// decode
+__global__ void k_footer(Inputs in, unsigned long long* err);
+__global__ void k_index_scan(Inputs in, const uint32_t* g_t4, const uint32_t* g_sh, unsigned long long* err);
+__global__ void k_index_emit(Inputs in, const uint32_t* in_blk0, Blocks blk);
+struct DecodeArgs {
+  Inputs in;
+  Blocks blk;
+  Tuples tu;
+  const uint32_t* g_crc;     // CrcLds image
+  unsigned long long* err;   // per job
+  uint32_t* ticket;
+  uint32_t* maxklen;
+  uint32_t* dev_flags;
+  uint32_t stage_bytes;      // per wave, multiple of 16
+  uint64_t cap;              // entry record capacity
+};
+__global__ void k_decode(DecodeArgs A);
+__global__ void k_keys(Tuples tu, Blocks blk, Inputs in, uint32_t kw8, uint64_t n, unsigned long long* err);
+__global__ void k_order(Tuples tu, Blocks blk, Inputs in, const uint32_t* in_blk0, uint32_t kw8, uint64_t n,
+                        int32_t* in_cmp, unsigned long long* err);
+
+// merge
+__global__ void k_iota(uint32_t* idx, uint64_t n);
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n);
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, uint64_t n);
+__global__ void k_merge(const MergeTask* tasks, uint32_t ntasks, const uint32_t* src, uint32_t* dst, Tuples tu,
+                        uint32_t kw8, uint64_t total);
+__global__ void k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, const JobDesc* jobs,
+                              const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
+                              unsigned long long* shadowed, unsigned long long* tomb, const uint32_t* active);
+__global__ void k_scatter(const uint32_t* ord, const uint32_t* keep, const uint32_t* pos, uint64_t n,
+                          uint32_t* surv);
+template <typename T>
+void launch_scan(const T* in, uint64_t n, T* out, T* scratch, hipStream_t st);
+constexpr uint32_t MERGE_ITEMS_PER_THREAD = 8;
+
+// plan
+__global__ void k_prep(const uint32_t* surv, Tuples tu, uint32_t kw8, const uint64_t* job_s0, uint32_t J,
+                       uint64_t S, uint32_t* sz_r, uint32_t* sz_n, uint32_t* shr);
+struct BlockNext;
+struct FileNext;
+void launch_seg_exit_blocks(const SegChunk* ch, const uint32_t* nch_dev, uint32_t grid, const SegJob* sj,
+                            const JobDesc* jobs, const uint32_t* sz_r, const uint32_t* sz_n, uint32_t* nxt,
+                            uint32_t* ex, uint32_t* cnt, uint32_t* job_bmax, hipStream_t st);
+void launch_seg_exit_files(const SegChunk* ch, const uint32_t* nch_dev, uint32_t grid, const SegJob* sj,
+                           const JobDesc* jobs, const uint64_t* ob_excl, const uint64_t* ob_full, uint32_t* nxt,
+                           uint32_t* ex, uint32_t* cnt, uint32_t* job_bmax, hipStream_t st);
+__global__ void k_seg_compose(const SegJob* sj, uint32_t J, const uint32_t* ex, const uint32_t* cnt,
+                              const uint32_t* job_bmax, uint32_t* chunk_entry, uint32_t* chunk_seg0,
+                              uint32_t* job_nseg, uint32_t cap);
+void launch_seg_mark(const SegChunk* ch, const uint32_t* nch_dev, uint32_t grid, const SegJob* sj,
+                     const uint32_t* nxt, const uint32_t* chunk_entry, const uint32_t* chunk_seg0,
+                     const uint64_t* job_seg_base, uint32_t* seg_first, hipStream_t st);
+__global__ void k_make_segjobs(const uint64_t* base_excl, const uint32_t* counts, uint32_t J, SegJob* sj,
+                               SegChunk* ch, uint32_t* nch_out);
+__global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out);
+__global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s, const JobDesc* jobs,
+                             const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n, uint64_t cap,
+                             OutBlocks ob);
+__global__ void k_file_pre(const uint64_t* job_f0, uint32_t J, const uint64_t* job_ob0, const uint32_t* file_first,
+                           const uint64_t* ob_excl, uint64_t cap, OutFiles of);
+__global__ void k_block_post(const uint64_t* nfiles_total, OutFiles of, const uint64_t* ob_excl,
+                             const uint64_t* job_ob0, uint32_t J, Tuples tu, const uint32_t* surv, uint64_t cap,
+                             OutBlocks ob, uint32_t* win_keys, uint32_t* win_fb);
+__global__ void k_win_size(const uint64_t* nwin_total, const uint64_t* file_w0_sorted, uint64_t nfiles,
+                           OutFiles of, const JobDesc* jobs, const uint32_t* win_keys, uint64_t cap,
+                           uint64_t* win_bytes, uint32_t* win_file, uint32_t* max_bytes);
+__global__ void k_file_layout(const uint64_t* nfiles_total, OutFiles of, const uint64_t* win_off,
+                              const uint64_t* ie_off, uint64_t cap);
+
+// encode
+struct EncodeArgs {
+  const JobDesc* jobs;
+  OutBlocks ob;
+  OutFiles of;
+  Tuples tu;
+  const uint32_t* surv;
+  const uint32_t* sz_r;
+  const uint32_t* sz_n;
+  const uint32_t* shr;
+  const uint64_t* nblocks;  // device total of output blocks
+  uint8_t* out;
+  const uint32_t* g_crc;
+  uint32_t kw8;
+  uint32_t stage_bytes;     // per wave
+  uint32_t ent_cap;         // entry-start slots per wave
+};
+__global__ void k_encode(EncodeArgs A);
+struct FilterArgs {
+  const JobDesc* jobs;
+  OutBlocks ob;
+  OutFiles of;
+  Tuples tu;
+  const uint32_t* surv;
+  const uint64_t* nwin;       // device total of windows
+  const uint32_t* win_keys;
+  const uint32_t* win_fb;
+  const uint32_t* win_file;
+  const uint64_t* win_bytes;
+  const uint64_t* win_off;    // exclusive scan of win_bytes
+  uint8_t* out;
+  uint32_t kw8;
+  uint32_t lds_bytes;         // per wave
+};
+__global__ void k_filter(FilterArgs A);
+__global__ void k_index_write(OutBlocks ob, OutFiles of, Tuples tu, const uint32_t* surv, const uint64_t* ie_off,
+                              const uint64_t* nblocks, uint32_t kw8, uint64_t cap, uint8_t* out);
+__global__ void k_meta(OutFiles of, const uint64_t* win_off, const uint64_t* nfiles, uint64_t cap, uint8_t* out);
+__global__ void k_filter_offsets(OutFiles of, const uint64_t* nwin, const uint32_t* win_file,
+                                 const uint64_t* win_off, uint64_t cap, uint8_t* out);
+// misc
+__global__ void k_decode_total(Blocks blk, uint64_t* total);
+__global__ void k_ranges(Blocks blk, const uint32_t* job_b0, uint32_t J, const uint32_t* in_blk0, uint32_t NG,
+                         uint64_t N, uint64_t* job_e0, uint64_t* in_e0);
+__global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0);
+__global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats);
+__global__ void k_u32_to_u64(const uint32_t* a, uint64_t* b, uint64_t n);
+__global__ void k_file_entries(OutFiles of, OutBlocks ob, uint64_t nf);
+__global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen);
+__global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,
+                         const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv);
+__global__ void k_check_sorted(Tuples tu, uint32_t kw8, uint64_t n, uint32_t* bad);
+__global__ void k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_t4,
+                             const uint32_t* g_sh);
+
+}  // namespace luda

@@ -1,0 +1,1239 @@
+// Host runtime of the GPU compaction path: the C-ABI of include/luda.h.
+//
+// One call runs the paper's per-job workflow (Sec. III-A overview: copy the
+// selected tables to the GPU, unpack, sort and drop, pack, return the new
+// tables), for one job or a batch of independent jobs at once.  Every stage
+// is a device kernel; the host only sizes buffers between stages from a few
+// counters it reads back, builds small work lists, and moves bytes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/luda.h"
+#include "kernels.h"
+
+using namespace luda;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// CRC32C tables built on the host: slicing-by-4 and "shift by 68 * 2^k bytes"
+// (k = 0..12), each a set of four 256-entry tables indexed by the bytes of
+// the 32-bit register.
+
+constexpr uint32_t POLY = 0x82F63B78u;  // CRC32C, reflected
+constexpr int NSH = 13;
+
+uint32_t step_byte(uint32_t r, uint8_t b, const uint32_t* t0) { return t0[(r ^ b) & 0xFF] ^ (r >> 8); }
+
+struct CrcTables {
+  uint32_t t4[4][256];
+  uint32_t sh[NSH][4][256];
+};
+
+uint32_t apply_shift(const uint32_t sh[4][256], uint32_t c) {
+  return sh[0][c & 0xFF] ^ sh[1][(c >> 8) & 0xFF] ^ sh[2][(c >> 16) & 0xFF] ^ sh[3][c >> 24];
+}
+
+void build_crc_tables(CrcTables* T) {
+  uint32_t t0[256];
+  for (uint32_t b = 0; b < 256; b++) {
+    uint32_t r = b;
+    for (int k = 0; k < 8; k++) r = (r >> 1) ^ (POLY & (0u - (r & 1u)));
+    t0[b] = r;
+  }
+  for (int b = 0; b < 256; b++) T->t4[0][b] = t0[b];
+  for (int k = 1; k < 4; k++)
+    for (int b = 0; b < 256; b++) T->t4[k][b] = (T->t4[k - 1][b] >> 8) ^ t0[T->t4[k - 1][b] & 0xFF];
+  // shift by 68 zero bytes, directly
+  for (int i = 0; i < 4; i++)
+    for (uint32_t v = 0; v < 256; v++) {
+      uint32_t r = v << (8 * i);
+      for (int z = 0; z < 68; z++) r = step_byte(r, 0, t0);
+      T->sh[0][i][v] = r;
+    }
+  // shift by 2m = shift by m, twice
+  for (int k = 1; k < NSH; k++)
+    for (int i = 0; i < 4; i++)
+      for (uint32_t v = 0; v < 256; v++)
+        T->sh[k][i][v] = apply_shift(T->sh[k - 1], apply_shift(T->sh[k - 1], v << (8 * i)));
+}
+
+// ---------------------------------------------------------------------------
+
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct StageMark {
+  const char* name;
+  hipEvent_t ev;
+};
+
+struct luda_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  uint32_t* d_crc = nullptr;  // CrcTables image
+  int n_cu = 256;
+  size_t lds_limit = 64 * 1024;  // dynamic + static LDS per workgroup
+  std::string last_error;
+  std::map<std::string, DBuf> bufs;
+  // stage timing
+  std::vector<std::pair<std::string, hipEvent_t>> marks;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_used = 0;
+  std::vector<std::pair<std::string, double>> stage_ms;
+  bool timing = false;
+};
+
+namespace {
+
+struct Fail {
+  int status;
+  std::string msg;
+};
+
+#define HIPCK(x)                                                                         \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw Fail{LUDA_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};           \
+  } while (0)
+
+#define LAUNCH_CHECK() HIPCK(hipGetLastError())
+
+template <typename T>
+T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  bytes = (bytes + 255) & ~size_t(255);
+  DBuf& b = c->bufs[name];
+  if (b.cap < bytes) {
+    if (b.p) HIPCK(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    size_t want = bytes + bytes / 8;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{LUDA_NOMEM, "device allocation of " + std::to_string(want) + " bytes for " + name + " failed"};
+    }
+    b.cap = want;
+  }
+  return (T*)b.p;
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t t = 256) { return (uint32_t)std::max<uint64_t>(1, (n + t - 1) / t); }
+
+void fill_u32(luda_ctx* c, uint32_t* p, uint32_t v, uint64_t n) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, c->stream, p, v, n);
+  LAUNCH_CHECK();
+}
+void fill_u64(luda_ctx* c, void* p, uint64_t v, uint64_t n) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n)), dim3(256), 0, c->stream, (unsigned long long*)p,
+                     (unsigned long long)v, n);
+  LAUNCH_CHECK();
+}
+
+template <typename T>
+void d2h(luda_ctx* c, T* host, const T* dev, size_t count) {
+  if (!count) return;
+  HIPCK(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+}
+template <typename T>
+void h2d(luda_ctx* c, T* dev, const T* host, size_t count) {
+  if (!count) return;
+  HIPCK(hipMemcpyAsync(dev, host, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
+}
+void sync(luda_ctx* c) { HIPCK(hipStreamSynchronize(c->stream)); }
+
+void mark(luda_ctx* c, const char* name) {
+  if (!c->timing) return;
+  if (c->event_used == c->event_pool.size()) {
+    hipEvent_t e;
+    HIPCK(hipEventCreate(&e));
+    c->event_pool.push_back(e);
+  }
+  hipEvent_t e = c->event_pool[c->event_used++];
+  HIPCK(hipEventRecord(e, c->stream));
+  c->marks.emplace_back(name, e);
+}
+
+int status_of(uint32_t code) {
+  switch (code) {
+    case EC_FORMAT: return LUDA_CORRUPT_FORMAT;
+    case EC_CHECKSUM: return LUDA_CORRUPT_CHECKSUM;
+    case EC_UNSUPPORTED: return LUDA_UNSUPPORTED;
+    case EC_UNSORTED: return LUDA_UNSORTED_INPUT;
+    case EC_LIMIT: return LUDA_UNSUPPORTED;
+    default: return LUDA_DEVICE;
+  }
+}
+
+luda_error decode_err(uint64_t key, const std::vector<uint64_t>& in_size, uint32_t in_first) {
+  luda_error e;
+  memset(&e, 0, sizeof e);
+  e.status = status_of((uint32_t)(key & 7));
+  e.input = (uint32_t)(key >> 52);
+  e.where = (uint32_t)((key >> 50) & 3);
+  e.block = (key >> 28) & 0x3FFFFF;
+  e.phase = (uint32_t)((key >> 26) & 3);
+  e.offset = (key >> 3) & 0x7FFFFF;
+  if (e.where == W_FOOTER) {
+    const uint64_t size = in_size[in_first + e.input];
+    e.offset = (e.phase == FP_SHORT) ? 0 : size - 48 + e.offset;
+    e.phase = 0;
+    e.block = 0;
+  }
+  return e;
+}
+
+struct JobIn {
+  std::vector<luda_buf> inputs;
+  luda_options opt;
+};
+
+struct BatchOut {
+  std::vector<luda_result>* results;
+  bool device_out;
+};
+
+// Per-job bookkeeping kept on the host between stages.
+struct HostJob {
+  uint32_t in_first = 0, n_in = 0;
+  uint64_t bytes_in = 0;
+  bool failed = false;
+  uint64_t err_key = ERR_NONE;
+  int status_limit = 0;
+};
+
+int check_opt(const luda_options* o) {
+  if (!o || o->block_size == 0 || o->restart_interval == 0 || o->bloom_bits_per_key == 0 ||
+      o->target_file_size == 0)
+    return LUDA_INVALID_ARG;
+  return LUDA_OK;
+}
+
+// Device output buffers are shared by the results of one call and freed
+// when the last of them is released.
+struct DevBlock {
+  void* p = nullptr;
+  int refs = 0;
+};
+
+struct ResultInternal {
+  DevBlock* dev = nullptr;
+  bool host_data = false;
+};
+
+void release_dev(ResultInternal* ri) {
+  if (ri && ri->dev && --ri->dev->refs == 0) {
+    (void)hipFree(ri->dev->p);
+    delete ri->dev;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The pipeline after survivors are known: block and file cuts, layout, and
+// the writers.  Shared by compaction and the table writer.
+
+struct PlanIn {
+  uint32_t J;
+  JobDesc* d_jobs;
+  const std::vector<JobDesc>* jobs;
+  Tuples tu;
+  uint32_t kw8;
+  const uint32_t* d_surv;
+  std::vector<uint64_t> job_s0;  // J + 1, host copy
+  const uint64_t* d_job_s0;
+};
+
+struct PlanOut {
+  uint64_t total_bytes = 0;
+  uint8_t* d_out = nullptr;
+  std::vector<uint64_t> file_out;  // nfiles + 1
+  std::vector<uint64_t> file_entries;
+  std::vector<uint64_t> job_f0;    // J + 1
+};
+
+void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
+  const uint32_t J = P.J;
+  const uint64_t S = P.job_s0[J];
+  hipStream_t st = c->stream;
+  O.job_f0.assign(J + 1, 0);
+  O.file_out.assign(1, 0);
+  if (S == 0) return;
+
+  uint32_t* sz_r = dbuf<uint32_t>(c, "sz_r", S);
+  uint32_t* sz_n = dbuf<uint32_t>(c, "sz_n", S);
+  uint32_t* shr = dbuf<uint32_t>(c, "shr", S);
+  hipLaunchKernelGGL(k_prep, dim3(blocks_for(S)), dim3(256), 0, st, P.d_surv, P.tu, P.kw8, P.d_job_s0, J, S, sz_r,
+                     sz_n, shr);
+  LAUNCH_CHECK();
+  mark(c, "prep");
+
+  // --- block cuts over survivors: host-built chunk list
+  std::vector<SegJob> sj(J);
+  std::vector<SegChunk> ch;
+  for (uint32_t j = 0; j < J; j++) {
+    const uint64_t m = P.job_s0[j + 1] - P.job_s0[j];
+    if (m > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "more than 2^32 surviving entries in one job"};
+    sj[j].base = P.job_s0[j];
+    sj[j].m = (uint32_t)m;
+    sj[j].chunk0 = (uint32_t)ch.size();
+    const uint32_t n = (uint32_t)((m + SEG_C - 1) / SEG_C);
+    sj[j].nchunks = n;
+    sj[j].pad = 0;
+    for (uint32_t q = 0; q < n; q++) ch.push_back(SegChunk{j, q * SEG_C, (uint32_t)std::min<uint64_t>(m, (uint64_t)(q + 1) * SEG_C), 0});
+  }
+  const uint32_t nch = (uint32_t)ch.size();
+  SegJob* d_sj = dbuf<SegJob>(c, "sj_b", J);
+  SegChunk* d_ch = dbuf<SegChunk>(c, "ch_b", nch);
+  uint32_t* d_nch = dbuf<uint32_t>(c, "nch_b", 1);
+  h2d(c, d_sj, sj.data(), J);
+  h2d(c, d_ch, ch.data(), nch);
+  h2d(c, d_nch, &nch, 1);
+  uint32_t* nxt = dbuf<uint32_t>(c, "seg_nxt", S);
+  uint32_t* ex = dbuf<uint32_t>(c, "seg_ex", S);
+  uint32_t* cnt = dbuf<uint32_t>(c, "seg_cnt", S);
+  uint32_t* bmax = dbuf<uint32_t>(c, "seg_bmax", J);
+  uint32_t* centry = dbuf<uint32_t>(c, "seg_centry", nch);
+  uint32_t* cseg0 = dbuf<uint32_t>(c, "seg_cseg0", nch);
+  uint32_t* nseg = dbuf<uint32_t>(c, "seg_nseg", J);
+  uint64_t* job_ob0 = dbuf<uint64_t>(c, "job_ob0", J + 1);
+  fill_u32(c, bmax, 0, J);
+  launch_seg_exit_blocks(d_ch, d_nch, nch, d_sj, P.d_jobs, sz_r, sz_n, nxt, ex, cnt, bmax, st);
+  LAUNCH_CHECK();
+  const uint32_t cap = (uint32_t)std::min<size_t>(24576, (c->lds_limit - 2048) / 4);
+  hipLaunchKernelGGL(k_seg_compose, dim3(J), dim3(256), 2 * cap * sizeof(uint16_t), st, d_sj, J, ex, cnt, bmax,
+                     centry, cseg0, nseg, cap);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(64), 0, st, nseg, J, job_ob0);
+  LAUNCH_CHECK();
+  uint32_t* seg_first = dbuf<uint32_t>(c, "seg_first_b", S);
+  launch_seg_mark(d_ch, d_nch, nch, d_sj, nxt, centry, cseg0, job_ob0, seg_first, st);
+  LAUNCH_CHECK();
+  mark(c, "block_cuts");
+
+  // --- output blocks (capacity: one per survivor)
+  const uint64_t OB = S;
+  OutBlocks ob;
+  ob.s0 = dbuf<uint64_t>(c, "ob_s0", OB);
+  ob.cnt = dbuf<uint32_t>(c, "ob_cnt", OB);
+  ob.size = dbuf<uint32_t>(c, "ob_size", OB);
+  ob.full = dbuf<uint64_t>(c, "ob_full", OB);
+  ob.job = dbuf<uint32_t>(c, "ob_job", OB);
+  ob.file = dbuf<uint32_t>(c, "ob_file", OB);
+  ob.off = dbuf<uint64_t>(c, "ob_off", OB);
+  ob.ie_size = dbuf<uint32_t>(c, "ob_ie", OB);
+  hipLaunchKernelGGL(k_block_meta, dim3(blocks_for(OB)), dim3(256), 0, st, job_ob0, J, d_sj, P.d_jobs, seg_first,
+                     sz_r, sz_n, OB, ob);
+  LAUNCH_CHECK();
+  uint64_t* ob_excl = dbuf<uint64_t>(c, "ob_excl", OB + 1);
+  uint64_t* scan_tmp = dbuf<uint64_t>(c, "scan_tmp64", OB / 2048 + 8);
+  launch_scan<uint64_t>(ob.full, OB, ob_excl, scan_tmp, st);
+  LAUNCH_CHECK();
+
+  // --- file cuts over output blocks: chunk list built on the device
+  const uint32_t fch_cap = (uint32_t)(OB / SEG_C + J + 1);
+  SegJob* d_sjf = dbuf<SegJob>(c, "sj_f", J);
+  SegChunk* d_chf = dbuf<SegChunk>(c, "ch_f", fch_cap);
+  uint32_t* d_nchf = dbuf<uint32_t>(c, "nch_f", 1);
+  hipLaunchKernelGGL(k_make_segjobs, dim3(1), dim3(64), 0, st, job_ob0, nseg, J, d_sjf, d_chf, d_nchf);
+  LAUNCH_CHECK();
+  uint32_t* fnxt = dbuf<uint32_t>(c, "fseg_nxt", OB);
+  uint32_t* fex = dbuf<uint32_t>(c, "fseg_ex", OB);
+  uint32_t* fcnt = dbuf<uint32_t>(c, "fseg_cnt", OB);
+  uint32_t* fbmax = dbuf<uint32_t>(c, "fseg_bmax", J);
+  uint32_t* fcentry = dbuf<uint32_t>(c, "fseg_centry", fch_cap);
+  uint32_t* fcseg0 = dbuf<uint32_t>(c, "fseg_cseg0", fch_cap);
+  uint32_t* fnseg = dbuf<uint32_t>(c, "fseg_nseg", J);
+  uint64_t* job_f0 = dbuf<uint64_t>(c, "job_f0", J + 1);
+  fill_u32(c, fbmax, 0, J);
+  launch_seg_exit_files(d_chf, d_nchf, fch_cap, d_sjf, P.d_jobs, ob_excl, ob.full, fnxt, fex, fcnt, fbmax, st);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_seg_compose, dim3(J), dim3(256), 2 * cap * sizeof(uint16_t), st, d_sjf, J, fex, fcnt, fbmax,
+                     fcentry, fcseg0, fnseg, cap);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(64), 0, st, fnseg, J, job_f0);
+  LAUNCH_CHECK();
+  uint32_t* file_first = dbuf<uint32_t>(c, "file_first", OB);
+  launch_seg_mark(d_chf, d_nchf, fch_cap, d_sjf, fnxt, fcentry, fcseg0, job_f0, file_first, st);
+  LAUNCH_CHECK();
+  mark(c, "file_cuts");
+
+  // --- per-file pre-layout (capacity: one file per block)
+  const uint64_t FC = OB;
+  OutFiles of;
+  of.job = dbuf<uint32_t>(c, "of_job", FC);
+  of.b0 = dbuf<uint64_t>(c, "of_b0", FC);
+  of.nb = dbuf<uint32_t>(c, "of_nb", FC);
+  of.data = dbuf<uint64_t>(c, "of_data", FC);
+  of.nwin = dbuf<uint64_t>(c, "of_nwin", FC);
+  of.w0 = dbuf<uint64_t>(c, "of_w0", FC + 1);
+  of.filter_off = dbuf<uint64_t>(c, "of_foff", FC);
+  of.filter_size = dbuf<uint64_t>(c, "of_fsize", FC);
+  of.meta_off = dbuf<uint64_t>(c, "of_moff", FC);
+  of.meta_size = dbuf<uint64_t>(c, "of_msize", FC);
+  of.index_off = dbuf<uint64_t>(c, "of_ioff", FC);
+  of.index_size = dbuf<uint64_t>(c, "of_isize", FC);
+  of.size = dbuf<uint64_t>(c, "of_size", FC);
+  of.out = dbuf<uint64_t>(c, "of_out", FC + 1);
+  of.entries = dbuf<uint64_t>(c, "of_entries", FC);
+  hipLaunchKernelGGL(k_file_pre, dim3(blocks_for(FC)), dim3(256), 0, st, job_f0, J, job_ob0, file_first, ob_excl,
+                     FC, of);
+  LAUNCH_CHECK();
+  launch_scan<uint64_t>(of.nwin, FC, of.w0, scan_tmp, st);
+  LAUNCH_CHECK();
+  // sizes needed to allocate window arrays and the encoder's LDS
+  uint32_t* stats = dbuf<uint32_t>(c, "plan_stats", 4);
+  fill_u32(c, stats, 0, 4);
+  hipLaunchKernelGGL(k_plan_stats, dim3(blocks_for(OB)), dim3(256), 0, st, ob, job_ob0, J, OB, stats);
+  LAUNCH_CHECK();
+  uint64_t hv[4];
+  uint32_t hs[4];
+  d2h(c, &hv[0], job_ob0 + J, 1);
+  d2h(c, &hv[1], job_f0 + J, 1);
+  d2h(c, &hv[2], of.w0 + FC, 1);
+  d2h(c, hs, stats, 4);
+  sync(c);
+  const uint64_t NBLK = hv[0], NF = hv[1], NW = hv[2];
+  const uint32_t max_bsize = hs[0], max_bcnt = hs[1];
+
+  uint32_t* win_keys = dbuf<uint32_t>(c, "win_keys", NW);
+  uint32_t* win_fb = dbuf<uint32_t>(c, "win_fb", NW);
+  uint32_t* win_file = dbuf<uint32_t>(c, "win_file", NW);
+  uint64_t* win_bytes = dbuf<uint64_t>(c, "win_bytes", NW);
+  uint64_t* win_off = dbuf<uint64_t>(c, "win_off", NW + 1);
+  fill_u32(c, win_keys, 0, NW);
+  fill_u32(c, win_fb, 0xFFFFFFFFu, NW);
+  hipLaunchKernelGGL(k_block_post, dim3(blocks_for(NBLK)), dim3(256), 0, st, job_f0 + J, of, ob_excl, job_ob0, J,
+                     P.tu, P.d_surv, NBLK, ob, win_keys, win_fb);
+  LAUNCH_CHECK();
+  uint32_t* wstat = dbuf<uint32_t>(c, "win_stat", 1);
+  fill_u32(c, wstat, 0, 1);
+  hipLaunchKernelGGL(k_win_size, dim3(blocks_for(NW)), dim3(256), 0, st, of.w0 + FC, of.w0, NF, of, P.d_jobs,
+                     win_keys, NW, win_bytes, win_file, wstat);
+  LAUNCH_CHECK();
+  uint64_t* scan_tmpw = dbuf<uint64_t>(c, "scan_tmpw", NW / 2048 + 8);
+  launch_scan<uint64_t>(win_bytes, NW, win_off, scan_tmpw, st);
+  LAUNCH_CHECK();
+  uint64_t* ie64 = dbuf<uint64_t>(c, "ie64", NBLK);
+  uint64_t* ie_off = dbuf<uint64_t>(c, "ie_off", NBLK + 1);
+  hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob.ie_size, ie64, NBLK);
+  LAUNCH_CHECK();
+  launch_scan<uint64_t>(ie64, NBLK, ie_off, scan_tmp, st);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_file_layout, dim3(blocks_for(NF)), dim3(256), 0, st, job_f0 + J, of, win_off, ie_off, NF);
+  LAUNCH_CHECK();
+  launch_scan<uint64_t>(of.size, NF, of.out, scan_tmp, st);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, NF);
+  LAUNCH_CHECK();
+  O.file_out.assign(NF + 1, 0);
+  O.file_entries.assign(NF, 0);
+  uint32_t max_win = 0;
+  d2h(c, O.file_out.data(), of.out, NF + 1);
+  d2h(c, O.file_entries.data(), of.entries, NF);
+  d2h(c, O.job_f0.data(), job_f0, J + 1);
+  d2h(c, &max_win, wstat, 1);
+  sync(c);
+  mark(c, "layout");
+  O.total_bytes = O.file_out[NF];
+  uint8_t* out = (uint8_t*)dbuf<uint8_t>(c, "out_tables", O.total_bytes + 64);
+  O.d_out = out;
+
+  // --- writers
+  {
+    EncodeArgs A;
+    A.jobs = P.d_jobs;
+    A.ob = ob;
+    A.of = of;
+    A.tu = P.tu;
+    A.surv = P.d_surv;
+    A.sz_r = sz_r;
+    A.sz_n = sz_n;
+    A.shr = shr;
+    A.nblocks = job_ob0 + J;
+    A.out = out;
+    A.g_crc = c->d_crc;
+    A.kw8 = P.kw8;
+    A.stage_bytes = (uint32_t)(((uint64_t)max_bsize + 1 + 4 + 15 + 15) & ~15ull);
+    A.ent_cap = max_bcnt + 1;
+    const size_t per_wave = A.stage_bytes + 4ull * A.ent_cap;
+    const size_t tables = sizeof(uint32_t) * (4 + 7 * 4) * 256;
+    const size_t budget = c->lds_limit - 2048;
+    int waves = 4;
+    while (waves > 1 && tables + per_wave * waves > budget) waves--;
+    if (tables + per_wave * waves > budget)
+      throw Fail{LUDA_UNSUPPORTED, "output block of " + std::to_string(max_bsize) + " bytes exceeds the encoder's LDS"};
+    const size_t lds = tables + per_wave * waves;
+    int occ = 0;
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, lds));
+    occ = std::max(occ, 1);
+    const uint64_t want = (NBLK + waves - 1) / waves;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
+    hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
+    LAUNCH_CHECK();
+  }
+  mark(c, "encode");
+  if (NW) {
+    FilterArgs F;
+    F.jobs = P.d_jobs;
+    F.ob = ob;
+    F.of = of;
+    F.tu = P.tu;
+    F.surv = P.d_surv;
+    F.nwin = of.w0 + FC;
+    F.win_keys = win_keys;
+    F.win_fb = win_fb;
+    F.win_file = win_file;
+    F.win_bytes = win_bytes;
+    F.win_off = win_off;
+    F.out = out;
+    F.kw8 = P.kw8;
+    F.lds_bytes = (uint32_t)(((uint64_t)max_win + 16 + 15) & ~15ull);
+    const size_t budget = c->lds_limit - 2048;
+    int waves = 4;
+    while (waves > 1 && (size_t)F.lds_bytes * waves > budget) waves--;
+    if ((size_t)F.lds_bytes * waves > budget)
+      throw Fail{LUDA_UNSUPPORTED, "filter of " + std::to_string(max_win) + " bytes exceeds the filter kernel's LDS"};
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NW + waves - 1) / waves, (uint64_t)c->n_cu * 8));
+    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_filter_offsets, dim3(blocks_for(NW)), dim3(256), 0, st, of, of.w0 + FC, win_file, win_off,
+                       NW, out);
+    LAUNCH_CHECK();
+  }
+  mark(c, "filter");
+  hipLaunchKernelGGL(k_index_write, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.tu, P.d_surv, ie_off,
+                     job_ob0 + J, P.kw8, NBLK, out);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_meta, dim3(blocks_for(NF)), dim3(256), 0, st, of, win_off, job_f0 + J, NF, out);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_crc_ranges, dim3((uint32_t)(3 * NF)), dim3(256), 0, st, of, job_f0 + J, NF, out, c->d_crc,
+                     c->d_crc + 4 * 256);
+  LAUNCH_CHECK();
+  mark(c, "meta");
+}
+
+// ---------------------------------------------------------------------------
+// The compaction pipeline over a batch.
+
+struct BatchState {
+  std::vector<HostJob> hj;
+  std::vector<JobDesc> jd;
+  std::vector<uint64_t> in_ptr, in_size;
+  std::vector<uint32_t> in_job, in_local;
+};
+
+void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, luda_result* results) {
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  hipStream_t st = c->stream;
+  c->marks.clear();
+  c->event_used = 0;
+  mark(c, "start");
+  BatchState B;
+  B.hj.resize(J);
+  B.jd.resize(J);
+  uint64_t G = 0, total_in = 0;
+  for (uint32_t j = 0; j < J; j++) {
+    B.hj[j].in_first = (uint32_t)G;
+    B.hj[j].n_in = jobs[j].n_inputs;
+    const luda_options& o = jobs[j].options;
+    B.jd[j] = JobDesc{o.block_size, o.restart_interval, o.bloom_bits_per_key, o.bottommost ? 1u : 0u,
+                      o.target_file_size, (uint32_t)G, jobs[j].n_inputs};
+    for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
+      B.in_size.push_back(jobs[j].inputs[i].size);
+      B.in_job.push_back(j);
+      B.in_local.push_back(i);
+      B.hj[j].bytes_in += jobs[j].inputs[i].size;
+      total_in += (jobs[j].inputs[i].size + 255) & ~255ull;
+    }
+    G += jobs[j].n_inputs;
+  }
+  if (G > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "too many inputs"};
+  // inputs on the device
+  if (dev_inputs) {
+    for (uint32_t j = 0; j < J; j++)
+      for (uint32_t i = 0; i < jobs[j].n_inputs; i++) B.in_ptr.push_back((uint64_t)(uintptr_t)jobs[j].inputs[i].data);
+  } else {
+    uint8_t* arena = dbuf<uint8_t>(c, "in_arena", total_in + 256);
+    uint64_t off = 0;
+    for (uint32_t j = 0; j < J; j++)
+      for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
+        const luda_buf& b = jobs[j].inputs[i];
+        if (b.size) HIPCK(hipMemcpyAsync(arena + off, b.data, b.size, hipMemcpyHostToDevice, st));
+        B.in_ptr.push_back((uint64_t)(uintptr_t)(arena + off));
+        off += (b.size + 255) & ~255ull;
+      }
+  }
+  mark(c, "h2d");
+  const uint32_t NG = (uint32_t)G;
+  JobDesc* d_jobs = dbuf<JobDesc>(c, "jobs", J);
+  h2d(c, d_jobs, B.jd.data(), J);
+  Inputs in;
+  in.n = NG;
+  uint64_t* d_in_ptr = dbuf<uint64_t>(c, "in_ptr", NG);
+  uint64_t* d_in_size = dbuf<uint64_t>(c, "in_size", NG);
+  uint32_t* d_in_job = dbuf<uint32_t>(c, "in_job", NG);
+  uint32_t* d_in_local = dbuf<uint32_t>(c, "in_local", NG);
+  h2d(c, d_in_ptr, B.in_ptr.data(), NG);
+  h2d(c, d_in_size, B.in_size.data(), NG);
+  h2d(c, d_in_job, B.in_job.data(), NG);
+  h2d(c, d_in_local, B.in_local.data(), NG);
+  in.ptr = d_in_ptr;
+  in.size = d_in_size;
+  in.job = d_in_job;
+  in.local = d_in_local;
+  in.idx_off = dbuf<uint64_t>(c, "in_idx_off", NG);
+  in.idx_size = dbuf<uint64_t>(c, "in_idx_size", NG);
+  in.nblk = dbuf<uint32_t>(c, "in_nblk", NG);
+  in.maxblk = dbuf<uint32_t>(c, "in_maxblk", NG);
+  unsigned long long* err = dbuf<unsigned long long>(c, "err", J);
+  fill_u64(c, err, ERR_NONE, J);
+  uint32_t* dev_flags = dbuf<uint32_t>(c, "dev_flags", 4);
+  fill_u32(c, dev_flags, 0, 4);
+
+  std::vector<uint32_t> nblk(NG), maxblk(NG);
+  std::vector<uint64_t> errs(J, ERR_NONE);
+  if (NG) {
+    hipLaunchKernelGGL(k_footer, dim3(blocks_for(NG)), dim3(256), 0, st, in, err);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_index_scan, dim3(NG), dim3(256), 0, st, in, c->d_crc, c->d_crc + 4 * 256, err);
+    LAUNCH_CHECK();
+    d2h(c, nblk.data(), in.nblk, NG);
+    d2h(c, maxblk.data(), in.maxblk, NG);
+  }
+  mark(c, "index");
+  sync(c);
+  // flat block table
+  std::vector<uint32_t> in_blk0(NG + 1, 0);
+  uint64_t NB = 0;
+  uint32_t max_block = 0;
+  const size_t crc_lds_b = sizeof(uint32_t) * (4 + 7 * 4) * 256;
+  const uint32_t kMaxStage = (uint32_t)(c->lds_limit - 2048 - crc_lds_b);
+  for (uint32_t g = 0; g < NG; g++) {
+    if (maxblk[g] + 1 + 4 + 32 > kMaxStage) {
+      // blocks too large for the decoder's LDS stage: the job fails with a
+      // size limit at this input's first block
+      const uint32_t j = B.in_job[g];
+      B.hj[j].status_limit = 1;
+      nblk[g] = 0;
+    }
+    in_blk0[g] = (uint32_t)NB;
+    NB += nblk[g];
+    max_block = std::max(max_block, nblk[g] ? maxblk[g] : 0u);
+  }
+  in_blk0[NG] = (uint32_t)NB;
+  if (NB > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "too many data blocks"};
+  uint32_t* d_in_blk0 = dbuf<uint32_t>(c, "in_blk0", NG + 1);
+  h2d(c, d_in_blk0, in_blk0.data(), NG + 1);
+  h2d(c, in.nblk, nblk.data(), NG);
+  Blocks blk;
+  blk.n = (uint32_t)NB;
+  blk.off = dbuf<uint64_t>(c, "blk_off", NB);
+  blk.size = dbuf<uint32_t>(c, "blk_size", NB);
+  blk.input = dbuf<uint32_t>(c, "blk_input", NB);
+  blk.local = dbuf<uint32_t>(c, "blk_local", NB);
+  blk.e0 = dbuf<uint64_t>(c, "blk_e0", NB + 1);
+  blk.ne = dbuf<uint32_t>(c, "blk_ne", NB);
+  blk.look = dbuf<unsigned long long>(c, "blk_look", NB);
+  if (NG) {
+    hipLaunchKernelGGL(k_index_emit, dim3(NG), dim3(256), 0, st, in, d_in_blk0, blk);
+    LAUNCH_CHECK();
+  }
+  mark(c, "index_emit");
+
+  // --- decode (with a retry if the entry capacity was too small)
+  uint64_t data_bytes = 0;
+  for (uint32_t g = 0; g < NG; g++) data_bytes += B.in_size[g];
+  uint64_t NCAP = std::max<uint64_t>(1024, data_bytes / 16 + 2 * NB);
+  uint64_t N = 0;
+  uint32_t maxklen = 0;
+  Tuples tu;
+  const uint32_t stage = (uint32_t)(((uint64_t)max_block + 1 + 4 + 15 + 15) & ~15ull);
+  const size_t crc_lds = sizeof(uint32_t) * (4 + 7 * 4) * 256;
+  int dwaves = 8;
+  while (dwaves > 1 && crc_lds + (size_t)stage * dwaves > c->lds_limit - 2048) dwaves--;
+  for (int attempt = 0; attempt < 2; attempt++) {
+    tu.kd = dbuf<uint64_t>(c, "tu_kd", NCAP);
+    tu.sn = dbuf<uint64_t>(c, "tu_sn", NCAP);
+    tu.vp = dbuf<uint64_t>(c, "tu_vp", NCAP);
+    tu.vlen = dbuf<uint32_t>(c, "tu_vlen", NCAP);
+    tu.blk = dbuf<uint32_t>(c, "tu_blk", NCAP);
+    tu.eoff = dbuf<uint32_t>(c, "tu_eoff", NCAP);
+    uint32_t* ticket = dbuf<uint32_t>(c, "ticket", 1);
+    uint32_t* d_maxk = dbuf<uint32_t>(c, "maxklen", 1);
+    uint64_t* d_tot = dbuf<uint64_t>(c, "dec_total", 1);
+    fill_u32(c, ticket, 0, 1);
+    fill_u32(c, d_maxk, 0, 1);
+    fill_u64(c, blk.look, 0, NB);
+    if (NB) {
+      DecodeArgs A;
+      A.in = in;
+      A.blk = blk;
+      A.tu = tu;
+      A.g_crc = c->d_crc;
+      A.err = err;
+      A.ticket = ticket;
+      A.maxklen = d_maxk;
+      A.dev_flags = dev_flags;
+      A.stage_bytes = stage;
+      A.cap = NCAP;
+      const size_t lds = crc_lds + (size_t)stage * dwaves;
+      int occ = 0;
+      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_decode, dwaves * 64, lds));
+      occ = std::max(occ, 1);
+      const uint64_t want = (NB + dwaves - 1) / dwaves;
+      const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
+      hipLaunchKernelGGL(k_decode, dim3(grid), dim3(dwaves * 64), lds, st, A);
+      LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_decode_total, dim3(1), dim3(64), 0, st, blk, d_tot);
+    LAUNCH_CHECK();
+    uint32_t fl[4];
+    d2h(c, &N, d_tot, 1);
+    d2h(c, &maxklen, d_maxk, 1);
+    d2h(c, fl, dev_flags, 4);
+    sync(c);
+    if (fl[0]) throw Fail{LUDA_DEVICE, "decode look-back wait gave up"};
+    if (N <= NCAP) break;
+    NCAP = N;
+  }
+  mark(c, "decode");
+  // entry ranges of inputs and jobs
+  std::vector<uint32_t> job_b0(J + 1, 0);
+  for (uint32_t j = 0; j < J; j++) job_b0[j] = in_blk0[B.hj[j].in_first];
+  job_b0[J] = (uint32_t)NB;
+  uint32_t* d_job_b0 = dbuf<uint32_t>(c, "job_b0", J + 1);
+  h2d(c, d_job_b0, job_b0.data(), J + 1);
+  uint64_t* d_job_e0 = dbuf<uint64_t>(c, "job_e0", J + 1);
+  uint64_t* d_in_e0 = dbuf<uint64_t>(c, "in_e0", NG + 1);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(std::max<uint64_t>(J, NG) + 1)), dim3(256), 0, st, blk, d_job_b0, J,
+                     d_in_blk0, NG, N, d_job_e0, d_in_e0);
+  LAUNCH_CHECK();
+  // keys
+  const uint32_t ulen_max = maxklen > 8 ? maxklen - 8 : 0;
+  const uint32_t kw8 = std::max<uint32_t>(2, (ulen_max + 7) / 8);
+  if ((double)N * kw8 * 8 > 64e9) throw Fail{LUDA_UNSUPPORTED, "key slots would exceed 64 GB"};
+  tu.kp0 = dbuf<uint64_t>(c, "tu_kp0", N);
+  tu.kp1 = dbuf<uint64_t>(c, "tu_kp1", N);
+  tu.tag = dbuf<uint64_t>(c, "tu_tag", N);
+  tu.ulen = dbuf<uint32_t>(c, "tu_ulen", N);
+  tu.heap = dbuf<uint64_t>(c, "tu_heap", N * kw8);
+  int32_t* in_cmp = dbuf<int32_t>(c, "in_cmp", NG);
+  fill_u32(c, (uint32_t*)in_cmp, 2u, NG);
+  if (N) {
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, kw8, N, err);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_order, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, d_in_blk0, kw8, N, in_cmp, err);
+    LAUNCH_CHECK();
+  }
+  std::vector<int32_t> h_cmp(NG);
+  std::vector<uint64_t> job_e0(J + 1), in_e0(NG + 1);
+  d2h(c, h_cmp.data(), in_cmp, NG);
+  d2h(c, job_e0.data(), d_job_e0, J + 1);
+  d2h(c, in_e0.data(), d_in_e0, NG + 1);
+  d2h(c, errs.data(), (uint64_t*)err, J);
+  sync(c);
+  mark(c, "keys");
+  for (uint32_t j = 0; j < J; j++) {
+    B.hj[j].err_key = errs[j];
+    B.hj[j].failed = errs[j] != ERR_NONE || B.hj[j].status_limit;
+  }
+
+  // --- merge rounds: runs are maximal stretches of consecutive inputs where
+  // each table's first key follows the previous table's last key
+  struct Run {
+    uint64_t a, n;
+  };
+  std::vector<std::vector<Run>> runs(J);
+  bool need_merge = false;
+  for (uint32_t j = 0; j < J; j++) {
+    if (B.hj[j].failed) {
+      runs[j].push_back(Run{job_e0[j], job_e0[j + 1] - job_e0[j]});
+      continue;
+    }
+    for (uint32_t i = 0; i < B.hj[j].n_in; i++) {
+      const uint32_t g = B.hj[j].in_first + i;
+      const uint64_t a = in_e0[g], n = in_e0[g + 1] - in_e0[g];
+      if (!n) continue;
+      if (!runs[j].empty() && h_cmp[g] == -1 && runs[j].back().a + runs[j].back().n == a) runs[j].back().n += n;
+      else runs[j].push_back(Run{a, n});
+    }
+    if (runs[j].size() > 1) need_merge = true;
+  }
+  uint32_t* ordA = dbuf<uint32_t>(c, "ordA", N);
+  uint32_t* ordB = dbuf<uint32_t>(c, "ordB", N);
+  if (N) {
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(N)), dim3(256), 0, st, ordA, N);
+    LAUNCH_CHECK();
+  }
+  uint32_t* ord = ordA;
+  int rounds = 0;
+  while (need_merge) {
+    std::vector<MergeTask> tasks;
+    need_merge = false;
+    for (uint32_t j = 0; j < J; j++) {
+      std::vector<Run> next;
+      const auto& rs = runs[j];
+      for (size_t k = 0; k < rs.size(); k += 2) {
+        if (k + 1 < rs.size()) {
+          tasks.push_back(MergeTask{(uint32_t)rs[k].a, (uint32_t)rs[k].n, (uint32_t)rs[k + 1].a, (uint32_t)rs[k + 1].n,
+                                    rs[k].a});
+          next.push_back(Run{rs[k].a, rs[k].n + rs[k + 1].n});
+        } else {
+          tasks.push_back(MergeTask{(uint32_t)rs[k].a, (uint32_t)rs[k].n, 0, 0, rs[k].a});
+          next.push_back(rs[k]);
+        }
+      }
+      if (rs.empty() && job_e0[j + 1] > job_e0[j]) {
+        tasks.push_back(MergeTask{(uint32_t)job_e0[j], (uint32_t)(job_e0[j + 1] - job_e0[j]), 0, 0, job_e0[j]});
+        next.push_back(Run{job_e0[j], job_e0[j + 1] - job_e0[j]});
+      }
+      runs[j] = next;
+      if (runs[j].size() > 1) need_merge = true;
+    }
+    // tasks must tile [0, N) in order
+    std::sort(tasks.begin(), tasks.end(), [](const MergeTask& x, const MergeTask& y) { return x.out0 < y.out0; });
+    std::vector<MergeTask> tiled;
+    uint64_t pos = 0;
+    for (auto& t : tasks) {
+      if (t.la + (uint64_t)t.lb == 0) continue;
+      if (t.out0 > pos) tiled.push_back(MergeTask{(uint32_t)pos, (uint32_t)(t.out0 - pos), 0, 0, pos});
+      tiled.push_back(t);
+      pos = t.out0 + t.la + t.lb;
+    }
+    if (pos < N) tiled.push_back(MergeTask{(uint32_t)pos, (uint32_t)(N - pos), 0, 0, pos});
+    MergeTask* d_tasks = dbuf<MergeTask>(c, "merge_tasks", tiled.size());
+    h2d(c, d_tasks, tiled.data(), tiled.size());
+    uint32_t* dst = (ord == ordA) ? ordB : ordA;
+    const uint64_t threads = (N + MERGE_ITEMS_PER_THREAD - 1) / MERGE_ITEMS_PER_THREAD;
+    hipLaunchKernelGGL(k_merge, dim3(blocks_for(threads)), dim3(256), 0, st, d_tasks, (uint32_t)tiled.size(), ord,
+                       dst, tu, kw8, N);
+    LAUNCH_CHECK();
+    ord = dst;
+    rounds++;
+    sync(c);  // the task list is reused next round
+  }
+  mark(c, "merge");
+  // --- drop shadowed versions and bottom-level deletions
+  uint32_t* keep = dbuf<uint32_t>(c, "keep", N);
+  uint32_t* kpos = dbuf<uint32_t>(c, "kpos", N + 1);
+  uint32_t* scan32 = dbuf<uint32_t>(c, "scan_tmp32", N / 2048 + 8);
+  unsigned long long* shadowed = dbuf<unsigned long long>(c, "shadowed", J);
+  unsigned long long* tomb = dbuf<unsigned long long>(c, "tomb", J);
+  fill_u64(c, shadowed, 0, J);
+  fill_u64(c, tomb, 0, J);
+  std::vector<uint32_t> active(J);
+  for (uint32_t j = 0; j < J; j++) active[j] = B.hj[j].failed ? 0u : 1u;
+  uint32_t* d_active = dbuf<uint32_t>(c, "job_active", J);
+  h2d(c, d_active, active.data(), J);
+  uint32_t* surv = dbuf<uint32_t>(c, "surv", N);
+  uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", J + 1);
+  if (N) {
+    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N)), dim3(256), 0, st, ord, tu, kw8, d_jobs, d_job_e0, J, N,
+                       keep, shadowed, tomb, d_active);
+    LAUNCH_CHECK();
+  }
+  launch_scan<uint32_t>(keep, N, kpos, scan32, st);
+  LAUNCH_CHECK();
+  if (N) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N)), dim3(256), 0, st, ord, keep, kpos, N, surv);
+    LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_job_surv, dim3(blocks_for(J + 1)), dim3(256), 0, st, d_job_e0, kpos, J, d_job_s0);
+  LAUNCH_CHECK();
+  PlanIn P;
+  P.J = J;
+  P.d_jobs = d_jobs;
+  P.jobs = &B.jd;
+  P.tu = tu;
+  P.kw8 = kw8;
+  P.d_surv = surv;
+  P.job_s0.assign(J + 1, 0);
+  P.d_job_s0 = d_job_s0;
+  std::vector<uint64_t> h_shadow(J), h_tomb(J);
+  d2h(c, P.job_s0.data(), d_job_s0, J + 1);
+  d2h(c, h_shadow.data(), (uint64_t*)shadowed, J);
+  d2h(c, h_tomb.data(), (uint64_t*)tomb, J);
+  sync(c);
+  mark(c, "dedup");
+
+  PlanOut O;
+  plan_and_write(c, P, O);
+
+  // --- results
+  const bool dev_out = dev_inputs;
+  uint8_t* host_all = nullptr;
+  if (!dev_out && O.total_bytes) {
+    host_all = (uint8_t*)malloc(O.total_bytes);
+    if (!host_all) throw Fail{LUDA_NOMEM, "host output allocation failed"};
+    HIPCK(hipMemcpyAsync(host_all, O.d_out, O.total_bytes, hipMemcpyDeviceToHost, st));
+  }
+  mark(c, "d2h");
+  sync(c);
+  const double ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
+  // device outputs get their own buffer so that the next call cannot reuse it
+  uint8_t* dev_copy = nullptr;
+  DevBlock* dblk = nullptr;
+  if (dev_out && O.total_bytes) {
+    DBuf& b = c->bufs["out_tables"];
+    dev_copy = (uint8_t*)b.p;  // hand the buffer over to the results
+    b.p = nullptr;
+    b.cap = 0;
+    dblk = new DevBlock{dev_copy, 0};
+  }
+  for (uint32_t j = 0; j < J; j++) {
+    luda_result& r = results[j];
+    memset(&r, 0, sizeof r);
+    r.entries_in = job_e0[j + 1] - job_e0[j];
+    r.bytes_in = B.hj[j].bytes_in;
+    r.ms_total = ms;
+    if (B.hj[j].failed) {
+      if (B.hj[j].err_key != ERR_NONE) r.error = decode_err(B.hj[j].err_key, B.in_size, B.hj[j].in_first);
+      else {
+        r.error.status = LUDA_UNSUPPORTED;
+      }
+      r.status = r.error.status;
+      continue;
+    }
+    r.entries_out = P.job_s0[j + 1] - P.job_s0[j];
+    r.dropped_shadowed = h_shadow[j];
+    r.dropped_tombstones = h_tomb[j];
+    const uint64_t f0 = O.job_f0[j], f1 = O.job_f0[j + 1];
+    r.num_files = (uint32_t)(f1 - f0);
+    ResultInternal* ri = new ResultInternal();
+    r.internal = ri;
+    if (r.num_files) {
+      r.files = (luda_file*)calloc(r.num_files, sizeof(luda_file));
+      const uint64_t base = O.file_out[f0];
+      for (uint64_t f = f0; f < f1; f++) {
+        r.files[f - f0].offset = O.file_out[f] - base;
+        r.files[f - f0].size = O.file_out[f + 1] - O.file_out[f];
+        r.files[f - f0].num_entries = O.file_entries[f];
+      }
+      r.data_size = O.file_out[f1] - base;
+      r.bytes_out = r.data_size;
+      if (dev_out) {
+        r.data = dev_copy + base;
+        ri->dev = dblk;
+        dblk->refs++;
+      } else {
+        r.data = (uint8_t*)malloc(r.data_size);
+        if (!r.data) throw Fail{LUDA_NOMEM, "host result allocation failed"};
+        memcpy(r.data, host_all + base, r.data_size);
+        ri->host_data = true;
+      }
+    }
+  }
+  free(host_all);
+  if (dblk && dblk->refs == 0) {
+    (void)hipFree(dblk->p);
+    delete dblk;
+  }
+  // collect stage times
+  c->stage_ms.clear();
+  if (c->timing && c->marks.size() > 1) {
+    for (size_t i = 1; i < c->marks.size(); i++) {
+      float t = 0;
+      HIPCK(hipEventElapsedTime(&t, c->marks[i - 1].second, c->marks[i].second));
+      c->stage_ms.emplace_back(c->marks[i].first, t);
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+int luda_selftest_crc(void) {
+  static CrcTables T;
+  build_crc_tables(&T);
+  // shift tables against zero-byte processing
+  uint32_t t0[256];
+  for (uint32_t b = 0; b < 256; b++) t0[b] = T.t4[0][b];
+  uint32_t x = 0x12345678u;
+  for (int k = 0; k < 4; k++) {
+    uint32_t r = x;
+    const int m = 68 << k;
+    for (int z = 0; z < m; z++) r = step_byte(r, 0, t0);
+    if (apply_shift(T.sh[k], x) != r) return 1;
+    x = x * 2654435761u + 12345u;
+  }
+  // slicing-by-4 against bytewise on one dword
+  uint32_t c = 0xDEADBEEFu, d = 0x01020304u;
+  uint32_t r = c;
+  for (int i = 0; i < 4; i++) r = step_byte(r, (uint8_t)(d >> (8 * i)), t0);
+  uint32_t y = c ^ d;
+  uint32_t s = T.t4[3][y & 0xFF] ^ T.t4[2][(y >> 8) & 0xFF] ^ T.t4[1][(y >> 16) & 0xFF] ^ T.t4[0][y >> 24];
+  if (r != s) return 2;
+  return 0;
+}
+
+int luda_ctx_create(int device, luda_ctx** out) {
+  if (!out) return LUDA_INVALID_ARG;
+  *out = nullptr;
+  luda_ctx* c = new luda_ctx();
+  try {
+    c->device = device;
+    HIPCK(hipSetDevice(device));
+    HIPCK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    c->stream = c->own;
+    hipDeviceProp_t prop;
+    HIPCK(hipGetDeviceProperties(&prop, device));
+    c->n_cu = prop.multiProcessorCount;
+    c->lds_limit = prop.sharedMemPerBlock;
+    // kernels whose dynamic LDS is sized at run time may use all of it
+    const void* dyn[] = {(const void*)k_decode, (const void*)k_encode, (const void*)k_filter,
+                         (const void*)k_seg_compose};
+    for (const void* f : dyn)
+      HIPCK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_limit - 2048));
+    static CrcTables T;
+    build_crc_tables(&T);
+    HIPCK(hipMalloc((void**)&c->d_crc, sizeof(CrcTables)));
+    HIPCK(hipMemcpy(c->d_crc, &T, sizeof(CrcTables), hipMemcpyHostToDevice));
+    c->timing = getenv("LUDA_STAGE_TIMES") != nullptr;
+  } catch (const Fail& f) {
+    fprintf(stderr, "luda_ctx_create: %s\n", f.msg.c_str());
+    delete c;
+    return f.status;
+  }
+  *out = c;
+  return LUDA_OK;
+}
+
+void luda_ctx_destroy(luda_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->d_crc) (void)hipFree(c->d_crc);
+  if (c->own) (void)hipStreamDestroy(c->own);
+  delete c;
+}
+
+int luda_set_stream(luda_ctx* c, void* s) {
+  if (!c) return LUDA_INVALID_ARG;
+  c->stream = s ? (hipStream_t)s : c->own;
+  return LUDA_OK;
+}
+
+static int run_guarded(luda_ctx* c, const luda_job* jobs, uint32_t n, bool dev, luda_result* res) {
+  try {
+    HIPCK(hipSetDevice(c->device));
+    run_batch(c, jobs, n, dev, res);
+  } catch (const Fail& f) {
+    c->last_error = f.msg;
+    for (uint32_t j = 0; j < n; j++) {
+      memset(&res[j], 0, sizeof(luda_result));
+      res[j].status = f.status;
+      res[j].error.status = f.status;
+    }
+    return f.status;
+  }
+  return LUDA_OK;
+}
+
+int luda_compact_batch(luda_ctx* c, const luda_job* jobs, uint32_t n_jobs, int device_inputs, luda_result* results) {
+  if (!c || (n_jobs && (!jobs || !results))) return LUDA_INVALID_ARG;
+  for (uint32_t j = 0; j < n_jobs; j++) {
+    if (check_opt(&jobs[j].options) != LUDA_OK || (jobs[j].n_inputs && !jobs[j].inputs)) return LUDA_INVALID_ARG;
+    for (uint32_t i = 0; i < jobs[j].n_inputs; i++)
+      if (!jobs[j].inputs[i].data && jobs[j].inputs[i].size) return LUDA_INVALID_ARG;
+  }
+  if (!n_jobs) return LUDA_OK;
+  return run_guarded(c, jobs, n_jobs, device_inputs != 0, results);
+}
+
+static int compact_one(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda_options* opt, luda_result* out,
+                       bool dev) {
+  if (!c || !out || (n && !inputs)) return LUDA_INVALID_ARG;
+  memset(out, 0, sizeof *out);
+  if (check_opt(opt) != LUDA_OK) {
+    out->status = out->error.status = LUDA_INVALID_ARG;
+    return LUDA_INVALID_ARG;
+  }
+  for (uint32_t i = 0; i < n; i++)
+    if (!inputs[i].data && inputs[i].size) {
+      out->status = out->error.status = LUDA_INVALID_ARG;
+      return LUDA_INVALID_ARG;
+    }
+  luda_job job{inputs, n, *opt};
+  int rc = run_guarded(c, &job, 1, dev, out);
+  if (rc != LUDA_OK) return rc;
+  return out->status;
+}
+
+int luda_compact(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda_options* opt, luda_result* out) {
+  return compact_one(c, inputs, n, opt, out, false);
+}
+
+int luda_compact_dev(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda_options* opt, luda_result* out) {
+  return compact_one(c, inputs, n, opt, out, true);
+}
+
+void luda_result_free(luda_ctx* c, luda_result* r) {
+  if (!r) return;
+  ResultInternal* ri = (ResultInternal*)r->internal;
+  if (ri && ri->host_data) free(r->data);
+  release_dev(ri);
+  delete ri;
+  free(r->files);
+  memset(r, 0, sizeof *r);
+  (void)c;
+}
+
+int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const uint64_t* koff, const uint64_t* tags,
+                          const uint8_t* vals, const uint64_t* voff, const luda_options* opt, luda_result* out) {
+  if (!c || !out || (n && (!keys || !koff || !tags || !vals || !voff))) return LUDA_INVALID_ARG;
+  memset(out, 0, sizeof *out);
+  if (check_opt(opt) != LUDA_OK) {
+    out->status = out->error.status = LUDA_INVALID_ARG;
+    return LUDA_INVALID_ARG;
+  }
+  try {
+    HIPCK(hipSetDevice(c->device));
+    if (n > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "more than 2^32 entries"};
+    hipStream_t st = c->stream;
+    c->marks.clear();
+    c->event_used = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    uint32_t* d_max = dbuf<uint32_t>(c, "w_max", 2);
+    fill_u32(c, d_max, 0, 2);
+    if (n) {
+      hipLaunchKernelGGL(k_ingest_max, dim3(blocks_for(n)), dim3(256), 0, st, koff, n, d_max);
+      LAUNCH_CHECK();
+    }
+    uint32_t maxlen = 0;
+    d2h(c, &maxlen, d_max, 1);
+    sync(c);
+    const uint32_t kw8 = std::max<uint32_t>(2, (maxlen + 7) / 8);
+    Tuples tu;
+    memset(&tu, 0, sizeof tu);
+    tu.kp0 = dbuf<uint64_t>(c, "tu_kp0", n);
+    tu.kp1 = dbuf<uint64_t>(c, "tu_kp1", n);
+    tu.tag = dbuf<uint64_t>(c, "tu_tag", n);
+    tu.ulen = dbuf<uint32_t>(c, "tu_ulen", n);
+    tu.heap = dbuf<uint64_t>(c, "tu_heap", n * kw8);
+    tu.vp = dbuf<uint64_t>(c, "tu_vp", n);
+    tu.vlen = dbuf<uint32_t>(c, "tu_vlen", n);
+    uint32_t* surv = dbuf<uint32_t>(c, "surv", n);
+    if (n) {
+      hipLaunchKernelGGL(k_ingest, dim3(blocks_for(n)), dim3(256), 0, st, keys, koff, tags, vals, voff, n, tu, kw8,
+                         surv);
+      LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_check_sorted, dim3(blocks_for(n)), dim3(256), 0, st, tu, kw8, n, d_max + 1);
+      LAUNCH_CHECK();
+    }
+    uint32_t bad = 0;
+    d2h(c, &bad, d_max + 1, 1);
+    sync(c);
+    if (bad) throw Fail{LUDA_UNSORTED_INPUT, "entries are not strictly increasing internal keys"};
+    std::vector<JobDesc> jd(1);
+    jd[0] = JobDesc{opt->block_size, opt->restart_interval, opt->bloom_bits_per_key, opt->bottommost ? 1u : 0u,
+                    opt->target_file_size, 0, 0};
+    JobDesc* d_jobs = dbuf<JobDesc>(c, "jobs", 1);
+    h2d(c, d_jobs, jd.data(), 1);
+    uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", 2);
+    uint64_t hs0[2] = {0, n};
+    h2d(c, d_job_s0, hs0, 2);
+    PlanIn P;
+    P.J = 1;
+    P.d_jobs = d_jobs;
+    P.jobs = &jd;
+    P.tu = tu;
+    P.kw8 = kw8;
+    P.d_surv = surv;
+    P.job_s0.assign(hs0, hs0 + 2);
+    P.d_job_s0 = d_job_s0;
+    PlanOut O;
+    plan_and_write(c, P, O);
+    sync(c);
+    out->status = LUDA_OK;
+    out->entries_in = out->entries_out = n;
+    out->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const uint64_t nf = O.job_f0[1] - O.job_f0[0];
+    out->num_files = (uint32_t)nf;
+    ResultInternal* ri = new ResultInternal();
+    out->internal = ri;
+    if (nf) {
+      DBuf& b = c->bufs["out_tables"];
+      uint8_t* dev = (uint8_t*)b.p;
+      b.p = nullptr;
+      b.cap = 0;
+      ri->dev = new DevBlock{dev, 1};
+      out->files = (luda_file*)calloc(nf, sizeof(luda_file));
+      for (uint64_t f = 0; f < nf; f++) {
+        out->files[f].offset = O.file_out[f];
+        out->files[f].size = O.file_out[f + 1] - O.file_out[f];
+        out->files[f].num_entries = O.file_entries[f];
+      }
+      out->data = dev;
+      out->data_size = O.file_out[nf];
+      out->bytes_out = out->data_size;
+    }
+  } catch (const Fail& f) {
+    c->last_error = f.msg;
+    out->status = out->error.status = f.status;
+    return f.status;
+  }
+  return LUDA_OK;
+}
+
+const char* luda_status_str(int s) {
+  switch (s) {
+    case LUDA_OK: return "OK";
+    case LUDA_INVALID_ARG: return "INVALID_ARG";
+    case LUDA_CORRUPT_FORMAT: return "CORRUPT_FORMAT";
+    case LUDA_CORRUPT_CHECKSUM: return "CORRUPT_CHECKSUM";
+    case LUDA_UNSORTED_INPUT: return "UNSORTED_INPUT";
+    case LUDA_UNSUPPORTED: return "UNSUPPORTED";
+    case LUDA_NOMEM: return "NOMEM";
+    case LUDA_DEVICE: return "DEVICE";
+    default: return "UNKNOWN";
+  }
+}
+
+int luda_debug_read(luda_ctx* c, const char* name, void* dst, uint64_t offset, uint64_t bytes) {
+  if (!c || !name || (!dst && bytes)) return LUDA_INVALID_ARG;
+  auto it = c->bufs.find(name);
+  if (it == c->bufs.end() || !it->second.p || offset + bytes > it->second.cap) return LUDA_INVALID_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LUDA_DEVICE;
+  if (hipMemcpy(dst, (const uint8_t*)it->second.p + offset, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return LUDA_DEVICE;
+  return LUDA_OK;
+}
+
+const char* luda_last_error(luda_ctx* c) { return c ? c->last_error.c_str() : ""; }
+
+int luda_stage_times(luda_ctx* c, const char** names, double* ms, int cap) {
+  if (!c) return 0;
+  int n = (int)c->stage_ms.size();
+  for (int i = 0; i < n && i < cap; i++) {
+    if (names) names[i] = c->stage_ms[i].first.c_str();
+    if (ms) ms[i] = c->stage_ms[i].second;
+  }
+  return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+"""GPU parity: output tables byte-identical to the oracle's, through the C-ABI.
+
+Inputs are written by the oracle's table writer from seeded workloads; the
+GPU library compacts them and every output byte is compared with the
+oracle's compaction of the same inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same_files, ctx, err_tuple, say
+from workload import config0, config1, config2, config3_job, tiny_job
+
+pytestmark = pytest.mark.gpu
+
+
+def to_dev(blobs):
+    import torch
+    return [torch.frombuffer(bytearray(b), dtype=torch.uint8).to("cuda") if len(b) else
+            torch.empty(0, dtype=torch.uint8, device="cuda") for b in blobs]
+
+
+def run_both(job, label, device=False, inputs=None):
+    ins = inputs if inputs is not None else oracle.build_input_tables(job)
+    say(f"[gpu] {label}: {len(ins)} inputs, {sum(map(len, ins))} bytes")
+    ref = oracle.compact(ins, job.options())
+    if device:
+        res = ctx().compact_dev(to_dev(ins), job.options())
+        files = [t.cpu().numpy().tobytes() for t in res.files]
+    else:
+        res = ctx().compact(ins, job.options())
+        files = res.files
+    assert res.status == ref.status, (label, res.name, ctx().last_error(), str(ref.error), res.error)
+    if ref.status != 0:
+        assert err_tuple(res.error) == err_tuple(ref.error), (label, res.error, ref.error)
+        return res, ref
+    assert_same_files(files, ref.files, label)
+    assert (res.entries_in, res.entries_out, res.dropped_shadowed, res.dropped_tombstones) == \
+        (ref.entries_in, ref.entries_out, ref.dropped_shadowed, ref.dropped_tombstones), label
+    return res, ref
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("mode", ["l0", "leveled"])
+def test_tiny(seed, mode):
+    run_both(tiny_job(seed, mode=mode, bottommost=seed % 2), f"tiny-{mode}-{seed}")
+
+
+TINY_VARIANTS = [
+    dict(restart_interval=1, block_size=32),
+    dict(restart_interval=16, block_size=4096, target_file_size=1 << 20),
+    dict(key_len=(1, 40), key_alphabet=2, val_len=(0, 300), block_size=256, restart_interval=4),
+    dict(key_len=(17, 33), key_alphabet=2, val_len=(0, 10), entries=200, block_size=512),
+    dict(n_inputs=9, entries=30, mode="leveled", block_size=100, target_file_size=300),
+    dict(n_inputs=6, entries=80, p_tomb=0.6, bottommost=1, block_size=1, target_file_size=1),
+    dict(entries=300, key_alphabet=4, key_len=(3, 6), val_len=(100, 200), block_size=4096, target_file_size=4096,
+         restart_interval=7, bloom_bits_per_key=3),
+]
+
+
+@pytest.mark.parametrize("vi", range(len(TINY_VARIANTS)))
+def test_tiny_variants(vi):
+    kw = dict(TINY_VARIANTS[vi])
+    for seed in range(3):
+        run_both(tiny_job(100 + seed, **kw), f"variant{vi}-{seed}")
+
+
+def test_empty_and_all_dropped():
+    res = ctx().compact([], dict(block_size=4096, restart_interval=16, bloom_bits_per_key=10, bottommost=1,
+                                 target_file_size=1 << 20))
+    assert res.status == 0 and res.files == []
+    res, ref = run_both(tiny_job(3, p_tomb=1.0, bottommost=1), "all-dropped")
+    assert res.files == [] and ref.files == []
+
+
+def test_config0():
+    run_both(config0(), "config0")
+
+
+def test_config0_device_inputs():
+    run_both(config0(), "config0-dev", device=True)
+
+
+@pytest.mark.parametrize("scale", [1 / 64, 1 / 16])
+def test_config1_scaled(scale):
+    run_both(config1(scale=scale), f"config1x{scale}")
+
+
+@pytest.mark.parametrize("scale", [1 / 64, 1 / 16])
+def test_config2_scaled(scale):
+    run_both(config2(scale=scale), f"config2x{scale}")
+
+
+@pytest.mark.parametrize("job", [0, 1, 7])
+def test_config3_jobs_scaled(job):
+    run_both(config3_job(job, scale=1 / 32), f"config3-job{job}")
+
+
+def test_batch_matches_alone():
+    jobs = [tiny_job(s, mode=("l0", "leveled")[s % 2], bottommost=s % 2) for s in range(10)]
+    jobs += [config3_job(2, scale=1 / 64), config0()]
+    ins = [oracle.build_input_tables(j) for j in jobs]
+    say(f"[gpu] batch of {len(jobs)} jobs")
+    out = ctx().compact_batch([(i, j.options()) for i, j in zip(ins, jobs)], device_inputs=False)
+    for k, (j, i, r) in enumerate(zip(jobs, ins, out)):
+        ref = oracle.compact(i, j.options())
+        assert r.status == 0, (k, r.name, ctx().last_error())
+        assert_same_files(r.files, ref.files, f"batch job {k}")
+        alone = ctx().compact(i, j.options())
+        assert alone.files == r.files, f"batch job {k}: alone vs batch"
