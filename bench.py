@@ -1,0 +1,191 @@
+"""Benchmark: compaction input GB/s of one large compaction on one MI355X.
+
+Workload: one upper table + 10 overlapping lower tables of ~64 MiB each
+(~700 MiB of input), 16-byte Zipf(0.99) keys over 2^32, 1 KiB values, 2%
+deletions, output not at the bottom level, 4 KiB blocks, restart interval 16,
+10 bits/key Bloom filters, 64 MiB output tables.  The input tables are written
+on the GPU by the library's own table writer from seeded synthetic entries and
+stay resident in HBM; each timed step is one whole compaction (decode with
+checksums, merge and drop, re-encode with index, filter and checksums), with
+the output tables left in HBM.
+
+The JSON line's `value` is input bytes / wall time of the timed steps.  Extra
+fields: the end-to-end rate (host tables -> device -> host tables, PCIe
+included), per-kernel times, the roofline of the dominant kernel, and the CPU
+baseline (the plain oracle on this host, single thread).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def device_tables(ctx, job):
+    """Write each run of the job as one input table on the GPU."""
+    import torch
+    tables = []
+    for r in job.runs:
+        t = lambda a: torch.from_numpy(a).to("cuda")  # noqa: E731
+        keys = t(r.keys if r.keys.size else r.keys.reshape(0))
+        res = ctx.build_tables_dev(t(r.keys), t(r.koff.astype("int64")), t(r.tags.view("int64")),
+                                   t(r.vals), t(r.voff.astype("int64")), job.table_options())
+        if res.status != 0 or len(res.files) != 1:
+            raise RuntimeError(f"device table writer failed: {res.name} {ctx.last_error()}")
+        tables.append(res.files[0])
+        del keys
+    torch.cuda.synchronize()
+    return tables
+
+
+def kernel_times(ctx):
+    return {k.split(":", 1)[1]: v for k, v in ctx.stage_times() if k.startswith("kernel:")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=float, default=1.0, help="table size scale (1.0 = 64 MiB tables)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--e2e-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (jobs are independent: "
+              "several GPUs would each run their own jobs with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2004_03054_amd import Context
+    from workload import config1
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    job = config1(scale=args.scale)
+    log(f"[bench] generated {job.name}: {sum(r.n for r in job.runs)} entries in {time.time() - t0:.1f}s")
+    ctx = Context(0)
+    tables = device_tables(ctx, job)
+    in_bytes = sum(int(t.numel()) for t in tables)
+    log(f"[bench] {len(tables)} input tables on the device, {in_bytes / 2**20:.1f} MiB")
+    opts = job.options()
+
+    # warmup (also checks the result is well formed)
+    res = None
+    for _ in range(args.warmup):
+        res = ctx.compact_dev(tables, opts, materialize=False)
+        assert res.status == 0, (res.name, ctx.last_error())
+    # timed steps: kernel-only (inputs resident in HBM, outputs left in HBM)
+    ktimes = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.compact_dev(tables, opts, materialize=False)
+        ktimes.append(kernel_times(ctx))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t_start
+    assert res.status == 0, (res.name, ctx.last_error())
+    counters = ctx.counters()
+    ms_step = dt * 1e3 / args.steps
+    value = in_bytes * args.steps / dt / 1e9
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} GB/s input")
+
+    # per-kernel average times over the timed steps
+    names = sorted(set(k for kt in ktimes for k in kt))
+    kavg = {n: float(np.mean([kt.get(n, 0.0) for kt in ktimes])) for n in names}
+    # roofline of the dominant kernel from its algorithmic bytes:
+    #   k_decode reads every input data block once (contents + trailer)
+    #   k_encode reads every surviving value once and writes every output
+    #   data block once; both are approximated by their data-block bytes
+    alg = {
+        "k_decode": counters.get("data_bytes_in", 0.0),
+        "k_encode": 2.0 * counters.get("data_bytes_out", 0.0),
+    }
+    dom = max(alg, key=lambda k: kavg.get(k, 0.0))
+    achieved = alg[dom] / (kavg[dom] * 1e-3) / 1e9 if kavg.get(dom) else 0.0
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": alg[dom], "avg_ms": round(kavg[dom], 4)}
+    other = {k: {"avg_ms": round(kavg.get(k, 0.0), 4),
+                 "gbps": round(alg[k] / (kavg[k] * 1e-3) / 1e9, 1) if kavg.get(k) else None}
+             for k in alg}
+
+    # end to end: host tables in, host tables out (PCIe both ways)
+    host_tables = [t.cpu().numpy().tobytes() for t in tables]
+    e2e = None
+    if args.e2e_steps > 0:
+        r = ctx.compact(host_tables, opts)
+        assert r.status == 0
+        t1 = time.perf_counter()
+        for _ in range(args.e2e_steps):
+            r = ctx.compact(host_tables, opts)
+        e2e_dt = time.perf_counter() - t1
+        e2e = round(in_bytes * args.e2e_steps / e2e_dt / 1e9, 2)
+        gpu_files = r.files
+        log(f"[bench] end to end: {e2e} GB/s")
+    else:
+        gpu_files = ctx.compact(host_tables, opts).files
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle (plain sequential C, one thread) on the same workload:
+        # its own input tables, timed around the compaction only
+        import oracle
+        ref_inputs = oracle.build_input_tables(job)
+        same_inputs = ref_inputs == host_tables
+        t2 = time.perf_counter()
+        ref = oracle.compact(ref_inputs, opts)
+        cdt = time.perf_counter() - t2
+        digest = lambda fs: hashlib.sha256(b"".join(fs)).hexdigest()  # noqa: E731
+        cpu = {"value": round(in_bytes / cdt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full compaction of the same workload ({in_bytes / 2**20:.0f} MiB input), "
+                         f"{cdt:.1f} s",
+               "bit_exact": bool(ref.status == 0 and ref.files == gpu_files),
+               "inputs_identical": bool(same_inputs),
+               "sha256_gpu": digest(gpu_files)[:16], "sha256_oracle": digest(ref.files)[:16]}
+        log(f"[bench] oracle: {cdt:.1f}s, bit-exact {cpu['bit_exact']}")
+
+    out = {
+        "metric": "compaction input GB/s",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": job.name, "inputs": len(tables), "input_bytes": in_bytes,
+                   "entries_in": res.entries_in, "entries_out": res.entries_out,
+                   "files_out": len(res.file_sizes), "block_size": opts["block_size"],
+                   "restart_interval": opts["restart_interval"], "bloom_bits_per_key": opts["bloom_bits_per_key"],
+                   "bottommost": opts["bottommost"], "target_file_size": opts["target_file_size"],
+                   "inputs_resident": "hbm", "outputs": "hbm"},
+        "end_to_end_gbps": e2e,
+        "kernel_ms": {k: round(v, 4) for k, v in kavg.items()},
+        "kernels": other,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -153,10 +153,16 @@ void luda_result_free(luda_ctx *ctx, luda_result *r);
 const char *luda_status_str(int status);
 const char *luda_last_error(luda_ctx *ctx);
 
-/* Per-stage device times (milliseconds) of the last call, measured with HIP
- * events on the context's stream; names[] and ms[] receive up to `cap`
- * entries.  Returns the number of stages. */
+/* Device times (milliseconds) of the last call, measured with HIP events on
+ * the context's stream: "kernel:<name>" for the hot kernels (always), and
+ * stage spans when the environment variable LUDA_STAGE_TIMES is set.
+ * names[] and ms[] receive up to `cap` entries; returns the count. */
 int luda_stage_times(luda_ctx *ctx, const char **names, double *ms, int cap);
+
+/* Counters of the last call (e.g. "data_bytes_in": bytes of the input data
+ * blocks with trailers, "data_bytes_out", "entries_in", "survivors").
+ * Same calling convention as luda_stage_times. */
+int luda_last_counters(luda_ctx *ctx, const char **names, double *values, int cap);
 
 /* Diagnostics: copy `bytes` bytes at `offset` of the named internal device
  * buffer of the last call into host memory `dst` (e.g. "tu_kp0", "surv").

@@ -54,7 +54,7 @@ class LudaJob(C.Structure):
 
 EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compact", "luda_compact_dev",
            "luda_compact_batch", "luda_build_tables_dev", "luda_result_free", "luda_status_str",
-           "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read"]
+           "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters"]
 
 _lib = None
 
@@ -90,6 +90,8 @@ def lib():
     L.luda_last_error.restype = C.c_char_p
     L.luda_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int]
     L.luda_stage_times.restype = C.c_int
+    L.luda_last_counters.argtypes = [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int]
+    L.luda_last_counters.restype = C.c_int
     L.luda_debug_read.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_uint64, C.c_uint64]
     L.luda_debug_read.restype = C.c_int
     L.luda_selftest_crc.argtypes = []
@@ -130,6 +132,7 @@ class Result:
     bytes_in: int = 0
     bytes_out: int = 0
     ms_total: float = 0.0
+    file_sizes: List[int] = field(default_factory=list)
 
     @property
     def name(self) -> str:
@@ -144,13 +147,17 @@ class _DevView:
                                          "version": 2, "strides": None}
 
 
-def _take(ctx, r: LudaResult, device: bool) -> Result:
+def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
     e = r.error
     res = Result(r.status, Error(e.status, e.input, e.where, e.phase, e.block, e.offset),
                  entries_in=r.entries_in, entries_out=r.entries_out, dropped_shadowed=r.dropped_shadowed,
                  dropped_tombstones=r.dropped_tombstones, bytes_in=r.bytes_in, bytes_out=r.bytes_out,
                  ms_total=r.ms_total)
-    if r.status == 0 and r.num_files:
+    if r.status == 0 and r.num_files and not materialize:
+        res.files = [None] * r.num_files
+        res.file_entries = [r.files[i].num_entries for i in range(r.num_files)]
+        res.file_sizes = [r.files[i].size for i in range(r.num_files)]
+    elif r.status == 0 and r.num_files:
         import torch  # device memory plumbing only
         for i in range(r.num_files):
             f = r.files[i]
@@ -230,15 +237,16 @@ class Context:
         lib().luda_compact(self._h, bufs, len(inputs), C.byref(o), C.byref(r))
         return _take(self._h, r, device=False)
 
-    def compact_dev(self, inputs: Sequence, opts: dict) -> Result:
-        """Device (torch uint8 cuda tensors) tables in, device tensors out."""
+    def compact_dev(self, inputs: Sequence, opts: dict, materialize: bool = True) -> Result:
+        """Device (torch uint8 cuda tensors) tables in, device tensors out.
+        With materialize=False the output tables are released unread (sizes only)."""
         bufs = _dev_bufs(inputs)
         o = options(opts)
         r = LudaResult()
         lib().luda_compact_dev(self._h, bufs, len(inputs), C.byref(o), C.byref(r))
-        return _take(self._h, r, device=True)
+        return _take(self._h, r, device=True, materialize=materialize)
 
-    def compact_batch(self, jobs: Sequence, device_inputs: bool) -> List[Result]:
+    def compact_batch(self, jobs: Sequence, device_inputs: bool, materialize: bool = True) -> List[Result]:
         """jobs: sequence of (inputs, options dict)."""
         J = len(jobs)
         cjobs = (LudaJob * max(1, J))()
@@ -255,7 +263,7 @@ class Context:
             cjobs[j].options = options(opts)
         res = (LudaResult * max(1, J))()
         rc = lib().luda_compact_batch(self._h, cjobs, J, 1 if device_inputs else 0, res)
-        out = [_take(self._h, res[j], device=device_inputs) for j in range(J)]
+        out = [_take(self._h, res[j], device=device_inputs, materialize=materialize) for j in range(J)]
         if rc != 0 and J:
             for o in out:
                 if o.status == 0:
@@ -285,6 +293,12 @@ class Context:
         ms = (C.c_double * 64)()
         n = lib().luda_stage_times(self._h, names, ms, 64)
         return [(names[i].decode(), ms[i]) for i in range(min(n, 64))]
+
+    def counters(self) -> dict:
+        names = (C.c_char_p * 64)()
+        vals = (C.c_double * 64)()
+        n = lib().luda_last_counters(self._h, names, vals, 64)
+        return {names[i].decode(): vals[i] for i in range(min(n, 64))}
 
 
 def selftest_crc() -> int:

@@ -27,6 +27,7 @@ __global__ void k_footer(Inputs in, unsigned long long* err) {
   const uint32_t job = in.job[g], loc = in.local[g];
   in.nblk[g] = 0;
   in.maxblk[g] = 0;
+  in.dbytes[g] = 0;
   in.idx_size[g] = ~0ull;  // marks a failed input
   if (size < 48) {
     report_err(&err[job], err_key(loc, W_FOOTER, 0, FP_SHORT, 0, EC_FORMAT));
@@ -216,6 +217,7 @@ __global__ void __launch_bounds__(256) k_index_scan(Inputs in, const uint32_t* g
   __shared__ uint32_t sflag;
   __shared__ uint32_t scount;
   __shared__ uint32_t smax;
+  __shared__ unsigned long long sbytes;
   const uint32_t g = blockIdx.x;
   if (in.idx_size[g] == ~0ull) return;  // footer failed
   const uint32_t job = in.job[g], loc = in.local[g];
@@ -223,6 +225,7 @@ __global__ void __launch_bounds__(256) k_index_scan(Inputs in, const uint32_t* g
   if (threadIdx.x == 0) {
     scount = 0;
     smax = 0;
+    sbytes = 0;
   }
   __syncthreads();
   const uint8_t* base = (const uint8_t*)in.ptr[g];
@@ -248,6 +251,7 @@ __global__ void __launch_bounds__(256) k_index_scan(Inputs in, const uint32_t* g
   }
   const uint64_t limit = in.size[g] - 48;
   uint32_t cnt = 0, mx = 0;
+  unsigned long long by = 0;
   bool bad = false;
   for (uint32_t k = threadIdx.x; k < nr; k += blockDim.x) {
     const uint64_t o = rd_u32_bytes(c + data_end + 4ull * k);
@@ -265,6 +269,7 @@ __global__ void __launch_bounds__(256) k_index_scan(Inputs in, const uint32_t* g
         return;
       }
       if (bsz > mx) mx = (uint32_t)(bsz > 0xFFFFFFF0ull ? 0xFFFFFFF0ull : bsz);
+      by += bsz + 5;
     });
     uint64_t first_bad = w.err_off < herr ? w.err_off : herr;
     if (first_bad != ~0ull) {
@@ -276,6 +281,7 @@ __global__ void __launch_bounds__(256) k_index_scan(Inputs in, const uint32_t* g
   if (bad) atomicOr(&sflag, 1u);
   atomicAdd(&scount, cnt);
   atomicMax(&smax, mx);
+  atomicAdd(&sbytes, by);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (sflag) {
@@ -284,6 +290,7 @@ __global__ void __launch_bounds__(256) k_index_scan(Inputs in, const uint32_t* g
     } else {
       in.nblk[g] = scount;
       in.maxblk[g] = smax;
+      in.dbytes[g] = sbytes;
     }
   }
 }

@@ -95,6 +95,11 @@ struct luda_ctx {
   size_t event_used = 0;
   std::vector<std::pair<std::string, double>> stage_ms;
   bool timing = false;
+  // hot-kernel timing (always on): begin/end event pairs
+  std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> kmarks;
+  std::vector<hipEvent_t> kevents;
+  size_t kevent_used = 0;
+  std::vector<std::pair<std::string, double>> counters;
 };
 
 namespace {
@@ -169,6 +174,54 @@ void mark(luda_ctx* c, const char* name) {
   hipEvent_t e = c->event_pool[c->event_used++];
   HIPCK(hipEventRecord(e, c->stream));
   c->marks.emplace_back(name, e);
+}
+
+hipEvent_t kevent(luda_ctx* c) {
+  if (c->kevent_used == c->kevents.size()) {
+    hipEvent_t e;
+    HIPCK(hipEventCreate(&e));
+    c->kevents.push_back(e);
+  }
+  return c->kevents[c->kevent_used++];
+}
+
+struct KTimer {
+  luda_ctx* c;
+  const char* name;
+  hipEvent_t b;
+  KTimer(luda_ctx* c_, const char* n) : c(c_), name(n) {
+    b = kevent(c);
+    HIPCK(hipEventRecord(b, c->stream));
+  }
+  ~KTimer() noexcept(false) {
+    hipEvent_t e = kevent(c);
+    HIPCK(hipEventRecord(e, c->stream));
+    c->kmarks.push_back({name, {b, e}});
+  }
+};
+
+void collect_times(luda_ctx* c) {
+  c->stage_ms.clear();
+  if (c->timing && c->marks.size() > 1) {
+    for (size_t i = 1; i < c->marks.size(); i++) {
+      float t = 0;
+      HIPCK(hipEventElapsedTime(&t, c->marks[i - 1].second, c->marks[i].second));
+      c->stage_ms.emplace_back(c->marks[i].first, t);
+    }
+  }
+  for (auto& km : c->kmarks) {
+    float t = 0;
+    HIPCK(hipEventElapsedTime(&t, km.second.first, km.second.second));
+    c->stage_ms.emplace_back(std::string("kernel:") + km.first, t);
+  }
+}
+
+void begin_call(luda_ctx* c) {
+  c->marks.clear();
+  c->event_used = 0;
+  c->kmarks.clear();
+  c->kevent_used = 0;
+  c->counters.clear();
 }
 
 int status_of(uint32_t code) {
@@ -452,6 +505,15 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   sync(c);
   mark(c, "layout");
   O.total_bytes = O.file_out[NF];
+  {
+    uint64_t dout = 0;
+    d2h(c, &dout, ob_excl + NBLK, 1);
+    sync(c);
+    c->counters.emplace_back("data_bytes_out", (double)dout);
+    c->counters.emplace_back("data_blocks_out", (double)NBLK);
+    c->counters.emplace_back("survivors", (double)S);
+    c->counters.emplace_back("files_out", (double)NF);
+  }
   uint8_t* out = (uint8_t*)dbuf<uint8_t>(c, "out_tables", O.total_bytes + 64);
   O.d_out = out;
 
@@ -485,8 +547,11 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     occ = std::max(occ, 1);
     const uint64_t want = (NBLK + waves - 1) / waves;
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
-    hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
-    LAUNCH_CHECK();
+    {
+      KTimer kt(c, "k_encode");
+      hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
+      LAUNCH_CHECK();
+    }
   }
   mark(c, "encode");
   if (NW) {
@@ -511,8 +576,11 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     if ((size_t)F.lds_bytes * waves > budget)
       throw Fail{LUDA_UNSUPPORTED, "filter of " + std::to_string(max_win) + " bytes exceeds the filter kernel's LDS"};
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NW + waves - 1) / waves, (uint64_t)c->n_cu * 8));
-    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
-    LAUNCH_CHECK();
+    {
+      KTimer kt(c, "k_filter");
+      hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
+      LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_filter_offsets, dim3(blocks_for(NW)), dim3(256), 0, st, of, of.w0 + FC, win_file, win_off,
                        NW, out);
     LAUNCH_CHECK();
@@ -543,8 +611,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
   hipStream_t st = c->stream;
-  c->marks.clear();
-  c->event_used = 0;
+  begin_call(c);
   mark(c, "start");
   BatchState B;
   B.hj.resize(J);
@@ -603,12 +670,14 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   in.idx_size = dbuf<uint64_t>(c, "in_idx_size", NG);
   in.nblk = dbuf<uint32_t>(c, "in_nblk", NG);
   in.maxblk = dbuf<uint32_t>(c, "in_maxblk", NG);
+  in.dbytes = dbuf<uint64_t>(c, "in_dbytes", NG);
   unsigned long long* err = dbuf<unsigned long long>(c, "err", J);
   fill_u64(c, err, ERR_NONE, J);
   uint32_t* dev_flags = dbuf<uint32_t>(c, "dev_flags", 4);
   fill_u32(c, dev_flags, 0, 4);
 
   std::vector<uint32_t> nblk(NG), maxblk(NG);
+  std::vector<uint64_t> dbytes;
   std::vector<uint64_t> errs(J, ERR_NONE);
   if (NG) {
     hipLaunchKernelGGL(k_footer, dim3(blocks_for(NG)), dim3(256), 0, st, in, err);
@@ -617,6 +686,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     LAUNCH_CHECK();
     d2h(c, nblk.data(), in.nblk, NG);
     d2h(c, maxblk.data(), in.maxblk, NG);
+    dbytes.resize(NG);
+    d2h(c, dbytes.data(), in.dbytes, NG);
   }
   mark(c, "index");
   sync(c);
@@ -657,6 +728,13 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     LAUNCH_CHECK();
   }
   mark(c, "index_emit");
+  {
+    double db = 0;
+    for (uint32_t g = 0; g < NG; g++)
+      if (nblk[g]) db += (double)dbytes[g];
+    c->counters.emplace_back("data_bytes_in", db);
+    c->counters.emplace_back("data_blocks_in", (double)NB);
+  }
 
   // --- decode (with a retry if the entry capacity was too small)
   uint64_t data_bytes = 0;
@@ -700,6 +778,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       occ = std::max(occ, 1);
       const uint64_t want = (NB + dwaves - 1) / dwaves;
       const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
+      KTimer kt(c, "k_decode");
       hipLaunchKernelGGL(k_decode, dim3(grid), dim3(dwaves * 64), lds, st, A);
       LAUNCH_CHECK();
     }
@@ -714,6 +793,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     if (N <= NCAP) break;
     NCAP = N;
   }
+  c->counters.emplace_back("entries_in", (double)N);
   mark(c, "decode");
   // entry ranges of inputs and jobs
   std::vector<uint32_t> job_b0(J + 1, 0);
@@ -738,8 +818,11 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   int32_t* in_cmp = dbuf<int32_t>(c, "in_cmp", NG);
   fill_u32(c, (uint32_t*)in_cmp, 2u, NG);
   if (N) {
-    hipLaunchKernelGGL(k_keys, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, kw8, N, err);
-    LAUNCH_CHECK();
+    {
+      KTimer kt(c, "k_keys");
+      hipLaunchKernelGGL(k_keys, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, kw8, N, err);
+      LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_order, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, d_in_blk0, kw8, N, in_cmp, err);
     LAUNCH_CHECK();
   }
@@ -823,9 +906,12 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     h2d(c, d_tasks, tiled.data(), tiled.size());
     uint32_t* dst = (ord == ordA) ? ordB : ordA;
     const uint64_t threads = (N + MERGE_ITEMS_PER_THREAD - 1) / MERGE_ITEMS_PER_THREAD;
-    hipLaunchKernelGGL(k_merge, dim3(blocks_for(threads)), dim3(256), 0, st, d_tasks, (uint32_t)tiled.size(), ord,
-                       dst, tu, kw8, N);
-    LAUNCH_CHECK();
+    {
+      KTimer kt(c, "k_merge");
+      hipLaunchKernelGGL(k_merge, dim3(blocks_for(threads)), dim3(256), 0, st, d_tasks, (uint32_t)tiled.size(), ord,
+                         dst, tu, kw8, N);
+      LAUNCH_CHECK();
+    }
     ord = dst;
     rounds++;
     sync(c);  // the task list is reused next round
@@ -946,15 +1032,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     (void)hipFree(dblk->p);
     delete dblk;
   }
-  // collect stage times
-  c->stage_ms.clear();
-  if (c->timing && c->marks.size() > 1) {
-    for (size_t i = 1; i < c->marks.size(); i++) {
-      float t = 0;
-      HIPCK(hipEventElapsedTime(&t, c->marks[i - 1].second, c->marks[i].second));
-      c->stage_ms.emplace_back(c->marks[i].first, t);
-    }
-  }
+  collect_times(c);
 }
 
 }  // namespace
@@ -1027,6 +1105,7 @@ void luda_ctx_destroy(luda_ctx* c) {
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  for (auto e : c->kevents) (void)hipEventDestroy(e);
   if (c->d_crc) (void)hipFree(c->d_crc);
   if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
@@ -1115,8 +1194,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     HIPCK(hipSetDevice(c->device));
     if (n > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "more than 2^32 entries"};
     hipStream_t st = c->stream;
-    c->marks.clear();
-    c->event_used = 0;
+    begin_call(c);
     const auto t0 = std::chrono::steady_clock::now();
     uint32_t* d_max = dbuf<uint32_t>(c, "w_max", 2);
     fill_u32(c, d_max, 0, 2);
@@ -1169,6 +1247,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     PlanOut O;
     plan_and_write(c, P, O);
     sync(c);
+    collect_times(c);
     out->status = LUDA_OK;
     out->entries_in = out->entries_out = n;
     out->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1225,6 +1304,16 @@ int luda_debug_read(luda_ctx* c, const char* name, void* dst, uint64_t offset, u
 }
 
 const char* luda_last_error(luda_ctx* c) { return c ? c->last_error.c_str() : ""; }
+
+int luda_last_counters(luda_ctx* c, const char** names, double* values, int cap) {
+  if (!c) return 0;
+  int n = (int)c->counters.size();
+  for (int i = 0; i < n && i < cap; i++) {
+    if (names) names[i] = c->counters[i].first.c_str();
+    if (values) values[i] = c->counters[i].second;
+  }
+  return n;
+}
 
 int luda_stage_times(luda_ctx* c, const char** names, double* ms, int cap) {
   if (!c) return 0;

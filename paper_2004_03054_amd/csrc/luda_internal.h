@@ -46,6 +46,7 @@ struct Inputs {
   uint64_t* idx_size;
   uint32_t* nblk;        // data blocks listed by the index
   uint32_t* maxblk;      // largest data block (contents + trailer) of the input
+  uint64_t* dbytes;      // bytes of its data blocks, trailers included
   uint32_t n;            // number of inputs
 };
 

@@ -108,3 +108,10 @@ def test_batch_matches_alone():
         assert_same_files(r.files, ref.files, f"batch job {k}")
         alone = ctx().compact(i, j.options())
         assert alone.files == r.files, f"batch job {k}: alone vs batch"
+
+
+# full sizes of the benchmark-class workloads: every output byte compared
+@pytest.mark.parametrize("make,label", [(lambda: config1(), "config1-full"), (lambda: config2(), "config2-full")])
+def test_full_size(make, label):
+    res, ref = run_both(make(), label, device=True)
+    say(f"[gpu] {label}: {len(ref.files)} files, {res.entries_in} entries in, {res.entries_out} out")
