@@ -51,7 +51,14 @@ def device_tables(ctx, job):
 
 
 def kernel_times(ctx):
-    return {k.split(":", 1)[1]: v for k, v in ctx.stage_times() if k.startswith("kernel:")}
+    """Device time of each timed kernel in the last call (launches of the same
+    kernel, e.g. merge rounds, summed)."""
+    out = {}
+    for k, v in ctx.stage_times():
+        if k.startswith("kernel:"):
+            name = k.split(":", 1)[1]
+            out[name] = out.get(name, 0.0) + v
+    return out
 
 
 def main():
@@ -107,12 +114,19 @@ def main():
     names = sorted(set(k for kt in ktimes for k in kt))
     kavg = {n: float(np.mean([kt.get(n, 0.0) for kt in ktimes])) for n in names}
     # roofline of the dominant kernel from its algorithmic bytes:
-    #   k_decode reads every input data block once (contents + trailer)
+    #   k_crc_data reads every input data block once (contents + trailer)
     #   k_encode reads every surviving value once and writes every output
-    #   data block once; both are approximated by their data-block bytes
+    #   data block once (both approximated by the output data-block bytes)
+    #   k_walk_emit writes one 36-byte entry record per input entry
+    #   k_keys reads 16 bytes of record per entry, writes its key slot
+    #   (8 * kw8 bytes) and 28 bytes of sort keys
+    n_in = counters.get("entries_in", 0.0)
+    kw8 = counters.get("kw8", 2.0)
     alg = {
-        "k_decode": counters.get("data_bytes_in", 0.0),
+        "k_crc_data": counters.get("data_bytes_in", 0.0),
         "k_encode": 2.0 * counters.get("data_bytes_out", 0.0),
+        "k_walk_emit": 36.0 * n_in,
+        "k_keys": n_in * (16.0 + 8.0 * kw8 + 28.0),
     }
     dom = max(alg, key=lambda k: kavg.get(k, 0.0))
     achieved = alg[dom] / (kavg[dom] * 1e-3) / 1e9 if kavg.get(dom) else 0.0

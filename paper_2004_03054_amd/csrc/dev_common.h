@@ -170,21 +170,24 @@ __device__ inline uint32_t put_varint(uint8_t* d, uint64_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// CRC32C.  Raw register arithmetic: the register after a message from state
-// 0 is linear in the message bytes, so
+// CRC32C.  Raw register arithmetic (state 0, no final xor) is linear in the
+// message bytes, so
 //   crc32c(M) = raw(M with its first 4 bytes complemented) ^ 0xFFFFFFFF
 // (the all-ones initial value acts like complementing the first 32 message
 // bits), raw(A || B) = shift(raw(A), |B|) ^ raw(B), and leading zero bytes
-// leave raw() unchanged.  Each lane folds a contiguous 68-byte slice of a
-// 4352-byte row with slicing-by-4 tables; slices and rows are joined with
-// precomputed "shift by 68 * 2^k bytes" tables (4 lookups each).
+// leave raw() unchanged.
+//
+// A wave folds a message as 16-byte chunks aligned to the message end: chunk
+// c (c = 0 is the last) covers bytes [n - 16(c+1), n - 16c).  Lane l owns the
+// chunks c = 63 - l + 64 i, so one wave step reads 1 KiB contiguously; each
+// lane keeps a Horner sum over its chunks (shift by 1024 bytes between them)
+// and the lanes are joined by a 6-level tree of shifts by 16 * 2^k bytes.
+// Shifts are four table lookups; long messages are split into segments
+// joined by multiplication with x^(8 len) mod P computed in GF(2).
 
-constexpr uint32_t CRC_SLICE = 68;                    // bytes per lane per row
-constexpr uint32_t CRC_ROW = CRC_SLICE * WAVE;        // 4352 bytes per wave row
-constexpr uint32_t CRC_DW = CRC_SLICE / 4;            // 17 dwords (odd: conflict-free)
+constexpr uint32_t CRC_POLY = 0x82F63B78u;  // CRC32C, reflected
 
-// LDS image of the tables one wave CRC needs: slicing tables + shifts
-// by 68 * 2^k bytes, k = 0..6 (k = 6 is one whole row).
+// LDS image: slicing-by-4 tables and shifts by 16 * 2^k bytes, k = 0..6
 struct CrcLds {
   uint32_t t4[4][256];
   uint32_t sh[7][4][256];
@@ -212,35 +215,123 @@ __device__ inline uint32_t crc_edge(uint32_t d, int64_t p) {
   return (d & keep) ^ flip;
 }
 
-// Wave-cooperative CRC32C of the n-byte message ending at the 4-byte aligned
-// LDS address `end` (n >= 4; at least 4 readable bytes precede the message).
-// Every lane must call; the result is returned to all lanes.
-__device__ inline uint32_t wave_crc_lds(const uint8_t* end, uint32_t n, const CrcLds* T) {
-  const uint32_t l = lane_id();
-  const uint32_t rows = (n + CRC_ROW - 1) / CRC_ROW;
-  uint32_t acc = 0;
-  for (uint32_t r = 0; r < rows; r++) {
-    // this row's slice from state 0, joined as acc * x^(8 * row) ^ slice
-    const int64_t pos0 = (int64_t)n - (int64_t)(rows - r) * CRC_ROW + (int64_t)CRC_SLICE * l;
-    const uint8_t* base = end - (int64_t)(rows - r) * CRC_ROW + CRC_SLICE * l;
-    uint32_t rs = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < CRC_DW; k++) {
-      const int64_t p = pos0 + 4 * k;
-      if (p + 4 <= 0) continue;
-      uint32_t d = *(const uint32_t*)(base + 4 * k);
-      d = crc_edge(d, p);
-      rs = crc_dword(T->t4, rs, d);
-    }
-    acc = (r ? crc_shift(T->sh[6], acc) : 0u) ^ rs;
-  }
-  // join the lanes: lane l's slice is followed by (63 - l) slices
+// raw CRC of one 16-byte chunk held in registers, starting at message
+// position p (bytes before position 0 are ignored)
+__device__ inline uint32_t crc_chunk(const CrcLds* T, uint4 v, int64_t p) {
+  uint32_t r = 0;
+  r = crc_dword(T->t4, r, crc_edge(v.x, p));
+  r = crc_dword(T->t4, r, crc_edge(v.y, p + 4));
+  r = crc_dword(T->t4, r, crc_edge(v.z, p + 8));
+  r = crc_dword(T->t4, r, crc_edge(v.w, p + 12));
+  return r;
+}
+
+// join the per-lane Horner sums: lane l's last chunk is followed by 63 - l
+// chunks.  Returns the raw CRC to every lane.
+__device__ inline uint32_t crc_wave_join(const CrcLds* T, uint32_t acc) {
 #pragma unroll
   for (int k = 0; k < 6; k++) {
     uint32_t other = __shfl_down(acc, 1u << k, WAVE);
     acc = crc_shift(T->sh[k], acc) ^ other;
   }
-  return __shfl(acc, 0, WAVE) ^ 0xFFFFFFFFu;
+  return __shfl(acc, 0, WAVE);
+}
+
+// load the 16 message bytes at positions [p, p + 16) of msg (p + 16 > 0);
+// bytes before position 0 are not read
+__device__ inline uint4 ld_chunk(const uint8_t* msg, int64_t p) {
+  uint4 v;
+  if (p >= 0) {
+    __builtin_memcpy(&v, msg + p, 16);
+    return v;
+  }
+  uint8_t b[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) b[k] = (p + k >= 0) ? msg[p + k] : 0;
+  __builtin_memcpy(&v, b, 16);
+  return v;
+}
+
+// Raw CRC (first 4 message bytes complemented) of message bytes
+// [s0, s0 + len) of a message that starts at msg; len a multiple of 16 or
+// the segment ends at the message end.  Chunks are aligned to the segment
+// end.  Every lane must call.
+__device__ inline uint32_t wave_raw_crc(const CrcLds* T, const uint8_t* msg, int64_t s0, uint64_t len) {
+  const uint32_t l = lane_id();
+  const int64_t send = s0 + (int64_t)len;
+  const uint64_t J = (len + 15) / 16;
+  uint32_t acc = 0;
+  // lane l, chunk c = 63 - l + 64 i, processed from the front (largest c)
+  const int64_t c_first = 63 - (int64_t)l;
+  if ((uint64_t)c_first < J) {
+    int64_t i = ((int64_t)J - 1 - c_first) / 64;
+    for (; i >= 0; i--) {
+      const int64_t c = c_first + 64 * i;
+      const int64_t p = send - 16 * (c + 1);
+      uint4 v = ld_chunk(msg, p < s0 ? p : p);
+      if (p < s0) {
+        // bytes before the segment start belong to another segment
+        uint8_t b[16];
+        __builtin_memcpy(b, &v, 16);
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+          if (p + k < s0) b[k] = 0;
+        __builtin_memcpy(&v, b, 16);
+      }
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p);
+    }
+  }
+  return crc_wave_join(T, acc);
+}
+
+// GF(2) arithmetic mod P in the reflected representation (bit 31 is x^0):
+// the product of a and b reduced mod P.
+__device__ __host__ inline uint32_t gf2_mulmod(uint32_t a, uint32_t b) {
+  uint32_t p = 0;
+  for (int i = 0; i < 32; i++) {
+    if (a & (0x80000000u >> i)) p ^= b;
+    b = (b & 1u) ? (b >> 1) ^ CRC_POLY : (b >> 1);
+  }
+  return p;
+}
+
+// x^(8 n) mod P: the multiplier that shifts a raw CRC over n zero bytes
+__device__ __host__ inline uint32_t gf2_xpow8n(uint64_t n) {
+  uint32_t result = 0x80000000u;  // x^0
+  uint32_t sq = 0x00800000u;      // x^8
+  while (n) {
+    if (n & 1) result = gf2_mulmod(result, sq);
+    sq = gf2_mulmod(sq, sq);
+    n >>= 1;
+  }
+  return result;
+}
+
+// Raw CRC of a whole message of n bytes by one workgroup of 16 waves: wave w
+// folds segment w (segments of L bytes, L a multiple of 16, aligned to the
+// message end; leading segments may start before the message and contribute
+// only their bytes inside it), and the segments are joined by multiplication
+// with x^(8 L) mod P.  Every thread must call; the result is valid in thread 0.
+__device__ inline uint32_t wg16_raw_crc(const CrcLds* T, const uint8_t* msg, uint64_t n, uint32_t* part) {
+  const uint64_t L = (((n + 15) / 16) + 15) / 16 * 16;
+  const uint32_t w = threadIdx.x / WAVE;
+  const int64_t s0 = (int64_t)n - (int64_t)(16 - w) * (int64_t)L;
+  const uint32_t raw = (s0 + (int64_t)L > 0) ? wave_raw_crc(T, msg, s0, L) : 0u;
+  if (lane_id() == 0) part[w] = raw;
+  __syncthreads();
+  uint32_t acc = 0;
+  if (threadIdx.x == 0) {
+    const uint32_t K = gf2_xpow8n(L);
+    for (int q = 0; q < 16; q++) acc = gf2_mulmod(acc, K) ^ part[q];
+  }
+  return acc;
+}
+
+// cooperative load of the global CRC tables into LDS
+__device__ inline void load_crc_tables(CrcLds* dst, const uint32_t* src, int tid, int nthreads) {
+  uint32_t* d = &dst->t4[0][0];
+  const int words = (int)(sizeof(CrcLds) / 4);
+  for (int i = tid; i < words; i += nthreads) d[i] = src[i];
 }
 
 __host__ __device__ inline uint32_t crc_mask(uint32_t c) {
@@ -251,13 +342,6 @@ __host__ __device__ inline uint32_t crc_unmask(uint32_t m) {
   return (r >> 17) | (r << 15);
 }
 
-// cooperative load of the global CRC tables into LDS
-__device__ inline void load_crc_tables(CrcLds* dst, const uint32_t* src, int tid, int nthreads) {
-  const uint32_t* s = src;
-  uint32_t* d = &dst->t4[0][0];
-  const int words = (int)(sizeof(CrcLds) / 4);
-  for (int i = tid; i < words; i += nthreads) d[i] = s[i];
-}
 
 // ---------------------------------------------------------------------------
 // XXH64 (published xxHash XXH64 algorithm), over a zero-padded 8-byte-aligned

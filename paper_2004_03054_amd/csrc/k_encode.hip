@@ -6,97 +6,114 @@
 //
 //   k_encode       one wave per output data block: assembles the block in
 //                  16-byte chunks aligned to the block end (entries, restart
-//                  array, count, type byte), stores it, CRCs it from LDS
+//                  array, count, type byte), stores each chunk and folds it
+//                  into the block's CRC in registers
 //   k_filter       one wave per filter window: Bloom bits in LDS, then stored
 //   k_index_write  one thread per data block: its index entry and restart slot
 //   k_meta         one thread per file: filter tail, metaindex, trailers' type
 //                  bytes, footer
-//   k_crc_ranges   one workgroup per (file, filter | metaindex | index block)
+//   k_crc_ranges   one workgroup of 16 waves per (file, filter | metaindex |
+//                  index block)
 #include "dev_common.h"
 #include "kernels.h"
 
 namespace luda {
 
-// byte p of output block b's message (contents || type byte)
-struct BlockGen {
-  const EncodeArgs* A;
-  uint64_t s0;
-  uint32_t cnt, R;
-  const uint32_t* est;  // entry starts in LDS (cnt + 1 values)
-  uint64_t data_end;
-  uint32_t nrest;
-  uint32_t size;
-  // cursor
-  int32_t ci;  // current entry index (-1: none)
-  uint64_t c_start, c_end;
-  uint32_t c_shared, c_hl, c_ns, c_ulen, c_vlen;
-  uint8_t c_hdr[15];
-  const uint8_t* c_slot;
-  uint64_t c_tag;
-  const uint8_t* c_val;
+__device__ inline uint32_t vlen32(uint32_t v) {
+  return 1u + (v >= (1u << 7)) + (v >= (1u << 14)) + (v >= (1u << 21)) + (v >= (1u << 28));
+}
 
-  __device__ void load_entry(uint32_t i) {
-    ci = (int32_t)i;
-    c_start = est[i];
-    c_end = est[i + 1];
-    const uint64_t s = s0 + i;
-    const bool restart = (i % R) == 0;
-    c_shared = restart ? 0 : A->shr[s];
-    const uint32_t e = A->surv[s];
-    c_ulen = A->tu.ulen[e];
-    const uint32_t klen = c_ulen + 8;
-    c_ns = klen - c_shared;
-    c_vlen = A->tu.vlen[e];
-    c_slot = (const uint8_t*)(A->tu.heap + (uint64_t)e * A->kw8);
-    c_tag = A->tu.tag[e];
-    c_val = (const uint8_t*)A->tu.vp[e];
-    uint32_t h = put_varint(c_hdr, c_shared);
-    h += put_varint(c_hdr + h, c_ns);
-    h += put_varint(c_hdr + h, c_vlen);
-    c_hl = h;
+// byte o of the varint encoding (len bytes) of v
+__device__ inline uint32_t varint_byte(uint32_t v, uint32_t o, uint32_t len) {
+  return ((v >> (7 * o)) & 0x7Fu) | (o + 1 < len ? 0x80u : 0u);
+}
+
+// One 16-byte chunk of block message bytes [p0, p0 + 16) (positions < 0 give
+// zeros), built byte by byte.  i is the window entry holding position
+// max(p0, 0) when that position lies in the entry area.
+__device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t i, int64_t p0, uint32_t data_end, uint32_t size,
+                                uint32_t nrest, uint32_t R, const uint32_t* blk_off, const uint64_t* heap,
+                                uint32_t kw8) {
+  uint32_t st = L->st[i], en = L->st[i + 1], vs = L->vs[i], sh = L->sh[i], ul = L->ul[i];
+  uint32_t ns = ul + 8 - sh;
+  uint32_t la = vlen32(sh), lb = vlen32(ns), lc = vlen32(en - vs);
+  const uint64_t* slot = heap + (uint64_t)L->e[i] * kw8;
+  uint64_t tag = L->tag[i];
+  const uint8_t* vp = (const uint8_t*)L->vp[i];
+  uint64_t lo = 0, hi = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int64_t p = p0 + k;
+    uint32_t byte = 0;
+    if (p >= 0) {
+      if (p < (int64_t)data_end) {
+        if (p >= (int64_t)en) {
+          i++;
+          st = L->st[i];
+          en = L->st[i + 1];
+          vs = L->vs[i];
+          sh = L->sh[i];
+          ul = L->ul[i];
+          ns = ul + 8 - sh;
+          la = vlen32(sh);
+          lb = vlen32(ns);
+          lc = vlen32(en - vs);
+          slot = heap + (uint64_t)L->e[i] * kw8;
+          tag = L->tag[i];
+          vp = (const uint8_t*)L->vp[i];
+        }
+        const uint32_t pp = (uint32_t)p;
+        const uint32_t ks = vs - ns;  // key delta start
+        if (pp < ks) {
+          uint32_t o = pp - st;
+          if (o < la) {
+            byte = varint_byte(sh, o, la);
+          } else if (o < la + lb) {
+            byte = varint_byte(ns, o - la, lb);
+          } else {
+            byte = varint_byte(en - vs, o - la - lb, lc);
+          }
+        } else if (pp < vs) {
+          const uint32_t q = sh + (pp - ks);
+          byte = q < ul ? (uint32_t)(slot[q >> 3] >> (8 * (q & 7))) & 0xFFu : (uint32_t)(tag >> (8 * (q - ul))) & 0xFFu;
+        } else {
+          byte = vp[pp - vs];
+        }
+      } else if (p < (int64_t)data_end + 4ll * nrest) {
+        const uint32_t q = (uint32_t)p - data_end;
+        byte = (blk_off[(uint64_t)(q >> 2) * R] >> (8 * (q & 3))) & 0xFFu;
+      } else if (p < (int64_t)size) {
+        byte = (nrest >> (8 * ((uint32_t)p - data_end - 4 * nrest))) & 0xFFu;
+      }
+    }
+    if (k < 8) lo |= (uint64_t)byte << (8 * k);
+    else hi |= (uint64_t)byte << (8 * (k - 8));
   }
+  uint4 v;
+  v.x = (uint32_t)lo;
+  v.y = (uint32_t)(lo >> 32);
+  v.z = (uint32_t)hi;
+  v.w = (uint32_t)(hi >> 32);
+  return v;
+}
 
-  __device__ uint32_t find_entry(uint64_t p) const {
-    uint32_t lo = 0, hi = cnt;  // est[lo] <= p < est[hi]
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) / 2;
-      if (est[mid] <= p) lo = mid;
-      else hi = mid;
-    }
-    return lo;
-  }
-
-  __device__ uint32_t byte(uint64_t p) {
-    if (p < data_end) {
-      if (ci < 0 || p < c_start || p >= c_end) load_entry(find_entry(p));
-      const uint64_t o = p - c_start;
-      if (o < c_hl) return c_hdr[o];
-      if (o < c_hl + c_ns) return ikey_byte(c_slot, c_ulen, c_tag, c_shared + (uint32_t)(o - c_hl));
-      return c_val[o - c_hl - c_ns];
-    }
-    if (p < data_end + 4ull * nrest) {
-      const uint64_t q = p - data_end;
-      const uint32_t v = est[(q / 4) * R];
-      return (v >> (8 * (q % 4))) & 0xFF;
-    }
-    if (p < (uint64_t)size) {
-      const uint64_t q = p - data_end - 4ull * nrest;
-      return (nrest >> (8 * q)) & 0xFF;
-    }
-    return 0;  // type byte: no compression
-  }
-};
-
-__global__ void __launch_bounds__(256) k_encode(EncodeArgs A) {
+// One wave per output data block.  The block's message (contents || type
+// byte) is produced as 16-byte chunks aligned to its end; lane l produces the
+// chunks c = 63 - l + 64 i (c counted from the end) in increasing position,
+// stores each and folds it into its CRC register (Horner with a shift by
+// 1024 bytes), and the wave joins the 64 registers at the end.  Entry
+// metadata is staged in LDS ENC_W entries at a time; a window after the first
+// starts 8 entries before the previous one ended, so a chunk assigned to a
+// window (by its first byte) never reaches past the window's entries (an
+// entry is at least 4 bytes).
+__global__ void __launch_bounds__(512) k_encode(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   CrcLds* T = (CrcLds*)smem;
   load_crc_tables(T, A.g_crc, threadIdx.x, blockDim.x);
   __syncthreads();
   const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
   const uint32_t waves = blockDim.x / WAVE;
-  uint8_t* wbase = smem + sizeof(CrcLds) + (size_t)wv * (A.stage_bytes + 4ull * A.ent_cap);
-  uint8_t* stage_end = wbase + A.stage_bytes;
-  uint32_t* est = (uint32_t*)stage_end;
+  EncLds* L = (EncLds*)(smem + sizeof(CrcLds)) + wv;
   const uint64_t nb = *A.nblocks;
   for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
     const uint32_t j = A.ob.job[b];
@@ -104,71 +121,78 @@ __global__ void __launch_bounds__(256) k_encode(EncodeArgs A) {
     const uint64_t s0 = A.ob.s0[b];
     const uint32_t cnt = A.ob.cnt[b];
     const uint32_t size = A.ob.size[b];
-    const uint32_t n = size + 1;
-    const uint32_t f = A.ob.file[b];
-    uint8_t* dst = A.out + A.of.out[f] + A.ob.off[b];
-    // entry starts
-    uint32_t running = 0;
-    for (uint32_t i0 = 0; i0 < cnt; i0 += WAVE) {
-      const uint32_t i = i0 + l;
-      uint32_t sz = 0;
-      if (i < cnt) sz = (i % R == 0) ? A.sz_r[s0 + i] : A.sz_n[s0 + i];
-      const uint32_t incl = wave_incl_scan(sz);
-      if (i < cnt) est[i] = running + incl - sz;
-      running += __shfl(incl, WAVE - 1, WAVE);
-    }
-    if (l == 0) est[cnt] = running;
-    wave_sync();
-    BlockGen G;
-    G.A = &A;
-    G.s0 = s0;
-    G.cnt = cnt;
-    G.R = R;
-    G.est = est;
-    G.data_end = running;
-    G.nrest = (cnt + R - 1) / R;
-    G.size = size;
-    G.ci = -1;
-    const uint32_t J16 = (n + 15) / 16;
-    for (uint32_t q = l; q < J16; q += WAVE) {
-      const int64_t p0 = (int64_t)n - 16ll * (J16 - q);
-      uint8_t* sdst = stage_end - 16ull * (J16 - q);
-      uint4 v;
-      bool fast = false;
-      if (p0 >= 0 && (uint64_t)p0 + 16 <= G.data_end) {
-        const uint32_t i = G.find_entry((uint64_t)p0);
-        if (G.ci != (int32_t)i) G.load_entry(i);
-        const uint64_t vstart = G.c_start + G.c_hl + G.c_ns;
-        if ((uint64_t)p0 >= vstart && (uint64_t)p0 + 16 <= G.c_end) {
-          __builtin_memcpy(&v, G.c_val + ((uint64_t)p0 - vstart), 16);
-          fast = true;
+    const uint32_t nrest = (cnt + R - 1) / R;
+    const uint32_t data_end = size - 4 * nrest - 4;
+    const int64_t n = (int64_t)size + 1;
+    uint8_t* dst = A.out + A.of.out[A.ob.file[b]] + A.ob.off[b];
+    const uint32_t* blk_off = A.ent_off + s0;
+    const int64_t J16 = (n + 15) / 16;
+    const int64_t c_first = 63 - (int64_t)l;
+    int64_t cc = c_first < J16 ? c_first + 64 * ((J16 - 1 - c_first) / 64) : -1;
+    uint32_t acc = 0;
+    uint32_t k0 = 0;
+    for (;;) {
+      const uint32_t k1 = min(cnt, k0 + ENC_W);
+      const uint32_t nw = k1 - k0;
+      const bool last = (k1 == cnt);
+      if (l < nw) {
+        const uint32_t i = k0 + l;
+        const uint64_t s = s0 + i;
+        const uint32_t e = A.surv[s];
+        const uint32_t shared = (i % R == 0) ? 0u : A.shr[s];
+        const uint32_t ul = A.tu.ulen[e];
+        const uint32_t vl = A.tu.vlen[e];
+        const uint32_t st = blk_off[i];
+        const uint32_t ns = ul + 8 - shared;
+        L->st[l] = st;
+        L->vs[l] = st + vlen32(shared) + vlen32(ns) + vlen32(vl) + ns;
+        L->e[l] = e;
+        L->sh[l] = shared;
+        L->ul[l] = ul;
+        L->vp[l] = A.tu.vp[e];
+        L->tag[l] = A.tu.tag[e];
+      }
+      if (l == 0) L->st[nw] = last ? data_end : blk_off[k1];
+      wave_sync();
+      const int64_t hi = last ? n : (int64_t)L->st[nw - 8];
+      uint32_t cur = 0;
+      while (cc >= 0) {
+        const int64_t p0 = n - 16 * (cc + 1);
+        const int64_t P = p0 < 0 ? 0 : p0;
+        if (P >= hi) break;
+        // entry holding P: the last with st <= P (from the lane's cursor)
+        uint32_t lo_i = cur, hi_i = nw;
+        while (hi_i - lo_i > 1) {
+          const uint32_t mid = (lo_i + hi_i) >> 1;
+          if ((int64_t)L->st[mid] <= P) lo_i = mid;
+          else hi_i = mid;
         }
-      }
-      if (!fast) {
-        uint8_t tmp[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-          const int64_t p = p0 + k;
-          tmp[k] = p >= 0 ? (uint8_t)G.byte((uint64_t)p) : 0;
+        cur = lo_i;
+        uint4 v;
+        if (p0 >= (int64_t)L->vs[cur] && p0 + 16 <= (int64_t)L->st[cur + 1]) {
+          __builtin_memcpy(&v, (const uint8_t*)L->vp[cur] + (p0 - L->vs[cur]), 16);
+        } else {
+          v = enc_chunk_slow(L, cur, p0, data_end, (uint32_t)size, nrest, R, blk_off, A.tu.heap, A.kw8);
         }
-        __builtin_memcpy(&v, tmp, 16);
+        if (p0 >= 0) {
+          __builtin_memcpy(dst + p0, &v, 16);
+        } else {
+          const uint8_t* vb = (const uint8_t*)&v;
+          for (int k = 0; k < 16; k++)
+            if (p0 + k >= 0) dst[p0 + k] = vb[k];
+        }
+        acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
+        cc -= 64;
       }
-      *(uint4*)sdst = v;
-      if (p0 >= 0) {
-        __builtin_memcpy(dst + p0, &v, 16);
-      } else {
-        const uint8_t* vb = (const uint8_t*)&v;
-        for (int k = 0; k < 16; k++)
-          if (p0 + k >= 0) dst[p0 + k] = vb[k];
-      }
+      wave_sync();
+      if (last) break;
+      k0 = k1 - 8;
     }
-    wave_sync();
-    const uint32_t crc = wave_crc_lds(stage_end, n, T);
+    const uint32_t raw = crc_wave_join(T, acc);
     if (l == 0) {
-      const uint32_t m = crc_mask(crc);
-      for (int k = 0; k < 4; k++) dst[n + k] = (uint8_t)(m >> (8 * k));
+      const uint32_t m = crc_mask(raw ^ 0xFFFFFFFFu);
+      __builtin_memcpy(dst + n, &m, 4);
     }
-    wave_sync();
   }
 }
 
@@ -310,66 +334,32 @@ __global__ void k_meta(OutFiles of, const uint64_t* win_off, const uint64_t* nfi
   for (int k = 0; k < 8; k++) ft[40 + k] = (uint8_t)(TABLE_MAGIC >> (8 * k));
 }
 
-// CRC of filter (kind 0), metaindex (1) and index (2) blocks of each file
-struct CrcLdsWG2 {
-  uint32_t t4[4][256];
-  uint32_t sh[9][4][256];
-};
-
-__device__ inline uint32_t ld_dword_from(const uint8_t* msg, int64_t p) {
-  if (p >= 0) return ldg_u32_unaligned(msg + p);
-  uint32_t v = 0;
-  for (int j = 0; j < 4; j++)
-    if (p + j >= 0) v |= (uint32_t)msg[p + j] << (8 * j);
-  return v;
-}
-
-__global__ void __launch_bounds__(256) k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out,
-                                                    const uint32_t* g_t4, const uint32_t* g_sh) {
-  __shared__ CrcLdsWG2 T;
-  __shared__ uint32_t red[4];
+// CRC of filter (kind 0), metaindex (1) and index (2) blocks of each file:
+// one workgroup of 16 waves per block
+__global__ void __launch_bounds__(1024) k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out,
+                                                     const uint32_t* g_crc) {
+  __shared__ CrcLds T;
+  __shared__ uint32_t part[16];
   const uint64_t f = blockIdx.x / 3;
   const uint32_t kind = blockIdx.x % 3;
   if (f >= cap || f >= *nfiles) return;
-  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&T.t4[0][0])[i] = g_t4[i];
-  for (int i = threadIdx.x; i < 9 * 4 * 256; i += blockDim.x) (&T.sh[0][0][0])[i] = g_sh[i];
+  load_crc_tables(&T, g_crc, threadIdx.x, blockDim.x);
   __syncthreads();
   uint64_t off, size;
-  if (kind == 0) { off = of.filter_off[f]; size = of.filter_size[f]; }
-  else if (kind == 1) { off = of.meta_off[f]; size = of.meta_size[f]; }
-  else { off = of.index_off[f]; size = of.index_size[f]; }
+  if (kind == 0) {
+    off = of.filter_off[f];
+    size = of.filter_size[f];
+  } else if (kind == 1) {
+    off = of.meta_off[f];
+    size = of.meta_size[f];
+  } else {
+    off = of.index_off[f];
+    size = of.index_size[f];
+  }
   uint8_t* msg = out + of.out[f] + off;
   const uint64_t n = size + 1;
-  const uint32_t tid = threadIdx.x;
-  const uint64_t ROW = (uint64_t)CRC_SLICE * 256;
-  const uint64_t rows = (n + ROW - 1) / ROW;
-  uint32_t acc = 0;
-  for (uint64_t r = 0; r < rows; r++) {
-    const int64_t pos0 = (int64_t)n - (int64_t)(rows - r) * (int64_t)ROW + (int64_t)CRC_SLICE * tid;
-    uint32_t rs = 0;
-    for (uint32_t k = 0; k < CRC_DW; k++) {
-      const int64_t p = pos0 + 4 * k;
-      if (p + 4 <= 0) continue;
-      rs = crc_dword(T.t4, rs, crc_edge(ld_dword_from(msg, p), p));
-    }
-    acc = (r ? crc_shift(T.sh[8], acc) : 0u) ^ rs;
-  }
-#pragma unroll
-  for (int k = 0; k < 6; k++) {
-    uint32_t other = __shfl_down(acc, 1u << k, WAVE);
-    acc = crc_shift(T.sh[k], acc) ^ other;
-  }
-  const uint32_t w = tid / WAVE;
-  if (lane_id() == 0) {
-    uint32_t v = acc;
-    for (uint32_t q = w; q < 3; q++) v = crc_shift(T.sh[6], v);
-    red[w] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const uint32_t crc = (red[0] ^ red[1] ^ red[2] ^ red[3]) ^ 0xFFFFFFFFu;
-    put_fixed32(msg + n, crc_mask(crc));
-  }
+  const uint32_t raw = wg16_raw_crc(&T, msg, n, part);
+  if (threadIdx.x == 0) put_fixed32(msg + n, crc_mask(raw ^ 0xFFFFFFFFu));
 }
 
 }  // namespace luda

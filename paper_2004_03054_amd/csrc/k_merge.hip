@@ -137,8 +137,11 @@ __device__ inline T block_excl_scan(T v, T* sh, T* total) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scan_tiles(const T* in, uint64_t n, T* out, T* tile_sums) {
+__global__ void __launch_bounds__(256) k_scan_tiles(const T* in, uint64_t cap, const uint64_t* n_dev, T* out,
+                                                    T* tile_sums) {
   __shared__ T sh[4];
+  const uint64_t n = n_dev ? *n_dev : cap;
+  if ((uint64_t)blockIdx.x * SCAN_TILE >= n && blockIdx.x > 0) return;
   const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER;
   T vals[SCAN_PER];
   T s = 0;
@@ -158,8 +161,10 @@ __global__ void __launch_bounds__(256) k_scan_tiles(const T* in, uint64_t n, T* 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scan_sums(T* tile_sums, uint64_t ntiles, T* total_out) {
+__global__ void __launch_bounds__(256) k_scan_sums(T* tile_sums, uint64_t cap, const uint64_t* n_dev, T* total_out) {
   __shared__ T sh[4];
+  const uint64_t n = n_dev ? *n_dev : cap;
+  const uint64_t ntiles = n ? (n + SCAN_TILE - 1) / SCAN_TILE : 1;
   T carry = 0;
   for (uint64_t b = 0; b < ntiles; b += SCAN_THREADS) {
     const uint64_t i = b + threadIdx.x;
@@ -173,26 +178,29 @@ __global__ void __launch_bounds__(256) k_scan_sums(T* tile_sums, uint64_t ntiles
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scan_add(T* out, uint64_t n, const T* tile_sums, T* total_out) {
+__global__ void __launch_bounds__(256) k_scan_add(T* out, uint64_t cap, const uint64_t* n_dev, const T* tile_sums,
+                                                  T* total_out) {
+  const uint64_t n = n_dev ? *n_dev : cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total_out;
+  if ((uint64_t)blockIdx.x * SCAN_TILE >= n) return;
   const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER;
   const T add = tile_sums[blockIdx.x];
 #pragma unroll
   for (uint32_t k = 0; k < SCAN_PER; k++)
     if (base + k < n) out[base + k] += add;
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total_out;
 }
 
 template <typename T>
-void launch_scan(const T* in, uint64_t n, T* out, T* scratch, hipStream_t st) {
-  // out must hold n + 1 values (out[n] = total); scratch >= ntiles + 1
-  const uint64_t ntiles = n ? (n + SCAN_TILE - 1) / SCAN_TILE : 1;
-  hipLaunchKernelGGL(k_scan_tiles<T>, dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, in, n, out, scratch);
-  hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(SCAN_THREADS), 0, st, scratch, ntiles, scratch + ntiles);
-  hipLaunchKernelGGL(k_scan_add<T>, dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, out, n, scratch,
+void launch_scan(const T* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st) {
+  const uint64_t ntiles = cap ? (cap + SCAN_TILE - 1) / SCAN_TILE : 1;
+  hipLaunchKernelGGL(k_scan_tiles<T>, dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, in, cap, n_dev, out,
+                     scratch);
+  hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(SCAN_THREADS), 0, st, scratch, cap, n_dev, scratch + ntiles);
+  hipLaunchKernelGGL(k_scan_add<T>, dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, out, cap, n_dev, scratch,
                      scratch + ntiles);
 }
 
-template void launch_scan<uint32_t>(const uint32_t*, uint64_t, uint32_t*, uint32_t*, hipStream_t);
-template void launch_scan<uint64_t>(const uint64_t*, uint64_t, uint64_t*, uint64_t*, hipStream_t);
+template void launch_scan<uint32_t>(const uint32_t*, uint64_t, const uint64_t*, uint32_t*, uint32_t*, hipStream_t);
+template void launch_scan<uint64_t>(const uint64_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t*, hipStream_t);
 
 }  // namespace luda

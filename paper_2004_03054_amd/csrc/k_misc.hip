@@ -5,18 +5,37 @@
 
 namespace luda {
 
-__global__ void k_decode_total(Blocks blk, uint64_t* total) {
-  if (blockIdx.x || threadIdx.x) return;
-  *total = blk.n ? blk.e0[blk.n - 1] + blk.ne[blk.n - 1] : 0;
+// gather device values into pinned host memory (one launch per readback)
+__global__ void k_mail(MailSegs m, uint8_t* mail) {
+  const uint32_t s = blockIdx.x;
+  if (s >= m.n) return;
+  const uint8_t* src = (const uint8_t*)m.src[s];
+  uint8_t* dst = mail + m.dst[s];
+  for (uint32_t i = threadIdx.x; i < m.bytes[s]; i += blockDim.x) dst[i] = src[i];
 }
 
-// first decoded entry of every job and every input (J + 1 and NG + 1 values);
-// a job or input without blocks starts where the next one does
-__global__ void k_ranges(Blocks blk, const uint32_t* job_b0, uint32_t J, const uint32_t* in_blk0, uint32_t NG,
-                         uint64_t N, uint64_t* job_e0, uint64_t* in_e0) {
+// scatter host-staged bytes (pinned host memory) to device buffers
+__global__ void k_upload(UpSegs u, const uint8_t* up) {
+  const uint32_t s = blockIdx.x;
+  if (s >= u.n) return;
+  const uint8_t* src = up + u.src[s];
+  uint8_t* dst = (uint8_t*)u.dst[s];
+  const uint32_t nb = u.bytes[s];
+  const uint32_t nw = nb / 8;
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) ((uint64_t*)dst)[i] = ((const uint64_t*)src)[i];
+  for (uint32_t i = nw * 8 + threadIdx.x; i < nb; i += blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_gather_u64(const uint64_t* src, const uint64_t* idx, uint32_t n, uint64_t* out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= J) job_e0[i] = job_b0[i] < blk.n ? blk.e0[job_b0[i]] : N;
-  if (i <= NG) in_e0[i] = in_blk0[i] < blk.n ? blk.e0[in_blk0[i]] : N;
+  if (i < n) out[i] = src[idx[i]];
+}
+
+// first output of each group: out[x] = ient[ibase[blk0_of ? blk0_of[x] : x]]
+__global__ void k_ranges(const uint64_t* ient, const uint64_t* ibase, const uint64_t* blk0_of, uint32_t n,
+                         uint64_t* out) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) out[x] = ient[ibase[blk0_of ? blk0_of[x] : x]];
 }
 
 __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0) {
@@ -25,17 +44,29 @@ __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_
 }
 
 __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats) {
-  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t m0, m1;
+  if (threadIdx.x == 0) {
+    m0 = 0;
+    m1 = 0;
+  }
+  __syncthreads();
+  const uint64_t nb = job_ob0[J];
   uint32_t sz = 0, cn = 0;
-  if (b < cap && b < job_ob0[J]) {
-    sz = ob.size[b];
-    cn = ob.cnt[b];
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb && b < cap;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    sz = max(sz, ob.size[b]);
+    cn = max(cn, ob.cnt[b]);
   }
   sz = wave_max(sz);
   cn = wave_max(cn);
   if (lane_id() == 0) {
-    atomicMax(&stats[0], sz);
-    atomicMax(&stats[1], cn);
+    atomicMax(&m0, sz);
+    atomicMax(&m1, cn);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(&stats[0], m0);
+    atomicMax(&stats[1], m1);
   }
 }
 

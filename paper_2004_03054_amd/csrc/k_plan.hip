@@ -372,7 +372,7 @@ __global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out) {
 
 __global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s, const JobDesc* jobs,
                              const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n,
-                             uint64_t cap, OutBlocks ob) {
+                             uint64_t cap, OutBlocks ob, uint32_t* ent_off) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= cap) return;
   if (b >= job_ob0[J]) {
@@ -389,6 +389,7 @@ __global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* 
   uint64_t E = 0;
   uint32_t r = 0;
   for (uint32_t t = first; t < end; t++) {
+    ent_off[sbase + t] = (uint32_t)E;
     E += (r == 0) ? sz_r[sbase + t] : sz_n[sbase + t];
     if (++r == R) r = 0;
   }
@@ -466,23 +467,27 @@ __global__ void k_win_size(const uint64_t* nwin_total, const uint64_t* file_w0_s
                            OutFiles of, const JobDesc* jobs, const uint32_t* win_keys, uint64_t cap,
                            uint64_t* win_bytes, uint32_t* win_file, uint32_t* max_bytes) {
   const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= cap) return;
-  if (w >= *nwin_total) {
-    win_bytes[w] = 0;
-    return;
+  uint32_t mine = 0;
+  if (w < cap) {
+    if (w >= *nwin_total) {
+      win_bytes[w] = 0;
+    } else {
+      const uint32_t f = find_sorted(file_w0_sorted, nfiles, w);
+      win_file[w] = f;
+      const uint32_t keys = win_keys[w];
+      uint64_t v = 0;
+      if (keys) {
+        const uint64_t bpk = jobs[of.job[f]].bloom_bits_per_key;
+        uint64_t bits = (uint64_t)keys * bpk;
+        if (bits < 64) bits = 64;
+        v = (bits + 7) / 8 + 1;
+      }
+      win_bytes[w] = v;
+      mine = (uint32_t)(v > 0xFFFFFFF0ull ? 0xFFFFFFF0ull : v);
+    }
   }
-  const uint32_t f = find_sorted(file_w0_sorted, nfiles, w);
-  win_file[w] = f;
-  const uint32_t keys = win_keys[w];
-  if (!keys) {
-    win_bytes[w] = 0;
-    return;
-  }
-  const uint64_t bpk = jobs[of.job[f]].bloom_bits_per_key;
-  uint64_t bits = (uint64_t)keys * bpk;
-  if (bits < 64) bits = 64;
-  win_bytes[w] = (bits + 7) / 8 + 1;
-  atomicMax(max_bytes, (uint32_t)((bits + 7) / 8 + 1));
+  mine = wave_max(mine);
+  if (lane_id() == 0 && mine) atomicMax(max_bytes, mine);
 }
 
 // per file: the layout of filter, metaindex and index blocks and the footer

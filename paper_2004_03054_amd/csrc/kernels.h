@@ -53,24 +53,32 @@ struct OutFiles {
 };
 
 // decode
-__global__ void k_footer(Inputs in, unsigned long long* err);
-__global__ void k_index_scan(Inputs in, const uint32_t* g_t4, const uint32_t* g_sh, unsigned long long* err);
-__global__ void k_index_emit(Inputs in, const uint32_t* in_blk0, Blocks blk);
-struct DecodeArgs {
+struct WalkArgs {
+  WalkSet ws;
   Inputs in;
-  Blocks blk;
-  Tuples tu;
-  const uint32_t* g_crc;     // CrcLds image
-  unsigned long long* err;   // per job
-  uint32_t* ticket;
+  const uint8_t* ok;       // block passed its checksum
+  const uint32_t* nr;      // restart count per block
+  const uint64_t* ibase;   // first interval of each block
+  const uint32_t* iblk;    // block of each interval
+  const uint64_t* ni_dev;  // number of intervals
+  uint32_t* icnt;          // count pass: entries per interval
+  const uint64_t* ient;    // emit pass: first output of each interval
+  WalkSet out_blk;         // index emit: the data block table
+  const uint64_t* in_blk0; // index emit: first data block of each input
+  Tuples tu;               // data emit: entry records
   uint32_t* maxklen;
-  uint32_t* dev_flags;
-  uint32_t stage_bytes;      // per wave, multiple of 16
-  uint64_t cap;              // entry record capacity
+  unsigned long long* err;
 };
-__global__ void k_decode(DecodeArgs A);
-__global__ void k_keys(Tuples tu, Blocks blk, Inputs in, uint32_t kw8, uint64_t n, unsigned long long* err);
-__global__ void k_order(Tuples tu, Blocks blk, Inputs in, const uint32_t* in_blk0, uint32_t kw8, uint64_t n,
+__global__ void k_footer(Inputs in, WalkSet idx, unsigned long long* err);
+__global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long long* err);
+__global__ void k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
+                           unsigned long long* bytes_total);
+__global__ void k_crc_big(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err);
+__global__ void k_imap(WalkSet ws, const uint32_t* nr, const uint64_t* ibase, uint32_t* iblk);
+template <int KIND, int MODE>
+__global__ void k_walk(WalkArgs A);
+__global__ void k_keys(Tuples tu, WalkSet ws, Inputs in, uint32_t kw8, const uint64_t* n_dev, unsigned long long* err);
+__global__ void k_order(Tuples tu, WalkSet ws, Inputs in, const uint64_t* in_e0, uint32_t kw8, const uint64_t* n_dev,
                         int32_t* in_cmp, unsigned long long* err);
 
 // merge
@@ -84,8 +92,10 @@ __global__ void k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, cons
                               unsigned long long* shadowed, unsigned long long* tomb, const uint32_t* active);
 __global__ void k_scatter(const uint32_t* ord, const uint32_t* keep, const uint32_t* pos, uint64_t n,
                           uint32_t* surv);
+// exclusive scan of n values (n from the device when n_dev is given; cap
+// bounds it): out[0..n) and out[n] = total.  scratch holds cap/2048 + 2.
 template <typename T>
-void launch_scan(const T* in, uint64_t n, T* out, T* scratch, hipStream_t st);
+void launch_scan(const T* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st);
 constexpr uint32_t MERGE_ITEMS_PER_THREAD = 8;
 
 // plan
@@ -110,7 +120,7 @@ __global__ void k_make_segjobs(const uint64_t* base_excl, const uint32_t* counts
 __global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out);
 __global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s, const JobDesc* jobs,
                              const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n, uint64_t cap,
-                             OutBlocks ob);
+                             OutBlocks ob, uint32_t* ent_off);
 __global__ void k_file_pre(const uint64_t* job_f0, uint32_t J, const uint64_t* job_ob0, const uint32_t* file_first,
                            const uint64_t* ob_excl, uint64_t cap, OutFiles of);
 __global__ void k_block_post(const uint64_t* nfiles_total, OutFiles of, const uint64_t* ob_excl,
@@ -135,9 +145,20 @@ struct EncodeArgs {
   const uint64_t* nblocks;  // device total of output blocks
   uint8_t* out;
   const uint32_t* g_crc;
+  const uint32_t* ent_off;  // each survivor's entry offset inside its block
   uint32_t kw8;
-  uint32_t stage_bytes;     // per wave
-  uint32_t ent_cap;         // entry-start slots per wave
+};
+// entries of one output block held in LDS at a time (per wave)
+constexpr uint32_t ENC_W = 64;
+struct EncLds {
+  uint64_t vp[ENC_W];       // value address
+  uint64_t tag[ENC_W];
+  uint32_t st[ENC_W + 1];   // entry start (block offset); st[n] = end of the last
+  uint32_t vs[ENC_W];       // value start (block offset)
+  uint32_t e[ENC_W];        // decoded entry (key slot)
+  uint32_t sh[ENC_W];       // key bytes shared with the previous entry
+  uint32_t ul[ENC_W];       // user key length
+  uint32_t pad[3];
 };
 __global__ void k_encode(EncodeArgs A);
 struct FilterArgs {
@@ -163,9 +184,23 @@ __global__ void k_meta(OutFiles of, const uint64_t* win_off, const uint64_t* nfi
 __global__ void k_filter_offsets(OutFiles of, const uint64_t* nwin, const uint32_t* win_file,
                                  const uint64_t* win_off, uint64_t cap, uint8_t* out);
 // misc
-__global__ void k_decode_total(Blocks blk, uint64_t* total);
-__global__ void k_ranges(Blocks blk, const uint32_t* job_b0, uint32_t J, const uint32_t* in_blk0, uint32_t NG,
-                         uint64_t N, uint64_t* job_e0, uint64_t* in_e0);
+struct MailSegs {
+  uint64_t src[12];
+  uint32_t bytes[12];
+  uint32_t dst[12];
+  uint32_t n;
+};
+__global__ void k_mail(MailSegs m, uint8_t* mail);
+struct UpSegs {
+  uint64_t dst[16];
+  uint32_t bytes[16];
+  uint32_t src[16];
+  uint32_t n;
+};
+__global__ void k_upload(UpSegs u, const uint8_t* up);
+__global__ void k_gather_u64(const uint64_t* src, const uint64_t* idx, uint32_t n, uint64_t* out);
+__global__ void k_ranges(const uint64_t* ient, const uint64_t* ibase, const uint64_t* blk0_of, uint32_t n,
+                         uint64_t* out);
 __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0);
 __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats);
 __global__ void k_u32_to_u64(const uint32_t* a, uint64_t* b, uint64_t n);
@@ -174,7 +209,6 @@ __global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen)
 __global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,
                          const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv);
 __global__ void k_check_sorted(Tuples tu, uint32_t kw8, uint64_t n, uint32_t* bad);
-__global__ void k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_t4,
-                             const uint32_t* g_sh);
+__global__ void k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc);
 
 }  // namespace luda

@@ -3,8 +3,10 @@
 // One call runs the paper's per-job workflow (Sec. III-A overview: copy the
 // selected tables to the GPU, unpack, sort and drop, pack, return the new
 // tables), for one job or a batch of independent jobs at once.  Every stage
-// is a device kernel; the host only sizes buffers between stages from a few
-// counters it reads back, builds small work lists, and moves bytes.
+// is a device kernel.  Between stages the host only reads a few counters
+// (gathered by one small kernel into pinned memory, then one stream sync),
+// sizes buffers, and builds small work lists (staged in pinned memory and
+// scattered to their device buffers by one kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,12 +26,12 @@ using namespace luda;
 namespace {
 
 // ---------------------------------------------------------------------------
-// CRC32C tables built on the host: slicing-by-4 and "shift by 68 * 2^k bytes"
-// (k = 0..12), each a set of four 256-entry tables indexed by the bytes of
-// the 32-bit register.
+// CRC32C tables built on the host: slicing-by-4 and "shift by 16 * 2^k zero
+// bytes" (k = 0..6), each a set of four 256-entry tables indexed by the bytes
+// of the 32-bit register.  The device copies this image into LDS.
 
 constexpr uint32_t POLY = 0x82F63B78u;  // CRC32C, reflected
-constexpr int NSH = 13;
+constexpr int NSH = 7;
 
 uint32_t step_byte(uint32_t r, uint8_t b, const uint32_t* t0) { return t0[(r ^ b) & 0xFF] ^ (r >> 8); }
 
@@ -37,6 +39,7 @@ struct CrcTables {
   uint32_t t4[4][256];
   uint32_t sh[NSH][4][256];
 };
+constexpr size_t CRC_LDS_BYTES = sizeof(CrcTables);
 
 uint32_t apply_shift(const uint32_t sh[4][256], uint32_t c) {
   return sh[0][c & 0xFF] ^ sh[1][(c >> 8) & 0xFF] ^ sh[2][(c >> 16) & 0xFF] ^ sh[3][c >> 24];
@@ -52,11 +55,11 @@ void build_crc_tables(CrcTables* T) {
   for (int b = 0; b < 256; b++) T->t4[0][b] = t0[b];
   for (int k = 1; k < 4; k++)
     for (int b = 0; b < 256; b++) T->t4[k][b] = (T->t4[k - 1][b] >> 8) ^ t0[T->t4[k - 1][b] & 0xFF];
-  // shift by 68 zero bytes, directly
+  // shift by 16 zero bytes, directly
   for (int i = 0; i < 4; i++)
     for (uint32_t v = 0; v < 256; v++) {
       uint32_t r = v << (8 * i);
-      for (int z = 0; z < 68; z++) r = step_byte(r, 0, t0);
+      for (int z = 0; z < 16; z++) r = step_byte(r, 0, t0);
       T->sh[0][i][v] = r;
     }
   // shift by 2m = shift by m, twice
@@ -66,7 +69,24 @@ void build_crc_tables(CrcTables* T) {
         T->sh[k][i][v] = apply_shift(T->sh[k - 1], apply_shift(T->sh[k - 1], v << (8 * i)));
 }
 
-// ---------------------------------------------------------------------------
+// GF(2) products mod P in the reflected representation, for the self check
+uint32_t h_mulmod(uint32_t a, uint32_t b) {
+  uint32_t p = 0;
+  for (int i = 0; i < 32; i++) {
+    if (a & (0x80000000u >> i)) p ^= b;
+    b = (b & 1u) ? (b >> 1) ^ POLY : (b >> 1);
+  }
+  return p;
+}
+uint32_t h_xpow8n(uint64_t n) {
+  uint32_t result = 0x80000000u, sq = 0x00800000u;
+  while (n) {
+    if (n & 1) result = h_mulmod(result, sq);
+    sq = h_mulmod(sq, sq);
+    n >>= 1;
+  }
+  return result;
+}
 
 struct DBuf {
   void* p = nullptr;
@@ -75,30 +95,31 @@ struct DBuf {
 
 }  // namespace
 
-struct StageMark {
-  const char* name;
-  hipEvent_t ev;
-};
-
 struct luda_ctx {
   int device = 0;
   hipStream_t own = nullptr;
   hipStream_t stream = nullptr;
   uint32_t* d_crc = nullptr;  // CrcTables image
   int n_cu = 256;
-  size_t lds_limit = 64 * 1024;  // dynamic + static LDS per workgroup
+  size_t lds_limit = 64 * 1024;  // LDS per workgroup
   std::string last_error;
   std::map<std::string, DBuf> bufs;
-  // stage timing
+  DBuf spare_out;  // an output buffer returned by luda_result_free, for reuse
+  // pinned host memory: readbacks (written by k_mail) and staged uploads
+  uint8_t* mail = nullptr;
+  size_t mail_cap = 0;
+  uint8_t* stage = nullptr;
+  size_t stage_cap = 0, stage_used = 0;
+  UpSegs up_pending{};
+  // stage timing (LUDA_STAGE_TIMES) and hot-kernel timing (always)
+  bool timing = false;
   std::vector<std::pair<std::string, hipEvent_t>> marks;
   std::vector<hipEvent_t> event_pool;
   size_t event_used = 0;
-  std::vector<std::pair<std::string, double>> stage_ms;
-  bool timing = false;
-  // hot-kernel timing (always on): begin/end event pairs
   std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> kmarks;
   std::vector<hipEvent_t> kevents;
   size_t kevent_used = 0;
+  std::vector<std::pair<std::string, double>> stage_ms;
   std::vector<std::pair<std::string, double>> counters;
 };
 
@@ -118,6 +139,7 @@ struct Fail {
 
 #define LAUNCH_CHECK() HIPCK(hipGetLastError())
 
+// grow-only named device buffers
 template <typename T>
 T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
@@ -138,11 +160,18 @@ T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
   return (T*)b.p;
 }
 
-inline uint32_t blocks_for(uint64_t n, uint32_t t = 256) { return (uint32_t)std::max<uint64_t>(1, (n + t - 1) / t); }
+inline uint32_t blocks_for(uint64_t n, uint32_t t = 256) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + t - 1) / t, 0x7FFFFFFFull));
+}
 
-void fill_u32(luda_ctx* c, uint32_t* p, uint32_t v, uint64_t n) {
+// grid of a grid-stride kernel over at most cap items
+uint32_t stride_grid(const luda_ctx* c, uint64_t cap, uint32_t t = 256) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((cap + t - 1) / t, (uint64_t)c->n_cu * 16));
+}
+
+void fill_u32(luda_ctx* c, void* p, uint32_t v, uint64_t n) {
   if (!n) return;
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, c->stream, p, v, n);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, c->stream, (uint32_t*)p, v, n);
   LAUNCH_CHECK();
 }
 void fill_u64(luda_ctx* c, void* p, uint64_t v, uint64_t n) {
@@ -151,18 +180,70 @@ void fill_u64(luda_ctx* c, void* p, uint64_t v, uint64_t n) {
                      (unsigned long long)v, n);
   LAUNCH_CHECK();
 }
-
-template <typename T>
-void d2h(luda_ctx* c, T* host, const T* dev, size_t count) {
-  if (!count) return;
-  HIPCK(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, c->stream));
-}
-template <typename T>
-void h2d(luda_ctx* c, T* dev, const T* host, size_t count) {
-  if (!count) return;
-  HIPCK(hipMemcpyAsync(dev, host, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
-}
 void sync(luda_ctx* c) { HIPCK(hipStreamSynchronize(c->stream)); }
+
+// --- staged uploads: the bytes are copied into pinned memory now and moved
+// to their device buffers by one kernel at the next flush (stream ordered).
+// The staging area is only reused by the next call, after its final sync.
+void up_flush(luda_ctx* c) {
+  if (!c->up_pending.n) return;
+  hipLaunchKernelGGL(k_upload, dim3(c->up_pending.n), dim3(256), 0, c->stream, c->up_pending,
+                     (const uint8_t*)c->stage);
+  LAUNCH_CHECK();
+  c->up_pending.n = 0;
+}
+
+void up(luda_ctx* c, void* dev, const void* host, size_t bytes) {
+  if (!bytes) return;
+  const size_t off = (c->stage_used + 15) & ~size_t(15);
+  if (off + bytes > c->stage_cap || bytes > 0xFFFFFFFFull) {
+    up_flush(c);
+    HIPCK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return;
+  }
+  memcpy(c->stage + off, host, bytes);
+  c->stage_used = off + bytes;
+  if (c->up_pending.n == 16) up_flush(c);
+  UpSegs& u = c->up_pending;
+  u.dst[u.n] = (uint64_t)(uintptr_t)dev;
+  u.bytes[u.n] = (uint32_t)bytes;
+  u.src[u.n] = (uint32_t)off;
+  u.n++;
+}
+
+// --- readbacks: device ranges gathered into the pinned mailbox by one
+// kernel per 12 ranges, then one stream sync
+struct Mail {
+  luda_ctx* c;
+  std::vector<MailSegs> segs;
+  size_t used = 0;
+  explicit Mail(luda_ctx* c_) : c(c_) { segs.emplace_back(); }
+  template <typename T>
+  const T* add(const T* dev, size_t count) {
+    const size_t bytes = count * sizeof(T);
+    const size_t off = (used + 15) & ~size_t(15);
+    if (off + bytes > c->mail_cap) throw Fail{LUDA_UNSUPPORTED, "readback larger than the pinned mailbox"};
+    used = off + bytes;
+    if (!bytes) return (const T*)(c->mail + off);
+    if (segs.back().n == 12) segs.emplace_back();
+    MailSegs& m = segs.back();
+    m.src[m.n] = (uint64_t)(uintptr_t)dev;
+    m.bytes[m.n] = (uint32_t)bytes;
+    m.dst[m.n] = (uint32_t)off;
+    m.n++;
+    return (const T*)(c->mail + off);
+  }
+  void flush() {
+    up_flush(c);
+    for (auto& m : segs)
+      if (m.n) {
+        hipLaunchKernelGGL(k_mail, dim3(m.n), dim3(256), 0, c->stream, m, c->mail);
+        LAUNCH_CHECK();
+      }
+    sync(c);
+  }
+};
 
 void mark(luda_ctx* c, const char* name) {
   if (!c->timing) return;
@@ -185,6 +266,7 @@ hipEvent_t kevent(luda_ctx* c) {
   return c->kevents[c->kevent_used++];
 }
 
+// HIP events around one hot kernel launch on the context's stream
 struct KTimer {
   luda_ctx* c;
   const char* name;
@@ -193,7 +275,7 @@ struct KTimer {
     b = kevent(c);
     HIPCK(hipEventRecord(b, c->stream));
   }
-  ~KTimer() noexcept(false) {
+  void stop() {
     hipEvent_t e = kevent(c);
     HIPCK(hipEventRecord(e, c->stream));
     c->kmarks.push_back({name, {b, e}});
@@ -222,6 +304,8 @@ void begin_call(luda_ctx* c) {
   c->kmarks.clear();
   c->kevent_used = 0;
   c->counters.clear();
+  c->stage_used = 0;
+  c->up_pending.n = 0;
 }
 
 int status_of(uint32_t code) {
@@ -253,25 +337,6 @@ luda_error decode_err(uint64_t key, const std::vector<uint64_t>& in_size, uint32
   return e;
 }
 
-struct JobIn {
-  std::vector<luda_buf> inputs;
-  luda_options opt;
-};
-
-struct BatchOut {
-  std::vector<luda_result>* results;
-  bool device_out;
-};
-
-// Per-job bookkeeping kept on the host between stages.
-struct HostJob {
-  uint32_t in_first = 0, n_in = 0;
-  uint64_t bytes_in = 0;
-  bool failed = false;
-  uint64_t err_key = ERR_NONE;
-  int status_limit = 0;
-};
-
 int check_opt(const luda_options* o) {
   if (!o || o->block_size == 0 || o->restart_interval == 0 || o->bloom_bits_per_key == 0 ||
       o->target_file_size == 0)
@@ -279,10 +344,12 @@ int check_opt(const luda_options* o) {
   return LUDA_OK;
 }
 
-// Device output buffers are shared by the results of one call and freed
-// when the last of them is released.
+// A device output buffer shared by the results of one call.  The last
+// release hands it back to the context (as the spare output buffer) or frees
+// it.
 struct DevBlock {
   void* p = nullptr;
+  size_t cap = 0;
   int refs = 0;
 };
 
@@ -291,11 +358,30 @@ struct ResultInternal {
   bool host_data = false;
 };
 
-void release_dev(ResultInternal* ri) {
-  if (ri && ri->dev && --ri->dev->refs == 0) {
-    (void)hipFree(ri->dev->p);
-    delete ri->dev;
+void release_dev(luda_ctx* c, ResultInternal* ri) {
+  if (!ri || !ri->dev || --ri->dev->refs > 0) return;
+  DevBlock* d = ri->dev;
+  ri->dev = nullptr;
+  if (c && d->cap > c->spare_out.cap) {
+    if (c->spare_out.p) (void)hipFree(c->spare_out.p);
+    c->spare_out.p = d->p;
+    c->spare_out.cap = d->cap;
+  } else {
+    (void)hipFree(d->p);
   }
+  delete d;
+}
+
+// the output buffer of this call, at least `bytes`; takes the spare buffer
+// when the current one is too small
+uint8_t* out_buffer(luda_ctx* c, size_t bytes) {
+  DBuf& b = c->bufs["out_tables"];
+  if (b.cap < bytes && c->spare_out.cap >= bytes) {
+    if (b.p) HIPCK(hipFree(b.p));
+    b = c->spare_out;
+    c->spare_out = DBuf{};
+  }
+  return dbuf<uint8_t>(c, "out_tables", bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +391,6 @@ void release_dev(ResultInternal* ri) {
 struct PlanIn {
   uint32_t J;
   JobDesc* d_jobs;
-  const std::vector<JobDesc>* jobs;
   Tuples tu;
   uint32_t kw8;
   const uint32_t* d_surv;
@@ -318,7 +403,7 @@ struct PlanOut {
   uint8_t* d_out = nullptr;
   std::vector<uint64_t> file_out;  // nfiles + 1
   std::vector<uint64_t> file_entries;
-  std::vector<uint64_t> job_f0;    // J + 1
+  std::vector<uint64_t> job_f0;  // J + 1
 };
 
 void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
@@ -349,15 +434,17 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     const uint32_t n = (uint32_t)((m + SEG_C - 1) / SEG_C);
     sj[j].nchunks = n;
     sj[j].pad = 0;
-    for (uint32_t q = 0; q < n; q++) ch.push_back(SegChunk{j, q * SEG_C, (uint32_t)std::min<uint64_t>(m, (uint64_t)(q + 1) * SEG_C), 0});
+    for (uint32_t q = 0; q < n; q++)
+      ch.push_back(SegChunk{j, q * SEG_C, (uint32_t)std::min<uint64_t>(m, (uint64_t)(q + 1) * SEG_C), 0});
   }
   const uint32_t nch = (uint32_t)ch.size();
   SegJob* d_sj = dbuf<SegJob>(c, "sj_b", J);
   SegChunk* d_ch = dbuf<SegChunk>(c, "ch_b", nch);
   uint32_t* d_nch = dbuf<uint32_t>(c, "nch_b", 1);
-  h2d(c, d_sj, sj.data(), J);
-  h2d(c, d_ch, ch.data(), nch);
-  h2d(c, d_nch, &nch, 1);
+  up(c, d_sj, sj.data(), J * sizeof(SegJob));
+  up(c, d_ch, ch.data(), nch * sizeof(SegChunk));
+  up(c, d_nch, &nch, sizeof nch);
+  up_flush(c);
   uint32_t* nxt = dbuf<uint32_t>(c, "seg_nxt", S);
   uint32_t* ex = dbuf<uint32_t>(c, "seg_ex", S);
   uint32_t* cnt = dbuf<uint32_t>(c, "seg_cnt", S);
@@ -391,12 +478,13 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   ob.file = dbuf<uint32_t>(c, "ob_file", OB);
   ob.off = dbuf<uint64_t>(c, "ob_off", OB);
   ob.ie_size = dbuf<uint32_t>(c, "ob_ie", OB);
+  uint32_t* ent_off = dbuf<uint32_t>(c, "ent_off", S);
   hipLaunchKernelGGL(k_block_meta, dim3(blocks_for(OB)), dim3(256), 0, st, job_ob0, J, d_sj, P.d_jobs, seg_first,
-                     sz_r, sz_n, OB, ob);
+                     sz_r, sz_n, OB, ob, ent_off);
   LAUNCH_CHECK();
   uint64_t* ob_excl = dbuf<uint64_t>(c, "ob_excl", OB + 1);
   uint64_t* scan_tmp = dbuf<uint64_t>(c, "scan_tmp64", OB / 2048 + 8);
-  launch_scan<uint64_t>(ob.full, OB, ob_excl, scan_tmp, st);
+  launch_scan<uint64_t>(ob.full, OB, nullptr, ob_excl, scan_tmp, st);
   LAUNCH_CHECK();
 
   // --- file cuts over output blocks: chunk list built on the device
@@ -448,22 +536,24 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   hipLaunchKernelGGL(k_file_pre, dim3(blocks_for(FC)), dim3(256), 0, st, job_f0, J, job_ob0, file_first, ob_excl,
                      FC, of);
   LAUNCH_CHECK();
-  launch_scan<uint64_t>(of.nwin, FC, of.w0, scan_tmp, st);
+  launch_scan<uint64_t>(of.nwin, FC, nullptr, of.w0, scan_tmp, st);
   LAUNCH_CHECK();
   // sizes needed to allocate window arrays and the encoder's LDS
   uint32_t* stats = dbuf<uint32_t>(c, "plan_stats", 4);
   fill_u32(c, stats, 0, 4);
-  hipLaunchKernelGGL(k_plan_stats, dim3(blocks_for(OB)), dim3(256), 0, st, ob, job_ob0, J, OB, stats);
+  hipLaunchKernelGGL(k_plan_stats, dim3(stride_grid(c, OB)), dim3(256), 0, st, ob, job_ob0, J, OB, stats);
   LAUNCH_CHECK();
-  uint64_t hv[4];
-  uint32_t hs[4];
-  d2h(c, &hv[0], job_ob0 + J, 1);
-  d2h(c, &hv[1], job_f0 + J, 1);
-  d2h(c, &hv[2], of.w0 + FC, 1);
-  d2h(c, hs, stats, 4);
-  sync(c);
-  const uint64_t NBLK = hv[0], NF = hv[1], NW = hv[2];
-  const uint32_t max_bsize = hs[0], max_bcnt = hs[1];
+  uint64_t NBLK, NF, NW;
+  {
+    Mail m(c);
+    const uint64_t* a = m.add(job_ob0 + J, 1);
+    const uint64_t* b = m.add(job_f0 + J, 1);
+    const uint64_t* w = m.add(of.w0 + FC, 1);
+    m.flush();
+    NBLK = *a;
+    NF = *b;
+    NW = *w;
+  }
 
   uint32_t* win_keys = dbuf<uint32_t>(c, "win_keys", NW);
   uint32_t* win_fb = dbuf<uint32_t>(c, "win_fb", NW);
@@ -481,40 +571,45 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
                      win_keys, NW, win_bytes, win_file, wstat);
   LAUNCH_CHECK();
   uint64_t* scan_tmpw = dbuf<uint64_t>(c, "scan_tmpw", NW / 2048 + 8);
-  launch_scan<uint64_t>(win_bytes, NW, win_off, scan_tmpw, st);
+  launch_scan<uint64_t>(win_bytes, NW, nullptr, win_off, scan_tmpw, st);
   LAUNCH_CHECK();
   uint64_t* ie64 = dbuf<uint64_t>(c, "ie64", NBLK);
   uint64_t* ie_off = dbuf<uint64_t>(c, "ie_off", NBLK + 1);
   hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob.ie_size, ie64, NBLK);
   LAUNCH_CHECK();
-  launch_scan<uint64_t>(ie64, NBLK, ie_off, scan_tmp, st);
+  launch_scan<uint64_t>(ie64, NBLK, nullptr, ie_off, scan_tmp, st);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_file_layout, dim3(blocks_for(NF)), dim3(256), 0, st, job_f0 + J, of, win_off, ie_off, NF);
   LAUNCH_CHECK();
-  launch_scan<uint64_t>(of.size, NF, of.out, scan_tmp, st);
+  launch_scan<uint64_t>(of.size, NF, nullptr, of.out, scan_tmp, st);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, NF);
   LAUNCH_CHECK();
   O.file_out.assign(NF + 1, 0);
   O.file_entries.assign(NF, 0);
   uint32_t max_win = 0;
-  d2h(c, O.file_out.data(), of.out, NF + 1);
-  d2h(c, O.file_entries.data(), of.entries, NF);
-  d2h(c, O.job_f0.data(), job_f0, J + 1);
-  d2h(c, &max_win, wstat, 1);
-  sync(c);
+  uint64_t dout = 0;
+  {
+    Mail m(c);
+    const uint64_t* fo = m.add(of.out, NF + 1);
+    const uint64_t* fe = m.add(of.entries, NF);
+    const uint64_t* jf = m.add(job_f0, J + 1);
+    const uint32_t* mw = m.add(wstat, 1);
+    const uint64_t* dx = m.add(ob_excl + NBLK, 1);
+    m.flush();
+    memcpy(O.file_out.data(), fo, (NF + 1) * 8);
+    memcpy(O.file_entries.data(), fe, NF * 8);
+    memcpy(O.job_f0.data(), jf, (J + 1) * 8);
+    max_win = *mw;
+    dout = *dx;
+  }
   mark(c, "layout");
   O.total_bytes = O.file_out[NF];
-  {
-    uint64_t dout = 0;
-    d2h(c, &dout, ob_excl + NBLK, 1);
-    sync(c);
-    c->counters.emplace_back("data_bytes_out", (double)dout);
-    c->counters.emplace_back("data_blocks_out", (double)NBLK);
-    c->counters.emplace_back("survivors", (double)S);
-    c->counters.emplace_back("files_out", (double)NF);
-  }
-  uint8_t* out = (uint8_t*)dbuf<uint8_t>(c, "out_tables", O.total_bytes + 64);
+  c->counters.emplace_back("data_bytes_out", (double)dout);
+  c->counters.emplace_back("data_blocks_out", (double)NBLK);
+  c->counters.emplace_back("survivors", (double)S);
+  c->counters.emplace_back("files_out", (double)NF);
+  uint8_t* out = out_buffer(c, O.total_bytes + 64);
   O.d_out = out;
 
   // --- writers
@@ -531,27 +626,19 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.nblocks = job_ob0 + J;
     A.out = out;
     A.g_crc = c->d_crc;
+    A.ent_off = ent_off;
     A.kw8 = P.kw8;
-    A.stage_bytes = (uint32_t)(((uint64_t)max_bsize + 1 + 4 + 15 + 15) & ~15ull);
-    A.ent_cap = max_bcnt + 1;
-    const size_t per_wave = A.stage_bytes + 4ull * A.ent_cap;
-    const size_t tables = sizeof(uint32_t) * (4 + 7 * 4) * 256;
-    const size_t budget = c->lds_limit - 2048;
-    int waves = 4;
-    while (waves > 1 && tables + per_wave * waves > budget) waves--;
-    if (tables + per_wave * waves > budget)
-      throw Fail{LUDA_UNSUPPORTED, "output block of " + std::to_string(max_bsize) + " bytes exceeds the encoder's LDS"};
-    const size_t lds = tables + per_wave * waves;
+    const int waves = 8;
+    const size_t lds = CRC_LDS_BYTES + sizeof(EncLds) * waves;
     int occ = 0;
     HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, lds));
     occ = std::max(occ, 1);
     const uint64_t want = (NBLK + waves - 1) / waves;
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
-    {
-      KTimer kt(c, "k_encode");
-      hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
-      LAUNCH_CHECK();
-    }
+    KTimer kt(c, "k_encode");
+    hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
+    LAUNCH_CHECK();
+    kt.stop();
   }
   mark(c, "encode");
   if (NW) {
@@ -575,12 +662,12 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     while (waves > 1 && (size_t)F.lds_bytes * waves > budget) waves--;
     if ((size_t)F.lds_bytes * waves > budget)
       throw Fail{LUDA_UNSUPPORTED, "filter of " + std::to_string(max_win) + " bytes exceeds the filter kernel's LDS"};
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NW + waves - 1) / waves, (uint64_t)c->n_cu * 8));
-    {
-      KTimer kt(c, "k_filter");
-      hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
-      LAUNCH_CHECK();
-    }
+    const uint32_t grid =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NW + waves - 1) / waves, (uint64_t)c->n_cu * 8));
+    KTimer kt(c, "k_filter");
+    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
+    LAUNCH_CHECK();
+    kt.stop();
     hipLaunchKernelGGL(k_filter_offsets, dim3(blocks_for(NW)), dim3(256), 0, st, of, of.w0 + FC, win_file, win_off,
                        NW, out);
     LAUNCH_CHECK();
@@ -591,20 +678,35 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_meta, dim3(blocks_for(NF)), dim3(256), 0, st, of, win_off, job_f0 + J, NF, out);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_crc_ranges, dim3((uint32_t)(3 * NF)), dim3(256), 0, st, of, job_f0 + J, NF, out, c->d_crc,
-                     c->d_crc + 4 * 256);
-  LAUNCH_CHECK();
+  {
+    KTimer kt(c, "k_crc_tables");
+    hipLaunchKernelGGL(k_crc_ranges, dim3((uint32_t)(3 * NF)), dim3(1024), 0, st, of, job_f0 + J, NF, out, c->d_crc);
+    LAUNCH_CHECK();
+    kt.stop();
+  }
   mark(c, "meta");
 }
 
 // ---------------------------------------------------------------------------
 // The compaction pipeline over a batch.
 
-struct BatchState {
-  std::vector<HostJob> hj;
-  std::vector<JobDesc> jd;
-  std::vector<uint64_t> in_ptr, in_size;
-  std::vector<uint32_t> in_job, in_local;
+struct HostJob {
+  uint32_t in_first = 0, n_in = 0;
+  uint64_t bytes_in = 0;
+  bool failed = false;
+  uint64_t err_key = ERR_NONE;
+};
+
+// one pass over a set of blocks: restart counts, checksums, interval map,
+// count walk, and the prefix sums that place every interval's output
+struct WalkPlan {
+  uint32_t* nr;
+  uint64_t* ibase;  // nb + 1
+  uint8_t* ok;
+  uint32_t* iblk;
+  uint32_t* icnt;
+  uint64_t* ient;   // ni + 1
+  uint64_t NI = 0;  // intervals
 };
 
 void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, luda_result* results) {
@@ -613,30 +715,34 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   hipStream_t st = c->stream;
   begin_call(c);
   mark(c, "start");
-  BatchState B;
-  B.hj.resize(J);
-  B.jd.resize(J);
+  std::vector<HostJob> hj(J);
+  std::vector<JobDesc> jd(J);
+  std::vector<uint64_t> in_ptr, in_size, job_in_first(J + 1);
+  std::vector<uint32_t> in_job, in_local;
   uint64_t G = 0, total_in = 0;
   for (uint32_t j = 0; j < J; j++) {
-    B.hj[j].in_first = (uint32_t)G;
-    B.hj[j].n_in = jobs[j].n_inputs;
+    hj[j].in_first = (uint32_t)G;
+    hj[j].n_in = jobs[j].n_inputs;
+    job_in_first[j] = G;
     const luda_options& o = jobs[j].options;
-    B.jd[j] = JobDesc{o.block_size, o.restart_interval, o.bloom_bits_per_key, o.bottommost ? 1u : 0u,
-                      o.target_file_size, (uint32_t)G, jobs[j].n_inputs};
+    jd[j] = JobDesc{o.block_size, o.restart_interval, o.bloom_bits_per_key, o.bottommost ? 1u : 0u,
+                    o.target_file_size, (uint32_t)G, jobs[j].n_inputs};
     for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
-      B.in_size.push_back(jobs[j].inputs[i].size);
-      B.in_job.push_back(j);
-      B.in_local.push_back(i);
-      B.hj[j].bytes_in += jobs[j].inputs[i].size;
+      in_size.push_back(jobs[j].inputs[i].size);
+      in_job.push_back(j);
+      in_local.push_back(i);
+      hj[j].bytes_in += jobs[j].inputs[i].size;
       total_in += (jobs[j].inputs[i].size + 255) & ~255ull;
     }
     G += jobs[j].n_inputs;
   }
+  job_in_first[J] = G;
   if (G > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "too many inputs"};
+  const uint32_t NG = (uint32_t)G;
   // inputs on the device
   if (dev_inputs) {
     for (uint32_t j = 0; j < J; j++)
-      for (uint32_t i = 0; i < jobs[j].n_inputs; i++) B.in_ptr.push_back((uint64_t)(uintptr_t)jobs[j].inputs[i].data);
+      for (uint32_t i = 0; i < jobs[j].n_inputs; i++) in_ptr.push_back((uint64_t)(uintptr_t)jobs[j].inputs[i].data);
   } else {
     uint8_t* arena = dbuf<uint8_t>(c, "in_arena", total_in + 256);
     uint64_t off = 0;
@@ -644,199 +750,271 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
         const luda_buf& b = jobs[j].inputs[i];
         if (b.size) HIPCK(hipMemcpyAsync(arena + off, b.data, b.size, hipMemcpyHostToDevice, st));
-        B.in_ptr.push_back((uint64_t)(uintptr_t)(arena + off));
+        in_ptr.push_back((uint64_t)(uintptr_t)(arena + off));
         off += (b.size + 255) & ~255ull;
       }
   }
   mark(c, "h2d");
-  const uint32_t NG = (uint32_t)G;
   JobDesc* d_jobs = dbuf<JobDesc>(c, "jobs", J);
-  h2d(c, d_jobs, B.jd.data(), J);
   Inputs in;
   in.n = NG;
   uint64_t* d_in_ptr = dbuf<uint64_t>(c, "in_ptr", NG);
   uint64_t* d_in_size = dbuf<uint64_t>(c, "in_size", NG);
   uint32_t* d_in_job = dbuf<uint32_t>(c, "in_job", NG);
   uint32_t* d_in_local = dbuf<uint32_t>(c, "in_local", NG);
-  h2d(c, d_in_ptr, B.in_ptr.data(), NG);
-  h2d(c, d_in_size, B.in_size.data(), NG);
-  h2d(c, d_in_job, B.in_job.data(), NG);
-  h2d(c, d_in_local, B.in_local.data(), NG);
+  uint64_t* d_job_in_first = dbuf<uint64_t>(c, "job_in_first", J + 1);
+  uint64_t* d_ng = dbuf<uint64_t>(c, "n_inputs", 1);
+  up(c, d_jobs, jd.data(), J * sizeof(JobDesc));
+  up(c, d_in_ptr, in_ptr.data(), (size_t)NG * 8);
+  up(c, d_in_size, in_size.data(), (size_t)NG * 8);
+  up(c, d_in_job, in_job.data(), (size_t)NG * 4);
+  up(c, d_in_local, in_local.data(), (size_t)NG * 4);
+  up(c, d_job_in_first, job_in_first.data(), (size_t)(J + 1) * 8);
+  up(c, d_ng, &G, 8);
+  up_flush(c);
   in.ptr = d_in_ptr;
   in.size = d_in_size;
   in.job = d_in_job;
   in.local = d_in_local;
-  in.idx_off = dbuf<uint64_t>(c, "in_idx_off", NG);
-  in.idx_size = dbuf<uint64_t>(c, "in_idx_size", NG);
-  in.nblk = dbuf<uint32_t>(c, "in_nblk", NG);
-  in.maxblk = dbuf<uint32_t>(c, "in_maxblk", NG);
-  in.dbytes = dbuf<uint64_t>(c, "in_dbytes", NG);
   unsigned long long* err = dbuf<unsigned long long>(c, "err", J);
   fill_u64(c, err, ERR_NONE, J);
-  uint32_t* dev_flags = dbuf<uint32_t>(c, "dev_flags", 4);
-  fill_u32(c, dev_flags, 0, 4);
+  unsigned long long* d_bytes = dbuf<unsigned long long>(c, "data_bytes", 1);
+  fill_u64(c, d_bytes, 0, 1);
+  uint32_t* d_maxk = dbuf<uint32_t>(c, "maxklen", 1);
+  fill_u32(c, d_maxk, 0, 1);
 
-  std::vector<uint32_t> nblk(NG), maxblk(NG);
-  std::vector<uint64_t> dbytes;
-  std::vector<uint64_t> errs(J, ERR_NONE);
+  WalkArgs WA;
+  memset(&WA, 0, sizeof WA);
+  WA.in = in;
+  WA.err = err;
+
+  // --- index blocks (one per input): footer, restart counts, checksums
+  WalkSet ix;
+  ix.ptr = dbuf<uint64_t>(c, "ix_ptr", NG);
+  ix.size = dbuf<uint32_t>(c, "ix_size", NG);
+  ix.input = dbuf<uint32_t>(c, "ix_input", NG);
+  ix.local = dbuf<uint32_t>(c, "ix_local", NG);
+  ix.skip = dbuf<uint8_t>(c, "ix_skip", NG);
+  ix.n_dev = d_ng;
+  ix.where = W_INDEX;
+  WalkPlan IX;
+  IX.nr = dbuf<uint32_t>(c, "ix_nr", NG);
+  IX.ibase = dbuf<uint64_t>(c, "ix_ibase", (uint64_t)NG + 1);
+  IX.ok = dbuf<uint8_t>(c, "ix_ok", NG);
+  uint64_t* nr64 = dbuf<uint64_t>(c, "nr64", NG);
   if (NG) {
-    hipLaunchKernelGGL(k_footer, dim3(blocks_for(NG)), dim3(256), 0, st, in, err);
+    hipLaunchKernelGGL(k_footer, dim3(blocks_for(NG)), dim3(256), 0, st, in, ix, err);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_index_scan, dim3(NG), dim3(256), 0, st, in, c->d_crc, c->d_crc + 4 * 256, err);
+    hipLaunchKernelGGL(k_blk_nr, dim3(blocks_for(NG)), dim3(256), 0, st, ix, in, IX.nr, err);
     LAUNCH_CHECK();
-    d2h(c, nblk.data(), in.nblk, NG);
-    d2h(c, maxblk.data(), in.maxblk, NG);
-    dbytes.resize(NG);
-    d2h(c, dbytes.data(), in.dbytes, NG);
+    hipLaunchKernelGGL(k_crc_big, dim3(NG), dim3(1024), 0, st, ix, in, c->d_crc, IX.ok, err);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NG)), dim3(256), 0, st, IX.nr, nr64, (uint64_t)NG);
+    LAUNCH_CHECK();
+    uint64_t* scan_g = dbuf<uint64_t>(c, "scan_tmp_g", NG / 2048 + 8);
+    launch_scan<uint64_t>(nr64, NG, nullptr, IX.ibase, scan_g, st);
+    LAUNCH_CHECK();
+    Mail m(c);
+    const uint64_t* p = m.add(IX.ibase + NG, 1);
+    m.flush();
+    IX.NI = *p;
+  } else {
+    fill_u64(c, IX.ibase, 0, 1);
   }
-  mark(c, "index");
-  sync(c);
-  // flat block table
-  std::vector<uint32_t> in_blk0(NG + 1, 0);
+  // index intervals: count data block handles, place them
+  IX.iblk = dbuf<uint32_t>(c, "ix_iblk", IX.NI);
+  IX.icnt = dbuf<uint32_t>(c, "ix_icnt", IX.NI);
+  IX.ient = dbuf<uint64_t>(c, "ix_ient", IX.NI + 1);
   uint64_t NB = 0;
-  uint32_t max_block = 0;
-  const size_t crc_lds_b = sizeof(uint32_t) * (4 + 7 * 4) * 256;
-  const uint32_t kMaxStage = (uint32_t)(c->lds_limit - 2048 - crc_lds_b);
-  for (uint32_t g = 0; g < NG; g++) {
-    if (maxblk[g] + 1 + 4 + 32 > kMaxStage) {
-      // blocks too large for the decoder's LDS stage: the job fails with a
-      // size limit at this input's first block
-      const uint32_t j = B.in_job[g];
-      B.hj[j].status_limit = 1;
-      nblk[g] = 0;
-    }
-    in_blk0[g] = (uint32_t)NB;
-    NB += nblk[g];
-    max_block = std::max(max_block, nblk[g] ? maxblk[g] : 0u);
+  WA.ws = ix;
+  WA.ok = IX.ok;
+  WA.nr = IX.nr;
+  WA.ibase = IX.ibase;
+  WA.iblk = IX.iblk;
+  WA.ni_dev = IX.ibase + NG;
+  WA.icnt = IX.icnt;
+  WA.maxklen = d_maxk;
+  if (IX.NI) {
+    hipLaunchKernelGGL(k_imap, dim3(blocks_for(NG)), dim3(256), 0, st, ix, IX.nr, IX.ibase, IX.iblk);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_walk<0, 0>), dim3(stride_grid(c, IX.NI)), dim3(256), 0, st, WA);
+    LAUNCH_CHECK();
+    uint64_t* c64 = dbuf<uint64_t>(c, "icnt64", IX.NI);
+    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(IX.NI)), dim3(256), 0, st, IX.icnt, c64, IX.NI);
+    LAUNCH_CHECK();
+    uint64_t* scan_i = dbuf<uint64_t>(c, "scan_tmp_i", IX.NI / 2048 + 8);
+    launch_scan<uint64_t>(c64, IX.NI, nullptr, IX.ient, scan_i, st);
+    LAUNCH_CHECK();
+    Mail m(c);
+    const uint64_t* p = m.add(IX.ient + IX.NI, 1);
+    m.flush();
+    NB = *p;
+  } else {
+    fill_u64(c, IX.ient, 0, 1);
   }
-  in_blk0[NG] = (uint32_t)NB;
   if (NB > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "too many data blocks"};
-  uint32_t* d_in_blk0 = dbuf<uint32_t>(c, "in_blk0", NG + 1);
-  h2d(c, d_in_blk0, in_blk0.data(), NG + 1);
-  h2d(c, in.nblk, nblk.data(), NG);
-  Blocks blk;
-  blk.n = (uint32_t)NB;
-  blk.off = dbuf<uint64_t>(c, "blk_off", NB);
-  blk.size = dbuf<uint32_t>(c, "blk_size", NB);
-  blk.input = dbuf<uint32_t>(c, "blk_input", NB);
-  blk.local = dbuf<uint32_t>(c, "blk_local", NB);
-  blk.e0 = dbuf<uint64_t>(c, "blk_e0", NB + 1);
-  blk.ne = dbuf<uint32_t>(c, "blk_ne", NB);
-  blk.look = dbuf<unsigned long long>(c, "blk_look", NB);
-  if (NG) {
-    hipLaunchKernelGGL(k_index_emit, dim3(NG), dim3(256), 0, st, in, d_in_blk0, blk);
+  mark(c, "index");
+
+  // --- data block table from the index entries
+  WalkSet db;
+  db.ptr = dbuf<uint64_t>(c, "db_ptr", NB);
+  db.size = dbuf<uint32_t>(c, "db_size", NB);
+  db.input = dbuf<uint32_t>(c, "db_input", NB);
+  db.local = dbuf<uint32_t>(c, "db_local", NB);
+  db.skip = dbuf<uint8_t>(c, "db_skip", NB);
+  db.n_dev = IX.ient + IX.NI;
+  db.where = W_DATA;
+  // first data block of each input: the first output of its index block
+  uint64_t* in_blk0 = dbuf<uint64_t>(c, "in_blk0", (uint64_t)NG + 1);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for((uint64_t)NG + 1)), dim3(256), 0, st, IX.ient, IX.ibase, nullptr,
+                     NG + 1, in_blk0);
+  LAUNCH_CHECK();
+  if (IX.NI) {
+    WA.ient = IX.ient;
+    WA.out_blk = db;
+    WA.in_blk0 = in_blk0;
+    hipLaunchKernelGGL((k_walk<0, 1>), dim3(stride_grid(c, IX.NI)), dim3(256), 0, st, WA);
     LAUNCH_CHECK();
   }
-  mark(c, "index_emit");
-  {
-    double db = 0;
-    for (uint32_t g = 0; g < NG; g++)
-      if (nblk[g]) db += (double)dbytes[g];
-    c->counters.emplace_back("data_bytes_in", db);
-    c->counters.emplace_back("data_blocks_in", (double)NB);
-  }
 
-  // --- decode (with a retry if the entry capacity was too small)
-  uint64_t data_bytes = 0;
-  for (uint32_t g = 0; g < NG; g++) data_bytes += B.in_size[g];
-  uint64_t NCAP = std::max<uint64_t>(1024, data_bytes / 16 + 2 * NB);
+  // --- data blocks: restart counts, checksums, count walk
+  WalkPlan DB;
+  DB.nr = dbuf<uint32_t>(c, "db_nr", NB);
+  DB.ibase = dbuf<uint64_t>(c, "db_ibase", NB + 1);
+  DB.ok = dbuf<uint8_t>(c, "db_ok", NB);
+  if (NB) {
+    hipLaunchKernelGGL(k_blk_nr, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, in, DB.nr, err);
+    LAUNCH_CHECK();
+    uint64_t* nrb64 = dbuf<uint64_t>(c, "db_nr64", NB);
+    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NB)), dim3(256), 0, st, DB.nr, nrb64, NB);
+    LAUNCH_CHECK();
+    uint64_t* scan_b = dbuf<uint64_t>(c, "scan_tmp_b", NB / 2048 + 8);
+    launch_scan<uint64_t>(nrb64, NB, nullptr, DB.ibase, scan_b, st);
+    LAUNCH_CHECK();
+    {
+      int occ = 0;
+      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_crc_wave, 512, 0));
+      occ = std::max(occ, 1);
+      const uint32_t grid =
+          (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NB + 7) / 8, (uint64_t)c->n_cu * occ));
+      KTimer kt(c, "k_crc_data");
+      hipLaunchKernelGGL(k_crc_wave, dim3(grid), dim3(512), 0, st, db, in, c->d_crc, DB.ok, err, d_bytes);
+      LAUNCH_CHECK();
+      kt.stop();
+    }
+    Mail m(c);
+    const uint64_t* p = m.add(DB.ibase + NB, 1);
+    const unsigned long long* by = m.add(d_bytes, 1);
+    m.flush();
+    DB.NI = *p;
+    c->counters.emplace_back("data_bytes_in", (double)*by);
+  } else {
+    fill_u64(c, DB.ibase, 0, 1);
+    c->counters.emplace_back("data_bytes_in", 0.0);
+  }
+  c->counters.emplace_back("data_blocks_in", (double)NB);
+  mark(c, "data_crc");
+  DB.iblk = dbuf<uint32_t>(c, "db_iblk", DB.NI);
+  DB.icnt = dbuf<uint32_t>(c, "db_icnt", DB.NI);
+  DB.ient = dbuf<uint64_t>(c, "db_ient", DB.NI + 1);
+  WA.ws = db;
+  WA.ok = DB.ok;
+  WA.nr = DB.nr;
+  WA.ibase = DB.ibase;
+  WA.iblk = DB.iblk;
+  WA.ni_dev = DB.ibase + NB;
+  WA.icnt = DB.icnt;
+  WA.ient = DB.ient;
   uint64_t N = 0;
   uint32_t maxklen = 0;
-  Tuples tu;
-  const uint32_t stage = (uint32_t)(((uint64_t)max_block + 1 + 4 + 15 + 15) & ~15ull);
-  const size_t crc_lds = sizeof(uint32_t) * (4 + 7 * 4) * 256;
-  int dwaves = 8;
-  while (dwaves > 1 && crc_lds + (size_t)stage * dwaves > c->lds_limit - 2048) dwaves--;
-  for (int attempt = 0; attempt < 2; attempt++) {
-    tu.kd = dbuf<uint64_t>(c, "tu_kd", NCAP);
-    tu.sn = dbuf<uint64_t>(c, "tu_sn", NCAP);
-    tu.vp = dbuf<uint64_t>(c, "tu_vp", NCAP);
-    tu.vlen = dbuf<uint32_t>(c, "tu_vlen", NCAP);
-    tu.blk = dbuf<uint32_t>(c, "tu_blk", NCAP);
-    tu.eoff = dbuf<uint32_t>(c, "tu_eoff", NCAP);
-    uint32_t* ticket = dbuf<uint32_t>(c, "ticket", 1);
-    uint32_t* d_maxk = dbuf<uint32_t>(c, "maxklen", 1);
-    uint64_t* d_tot = dbuf<uint64_t>(c, "dec_total", 1);
-    fill_u32(c, ticket, 0, 1);
-    fill_u32(c, d_maxk, 0, 1);
-    fill_u64(c, blk.look, 0, NB);
-    if (NB) {
-      DecodeArgs A;
-      A.in = in;
-      A.blk = blk;
-      A.tu = tu;
-      A.g_crc = c->d_crc;
-      A.err = err;
-      A.ticket = ticket;
-      A.maxklen = d_maxk;
-      A.dev_flags = dev_flags;
-      A.stage_bytes = stage;
-      A.cap = NCAP;
-      const size_t lds = crc_lds + (size_t)stage * dwaves;
-      int occ = 0;
-      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_decode, dwaves * 64, lds));
-      occ = std::max(occ, 1);
-      const uint64_t want = (NB + dwaves - 1) / dwaves;
-      const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
-      KTimer kt(c, "k_decode");
-      hipLaunchKernelGGL(k_decode, dim3(grid), dim3(dwaves * 64), lds, st, A);
-      LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_decode_total, dim3(1), dim3(64), 0, st, blk, d_tot);
+  if (DB.NI) {
+    hipLaunchKernelGGL(k_imap, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, DB.nr, DB.ibase, DB.iblk);
     LAUNCH_CHECK();
-    uint32_t fl[4];
-    d2h(c, &N, d_tot, 1);
-    d2h(c, &maxklen, d_maxk, 1);
-    d2h(c, fl, dev_flags, 4);
-    sync(c);
-    if (fl[0]) throw Fail{LUDA_DEVICE, "decode look-back wait gave up"};
-    if (N <= NCAP) break;
-    NCAP = N;
+    {
+      KTimer kt(c, "k_walk_count");
+      hipLaunchKernelGGL((k_walk<1, 0>), dim3(stride_grid(c, DB.NI)), dim3(256), 0, st, WA);
+      LAUNCH_CHECK();
+      kt.stop();
+    }
+    uint64_t* c64 = dbuf<uint64_t>(c, "icnt64", DB.NI);
+    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(DB.NI)), dim3(256), 0, st, DB.icnt, c64, DB.NI);
+    LAUNCH_CHECK();
+    uint64_t* scan_e = dbuf<uint64_t>(c, "scan_tmp_e", DB.NI / 2048 + 8);
+    launch_scan<uint64_t>(c64, DB.NI, nullptr, DB.ient, scan_e, st);
+    LAUNCH_CHECK();
+    Mail m(c);
+    const uint64_t* p = m.add(DB.ient + DB.NI, 1);
+    const uint32_t* mk = m.add(d_maxk, 1);
+    m.flush();
+    N = *p;
+    maxklen = *mk;
+  } else {
+    fill_u64(c, DB.ient, 0, 1);
   }
+  if (N > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "more than 2^32 entries in one call"};
   c->counters.emplace_back("entries_in", (double)N);
-  mark(c, "decode");
-  // entry ranges of inputs and jobs
-  std::vector<uint32_t> job_b0(J + 1, 0);
-  for (uint32_t j = 0; j < J; j++) job_b0[j] = in_blk0[B.hj[j].in_first];
-  job_b0[J] = (uint32_t)NB;
-  uint32_t* d_job_b0 = dbuf<uint32_t>(c, "job_b0", J + 1);
-  h2d(c, d_job_b0, job_b0.data(), J + 1);
-  uint64_t* d_job_e0 = dbuf<uint64_t>(c, "job_e0", J + 1);
-  uint64_t* d_in_e0 = dbuf<uint64_t>(c, "in_e0", NG + 1);
-  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(std::max<uint64_t>(J, NG) + 1)), dim3(256), 0, st, blk, d_job_b0, J,
-                     d_in_blk0, NG, N, d_job_e0, d_in_e0);
-  LAUNCH_CHECK();
-  // keys
   const uint32_t ulen_max = maxklen > 8 ? maxklen - 8 : 0;
   const uint32_t kw8 = std::max<uint32_t>(2, (ulen_max + 7) / 8);
+  c->counters.emplace_back("kw8", (double)kw8);
   if ((double)N * kw8 * 8 > 64e9) throw Fail{LUDA_UNSUPPORTED, "key slots would exceed 64 GB"};
+  Tuples tu;
+  tu.kd = dbuf<uint64_t>(c, "tu_kd", N);
+  tu.sn = dbuf<uint64_t>(c, "tu_sn", N);
+  tu.vp = dbuf<uint64_t>(c, "tu_vp", N);
+  tu.vlen = dbuf<uint32_t>(c, "tu_vlen", N);
+  tu.blk = dbuf<uint32_t>(c, "tu_blk", N);
+  tu.eoff = dbuf<uint32_t>(c, "tu_eoff", N);
   tu.kp0 = dbuf<uint64_t>(c, "tu_kp0", N);
   tu.kp1 = dbuf<uint64_t>(c, "tu_kp1", N);
   tu.tag = dbuf<uint64_t>(c, "tu_tag", N);
   tu.ulen = dbuf<uint32_t>(c, "tu_ulen", N);
   tu.heap = dbuf<uint64_t>(c, "tu_heap", N * kw8);
+  const uint64_t* d_n = DB.ient + DB.NI;
+  // entry ranges of inputs and jobs
+  uint64_t* in_e0 = dbuf<uint64_t>(c, "in_e0", (uint64_t)NG + 1);
+  uint64_t* job_e0d = dbuf<uint64_t>(c, "job_e0", J + 1);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for((uint64_t)NG + 1)), dim3(256), 0, st, DB.ient, DB.ibase, in_blk0,
+                     NG + 1, in_e0);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gather_u64, dim3(blocks_for(J + 1)), dim3(256), 0, st, in_e0, d_job_in_first, J + 1, job_e0d);
+  LAUNCH_CHECK();
   int32_t* in_cmp = dbuf<int32_t>(c, "in_cmp", NG);
-  fill_u32(c, (uint32_t*)in_cmp, 2u, NG);
+  fill_u32(c, in_cmp, 2u, NG);
   if (N) {
+    WA.tu = tu;
+    {
+      KTimer kt(c, "k_walk_emit");
+      hipLaunchKernelGGL((k_walk<1, 1>), dim3(stride_grid(c, DB.NI)), dim3(256), 0, st, WA);
+      LAUNCH_CHECK();
+      kt.stop();
+    }
     {
       KTimer kt(c, "k_keys");
-      hipLaunchKernelGGL(k_keys, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, kw8, N, err);
+      hipLaunchKernelGGL(k_keys, dim3(stride_grid(c, N)), dim3(256), 0, st, tu, db, in, kw8, d_n, err);
       LAUNCH_CHECK();
+      kt.stop();
     }
-    hipLaunchKernelGGL(k_order, dim3(blocks_for(N)), dim3(256), 0, st, tu, blk, in, d_in_blk0, kw8, N, in_cmp, err);
+    hipLaunchKernelGGL(k_order, dim3(stride_grid(c, N)), dim3(256), 0, st, tu, db, in, in_e0, kw8, d_n, in_cmp, err);
     LAUNCH_CHECK();
   }
   std::vector<int32_t> h_cmp(NG);
-  std::vector<uint64_t> job_e0(J + 1), in_e0(NG + 1);
-  d2h(c, h_cmp.data(), in_cmp, NG);
-  d2h(c, job_e0.data(), d_job_e0, J + 1);
-  d2h(c, in_e0.data(), d_in_e0, NG + 1);
-  d2h(c, errs.data(), (uint64_t*)err, J);
-  sync(c);
+  std::vector<uint64_t> job_e0(J + 1), in_e0h((size_t)NG + 1), errs(J);
+  {
+    Mail m(c);
+    const int32_t* a = m.add(in_cmp, NG);
+    const uint64_t* b = m.add(job_e0d, J + 1);
+    const uint64_t* d = m.add(in_e0, (size_t)NG + 1);
+    const uint64_t* e = m.add((const uint64_t*)err, J);
+    m.flush();
+    memcpy(h_cmp.data(), a, (size_t)NG * 4);
+    memcpy(job_e0.data(), b, (size_t)(J + 1) * 8);
+    memcpy(in_e0h.data(), d, ((size_t)NG + 1) * 8);
+    memcpy(errs.data(), e, (size_t)J * 8);
+  }
   mark(c, "keys");
   for (uint32_t j = 0; j < J; j++) {
-    B.hj[j].err_key = errs[j];
-    B.hj[j].failed = errs[j] != ERR_NONE || B.hj[j].status_limit;
+    hj[j].err_key = errs[j];
+    hj[j].failed = errs[j] != ERR_NONE;
   }
 
   // --- merge rounds: runs are maximal stretches of consecutive inputs where
@@ -847,13 +1025,13 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   std::vector<std::vector<Run>> runs(J);
   bool need_merge = false;
   for (uint32_t j = 0; j < J; j++) {
-    if (B.hj[j].failed) {
-      runs[j].push_back(Run{job_e0[j], job_e0[j + 1] - job_e0[j]});
+    if (hj[j].failed) {
+      if (job_e0[j + 1] > job_e0[j]) runs[j].push_back(Run{job_e0[j], job_e0[j + 1] - job_e0[j]});
       continue;
     }
-    for (uint32_t i = 0; i < B.hj[j].n_in; i++) {
-      const uint32_t g = B.hj[j].in_first + i;
-      const uint64_t a = in_e0[g], n = in_e0[g + 1] - in_e0[g];
+    for (uint32_t i = 0; i < hj[j].n_in; i++) {
+      const uint32_t g = hj[j].in_first + i;
+      const uint64_t a = in_e0h[g], n = in_e0h[g + 1] - in_e0h[g];
       if (!n) continue;
       if (!runs[j].empty() && h_cmp[g] == -1 && runs[j].back().a + runs[j].back().n == a) runs[j].back().n += n;
       else runs[j].push_back(Run{a, n});
@@ -867,7 +1045,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     LAUNCH_CHECK();
   }
   uint32_t* ord = ordA;
-  int rounds = 0;
+  int round = 0;
   while (need_merge) {
     std::vector<MergeTask> tasks;
     need_merge = false;
@@ -884,14 +1062,10 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
           next.push_back(rs[k]);
         }
       }
-      if (rs.empty() && job_e0[j + 1] > job_e0[j]) {
-        tasks.push_back(MergeTask{(uint32_t)job_e0[j], (uint32_t)(job_e0[j + 1] - job_e0[j]), 0, 0, job_e0[j]});
-        next.push_back(Run{job_e0[j], job_e0[j + 1] - job_e0[j]});
-      }
       runs[j] = next;
       if (runs[j].size() > 1) need_merge = true;
     }
-    // tasks must tile [0, N) in order
+    // the tasks must tile [0, N) in order
     std::sort(tasks.begin(), tasks.end(), [](const MergeTask& x, const MergeTask& y) { return x.out0 < y.out0; });
     std::vector<MergeTask> tiled;
     uint64_t pos = 0;
@@ -902,19 +1076,18 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       pos = t.out0 + t.la + t.lb;
     }
     if (pos < N) tiled.push_back(MergeTask{(uint32_t)pos, (uint32_t)(N - pos), 0, 0, pos});
-    MergeTask* d_tasks = dbuf<MergeTask>(c, "merge_tasks", tiled.size());
-    h2d(c, d_tasks, tiled.data(), tiled.size());
+    MergeTask* d_tasks = dbuf<MergeTask>(c, "merge_tasks" + std::to_string(round), tiled.size());
+    up(c, d_tasks, tiled.data(), tiled.size() * sizeof(MergeTask));
+    up_flush(c);
     uint32_t* dst = (ord == ordA) ? ordB : ordA;
     const uint64_t threads = (N + MERGE_ITEMS_PER_THREAD - 1) / MERGE_ITEMS_PER_THREAD;
-    {
-      KTimer kt(c, "k_merge");
-      hipLaunchKernelGGL(k_merge, dim3(blocks_for(threads)), dim3(256), 0, st, d_tasks, (uint32_t)tiled.size(), ord,
-                         dst, tu, kw8, N);
-      LAUNCH_CHECK();
-    }
+    KTimer kt(c, "k_merge");
+    hipLaunchKernelGGL(k_merge, dim3(blocks_for(threads)), dim3(256), 0, st, d_tasks, (uint32_t)tiled.size(), ord, dst,
+                       tu, kw8, N);
+    LAUNCH_CHECK();
+    kt.stop();
     ord = dst;
-    rounds++;
-    sync(c);  // the task list is reused next round
+    round++;
   }
   mark(c, "merge");
   // --- drop shadowed versions and bottom-level deletions
@@ -926,38 +1099,44 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   fill_u64(c, shadowed, 0, J);
   fill_u64(c, tomb, 0, J);
   std::vector<uint32_t> active(J);
-  for (uint32_t j = 0; j < J; j++) active[j] = B.hj[j].failed ? 0u : 1u;
+  for (uint32_t j = 0; j < J; j++) active[j] = hj[j].failed ? 0u : 1u;
   uint32_t* d_active = dbuf<uint32_t>(c, "job_active", J);
-  h2d(c, d_active, active.data(), J);
+  up(c, d_active, active.data(), (size_t)J * 4);
+  up_flush(c);
   uint32_t* surv = dbuf<uint32_t>(c, "surv", N);
   uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", J + 1);
   if (N) {
-    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N)), dim3(256), 0, st, ord, tu, kw8, d_jobs, d_job_e0, J, N,
-                       keep, shadowed, tomb, d_active);
+    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N)), dim3(256), 0, st, ord, tu, kw8, d_jobs, job_e0d, J, N, keep,
+                       shadowed, tomb, d_active);
     LAUNCH_CHECK();
   }
-  launch_scan<uint32_t>(keep, N, kpos, scan32, st);
+  launch_scan<uint32_t>(keep, N, nullptr, kpos, scan32, st);
   LAUNCH_CHECK();
   if (N) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N)), dim3(256), 0, st, ord, keep, kpos, N, surv);
     LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_job_surv, dim3(blocks_for(J + 1)), dim3(256), 0, st, d_job_e0, kpos, J, d_job_s0);
+  hipLaunchKernelGGL(k_job_surv, dim3(blocks_for(J + 1)), dim3(256), 0, st, job_e0d, kpos, J, d_job_s0);
   LAUNCH_CHECK();
   PlanIn P;
   P.J = J;
   P.d_jobs = d_jobs;
-  P.jobs = &B.jd;
   P.tu = tu;
   P.kw8 = kw8;
   P.d_surv = surv;
   P.job_s0.assign(J + 1, 0);
   P.d_job_s0 = d_job_s0;
   std::vector<uint64_t> h_shadow(J), h_tomb(J);
-  d2h(c, P.job_s0.data(), d_job_s0, J + 1);
-  d2h(c, h_shadow.data(), (uint64_t*)shadowed, J);
-  d2h(c, h_tomb.data(), (uint64_t*)tomb, J);
-  sync(c);
+  {
+    Mail m(c);
+    const uint64_t* a = m.add(d_job_s0, J + 1);
+    const uint64_t* b = m.add((const uint64_t*)shadowed, J);
+    const uint64_t* d = m.add((const uint64_t*)tomb, J);
+    m.flush();
+    memcpy(P.job_s0.data(), a, (size_t)(J + 1) * 8);
+    memcpy(h_shadow.data(), b, (size_t)J * 8);
+    memcpy(h_tomb.data(), d, (size_t)J * 8);
+  }
   mark(c, "dedup");
 
   PlanOut O;
@@ -974,27 +1153,21 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   mark(c, "d2h");
   sync(c);
   const double ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
-  // device outputs get their own buffer so that the next call cannot reuse it
-  uint8_t* dev_copy = nullptr;
+  // device outputs: the output buffer is handed over to the results
   DevBlock* dblk = nullptr;
   if (dev_out && O.total_bytes) {
     DBuf& b = c->bufs["out_tables"];
-    dev_copy = (uint8_t*)b.p;  // hand the buffer over to the results
-    b.p = nullptr;
-    b.cap = 0;
-    dblk = new DevBlock{dev_copy, 0};
+    dblk = new DevBlock{b.p, b.cap, 0};
+    b = DBuf{};
   }
   for (uint32_t j = 0; j < J; j++) {
     luda_result& r = results[j];
     memset(&r, 0, sizeof r);
     r.entries_in = job_e0[j + 1] - job_e0[j];
-    r.bytes_in = B.hj[j].bytes_in;
+    r.bytes_in = hj[j].bytes_in;
     r.ms_total = ms;
-    if (B.hj[j].failed) {
-      if (B.hj[j].err_key != ERR_NONE) r.error = decode_err(B.hj[j].err_key, B.in_size, B.hj[j].in_first);
-      else {
-        r.error.status = LUDA_UNSUPPORTED;
-      }
+    if (hj[j].failed) {
+      r.error = decode_err(hj[j].err_key, in_size, hj[j].in_first);
       r.status = r.error.status;
       continue;
     }
@@ -1016,7 +1189,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       r.data_size = O.file_out[f1] - base;
       r.bytes_out = r.data_size;
       if (dev_out) {
-        r.data = dev_copy + base;
+        r.data = (uint8_t*)dblk->p + base;
         ri->dev = dblk;
         dblk->refs++;
       } else {
@@ -1028,8 +1201,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     }
   }
   free(host_all);
-  if (dblk && dblk->refs == 0) {
-    (void)hipFree(dblk->p);
+  if (dblk && dblk->refs == 0) {  // no result kept it
+    c->bufs["out_tables"] = DBuf{dblk->p, dblk->cap};
     delete dblk;
   }
   collect_times(c);
@@ -1045,16 +1218,22 @@ extern "C" {
 int luda_selftest_crc(void) {
   static CrcTables T;
   build_crc_tables(&T);
-  // shift tables against zero-byte processing
   uint32_t t0[256];
   for (uint32_t b = 0; b < 256; b++) t0[b] = T.t4[0][b];
+  // shift tables and GF(2) multipliers against zero-byte processing
   uint32_t x = 0x12345678u;
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < NSH; k++) {
     uint32_t r = x;
-    const int m = 68 << k;
+    const int m = 16 << k;
     for (int z = 0; z < m; z++) r = step_byte(r, 0, t0);
     if (apply_shift(T.sh[k], x) != r) return 1;
+    if (h_mulmod(x, h_xpow8n((uint64_t)m)) != r) return 3;
     x = x * 2654435761u + 12345u;
+  }
+  for (uint64_t m = 1; m < 300; m += 37) {
+    uint32_t r = x;
+    for (uint64_t z = 0; z < m; z++) r = step_byte(r, 0, t0);
+    if (h_mulmod(x, h_xpow8n(m)) != r) return 4;
   }
   // slicing-by-4 against bytewise on one dword
   uint32_t c = 0xDEADBEEFu, d = 0x01020304u;
@@ -1080,17 +1259,24 @@ int luda_ctx_create(int device, luda_ctx** out) {
     c->n_cu = prop.multiProcessorCount;
     c->lds_limit = prop.sharedMemPerBlock;
     // kernels whose dynamic LDS is sized at run time may use all of it
-    const void* dyn[] = {(const void*)k_decode, (const void*)k_encode, (const void*)k_filter,
-                         (const void*)k_seg_compose};
+    const void* dyn[] = {(const void*)k_encode, (const void*)k_filter, (const void*)k_seg_compose};
     for (const void* f : dyn)
       HIPCK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_limit - 2048));
     static CrcTables T;
     build_crc_tables(&T);
     HIPCK(hipMalloc((void**)&c->d_crc, sizeof(CrcTables)));
     HIPCK(hipMemcpy(c->d_crc, &T, sizeof(CrcTables), hipMemcpyHostToDevice));
+    c->mail_cap = 8u << 20;
+    HIPCK(hipHostMalloc((void**)&c->mail, c->mail_cap, hipHostMallocCoherent));
+    c->stage_cap = 16u << 20;
+    HIPCK(hipHostMalloc((void**)&c->stage, c->stage_cap, hipHostMallocCoherent));
     c->timing = getenv("LUDA_STAGE_TIMES") != nullptr;
   } catch (const Fail& f) {
     fprintf(stderr, "luda_ctx_create: %s\n", f.msg.c_str());
+    if (c->mail) (void)hipHostFree(c->mail);
+    if (c->stage) (void)hipHostFree(c->stage);
+    if (c->d_crc) (void)hipFree(c->d_crc);
+    if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
     return f.status;
   }
@@ -1104,9 +1290,12 @@ void luda_ctx_destroy(luda_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
+  if (c->spare_out.p) (void)hipFree(c->spare_out.p);
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
   for (auto e : c->kevents) (void)hipEventDestroy(e);
   if (c->d_crc) (void)hipFree(c->d_crc);
+  if (c->mail) (void)hipHostFree(c->mail);
+  if (c->stage) (void)hipHostFree(c->stage);
   if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
 }
@@ -1123,6 +1312,7 @@ static int run_guarded(luda_ctx* c, const luda_job* jobs, uint32_t n, bool dev, 
     run_batch(c, jobs, n, dev, res);
   } catch (const Fail& f) {
     c->last_error = f.msg;
+    (void)hipStreamSynchronize(c->stream);
     for (uint32_t j = 0; j < n; j++) {
       memset(&res[j], 0, sizeof(luda_result));
       res[j].status = f.status;
@@ -1175,11 +1365,10 @@ void luda_result_free(luda_ctx* c, luda_result* r) {
   if (!r) return;
   ResultInternal* ri = (ResultInternal*)r->internal;
   if (ri && ri->host_data) free(r->data);
-  release_dev(ri);
+  release_dev(c, ri);
   delete ri;
   free(r->files);
   memset(r, 0, sizeof *r);
-  (void)c;
 }
 
 int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const uint64_t* koff, const uint64_t* tags,
@@ -1203,8 +1392,12 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
       LAUNCH_CHECK();
     }
     uint32_t maxlen = 0;
-    d2h(c, &maxlen, d_max, 1);
-    sync(c);
+    {
+      Mail m(c);
+      const uint32_t* p = m.add(d_max, 1);
+      m.flush();
+      maxlen = *p;
+    }
     const uint32_t kw8 = std::max<uint32_t>(2, (maxlen + 7) / 8);
     Tuples tu;
     memset(&tu, 0, sizeof tu);
@@ -1224,21 +1417,24 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
       LAUNCH_CHECK();
     }
     uint32_t bad = 0;
-    d2h(c, &bad, d_max + 1, 1);
-    sync(c);
+    {
+      Mail m(c);
+      const uint32_t* p = m.add(d_max + 1, 1);
+      m.flush();
+      bad = *p;
+    }
     if (bad) throw Fail{LUDA_UNSORTED_INPUT, "entries are not strictly increasing internal keys"};
-    std::vector<JobDesc> jd(1);
-    jd[0] = JobDesc{opt->block_size, opt->restart_interval, opt->bloom_bits_per_key, opt->bottommost ? 1u : 0u,
-                    opt->target_file_size, 0, 0};
+    JobDesc jd{opt->block_size, opt->restart_interval, opt->bloom_bits_per_key, opt->bottommost ? 1u : 0u,
+               opt->target_file_size, 0, 0};
     JobDesc* d_jobs = dbuf<JobDesc>(c, "jobs", 1);
-    h2d(c, d_jobs, jd.data(), 1);
     uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", 2);
-    uint64_t hs0[2] = {0, n};
-    h2d(c, d_job_s0, hs0, 2);
+    const uint64_t hs0[2] = {0, n};
+    up(c, d_jobs, &jd, sizeof jd);
+    up(c, d_job_s0, hs0, sizeof hs0);
+    up_flush(c);
     PlanIn P;
     P.J = 1;
     P.d_jobs = d_jobs;
-    P.jobs = &jd;
     P.tu = tu;
     P.kw8 = kw8;
     P.d_surv = surv;
@@ -1257,22 +1453,21 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     out->internal = ri;
     if (nf) {
       DBuf& b = c->bufs["out_tables"];
-      uint8_t* dev = (uint8_t*)b.p;
-      b.p = nullptr;
-      b.cap = 0;
-      ri->dev = new DevBlock{dev, 1};
+      ri->dev = new DevBlock{b.p, b.cap, 1};
+      b = DBuf{};
       out->files = (luda_file*)calloc(nf, sizeof(luda_file));
       for (uint64_t f = 0; f < nf; f++) {
         out->files[f].offset = O.file_out[f];
         out->files[f].size = O.file_out[f + 1] - O.file_out[f];
         out->files[f].num_entries = O.file_entries[f];
       }
-      out->data = dev;
+      out->data = (uint8_t*)ri->dev->p;
       out->data_size = O.file_out[nf];
       out->bytes_out = out->data_size;
     }
   } catch (const Fail& f) {
     c->last_error = f.msg;
+    (void)hipStreamSynchronize(c->stream);
     out->status = out->error.status = f.status;
     return f.status;
   }

@@ -42,23 +42,18 @@ struct Inputs {
   const uint64_t* size;  // bytes
   const uint32_t* job;   // owning job
   const uint32_t* local; // index inside its job
-  uint64_t* idx_off;     // index block handle (from the footer)
-  uint64_t* idx_size;
-  uint32_t* nblk;        // data blocks listed by the index
-  uint32_t* maxblk;      // largest data block (contents + trailer) of the input
-  uint64_t* dbytes;      // bytes of its data blocks, trailers included
   uint32_t n;            // number of inputs
 };
 
-struct Blocks {
-  uint64_t* off;       // data block offset within its input
-  uint32_t* size;      // contents size (trailer excluded)
-  uint32_t* input;     // global input
-  uint32_t* local;     // block number inside its input
-  uint64_t* e0;        // first decoded entry of the block
-  uint32_t* ne;        // entries decoded from the block
-  unsigned long long* look;  // decoupled look-back words
-  uint32_t n;
+// A set of blocks to read: index blocks (one per input) or data blocks.
+struct WalkSet {
+  uint64_t* ptr;          // device address of the block contents
+  uint32_t* size;         // contents bytes (trailer excluded)
+  uint32_t* input;        // global input
+  uint32_t* local;        // block number inside its input
+  uint8_t* skip;          // 1: not read (its input already failed)
+  const uint64_t* n_dev;  // number of blocks (device)
+  uint32_t where;         // W_INDEX or W_DATA
 };
 
 // decoded entries (struct of arrays)
@@ -72,14 +67,8 @@ struct Tuples {
   uint64_t* sn;    // shared | non_shared << 32
   uint64_t* vp;    // device address of the value
   uint32_t* vlen;
-  uint32_t* blk;   // global data block
+  uint32_t* blk;   // data block
   uint32_t* eoff;  // entry offset inside the block contents
 };
-
-// look-back word: flag in bits 63..62 (1 = block aggregate, 2 = inclusive
-// prefix), value in bits 61..0
-constexpr unsigned long long LB_AGG = 1ull << 62;
-constexpr unsigned long long LB_INC = 2ull << 62;
-constexpr unsigned long long LB_VAL = (1ull << 62) - 1;
 
 }  // namespace luda
