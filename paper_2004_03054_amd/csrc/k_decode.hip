@@ -9,7 +9,7 @@
 //   k_blk_nr     one thread per block: restart count
 //   k_crc_wave   one wave per block: masked CRC32C and block type
 //   k_crc_big    one workgroup per (long) block: 16 waves on 16 segments
-//   k_imap       one thread per block: restart interval -> block map
+//   k_imap       one thread per restart interval: its block (binary search)
 //   k_walk       one thread per restart interval: walks the interval's
 //                entries (count pass, then emit pass after a prefix sum)
 //   k_keys       one thread per entry: restores the internal key by tracing
@@ -146,12 +146,18 @@ __global__ void __launch_bounds__(1024) k_crc_big(WalkSet ws, Inputs in, const u
   if (threadIdx.x == 0) finish_crc(ws, in, b, raw, ok, err);
 }
 
-// interval -> block map
-__global__ void k_imap(WalkSet ws, const uint32_t* nr, const uint64_t* ibase, uint32_t* iblk) {
-  const uint64_t nb = *ws.n_dev;
-  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t base = ibase[b];
-    for (uint32_t k = 0; k < nr[b]; k++) iblk[base + k] = (uint32_t)b;
+// interval -> block map: the block of interval i is the last b with
+// ibase[b] <= i (blocks without intervals share their successor's base)
+__global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev, uint32_t* iblk) {
+  const uint64_t nb = *ws.n_dev, ni = *ni_dev;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (ibase[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    iblk[i] = (uint32_t)lo;
   }
 }
 

@@ -4,11 +4,17 @@
 // table bytes straight into the output block (the paper's lazy value
 // movement, Sec. III-D, without the intermediate pair buffer).
 //
-//   k_encode       one wave per output data block: assembles the block in
-//                  16-byte chunks aligned to the block end (entries, restart
-//                  array, count, type byte), stores each chunk and folds it
-//                  into the block's CRC in registers
-//   k_filter       one wave per filter window: Bloom bits in LDS, then stored
+//   k_encode       one wave per output data block: assembles the block in an
+//                  LDS stage (value interiors as aligned 16-byte copies,
+//                  headers, keys, value edges and the tail as bytes), then
+//                  stores it in 16-byte chunks aligned to the block end and
+//                  folds each chunk into the block's CRC in registers
+//   k_encode_gen   the same bytes for blocks too large for the stage: every
+//                  chunk is generated in registers from the entry records
+//   k_key_hash     one thread per surviving key: its XXH64
+//   k_filter_small one thread per small filter window: bits in a private LDS
+//                  slot
+//   k_filter       one wave per larger filter window: bits in LDS, then stored
 //   k_index_write  one thread per data block: its index entry and restart slot
 //   k_meta         one thread per file: filter tail, metaindex, trailers' type
 //                  bytes, footer
@@ -23,77 +29,126 @@ __device__ inline uint32_t vlen32(uint32_t v) {
   return 1u + (v >= (1u << 7)) + (v >= (1u << 14)) + (v >= (1u << 21)) + (v >= (1u << 28));
 }
 
-// byte o of the varint encoding (len bytes) of v
-__device__ inline uint32_t varint_byte(uint32_t v, uint32_t o, uint32_t len) {
-  return ((v >> (7 * o)) & 0x7Fu) | (o + 1 < len ? 0x80u : 0u);
+typedef unsigned __int128 u128;
+
+__device__ inline u128 shr_bytes(u128 v, uint32_t o) { return o >= 16 ? (u128)0 : v >> (8 * o); }
+__device__ inline u128 shl_bytes(u128 v, uint32_t o) { return o >= 16 ? (u128)0 : v << (8 * o); }
+__device__ inline u128 keep_bytes(u128 v, uint32_t n) {
+  return n >= 16 ? v : v & ((((u128)1) << (8 * n)) - 1);
+}
+
+// the n (1..16) bytes at address a as a little-endian 128-bit value; only
+// [a, a + n) need be readable: the loads are aligned 16-byte loads, and an
+// aligned load holding a readable byte never leaves that byte's page
+__device__ inline u128 load_span(const uint8_t* a, uint32_t n) {
+  const uintptr_t x = (uintptr_t)a;
+  const uint32_t s = (uint32_t)(x & 15);
+  const uint4* p = (const uint4*)(x - s);
+  const uint4 w0 = p[0];
+  u128 r = ((u128)(((uint64_t)w0.w << 32) | w0.z) << 64) | (((uint64_t)w0.y << 32) | w0.x);
+  r >>= 8 * s;
+  if (s + n > 16) {
+    const uint4 w1 = p[1];
+    const u128 h = ((u128)(((uint64_t)w1.w << 32) | w1.z) << 64) | (((uint64_t)w1.y << 32) | w1.x);
+    r |= h << (8 * (16 - s));
+  }
+  return keep_bytes(r, n);
+}
+
+__device__ inline uint64_t pack_varint(uint32_t v, uint32_t* len) {
+  uint64_t r = 0;
+  uint32_t n = 0;
+  while (v >= 128) {
+    r |= (uint64_t)((v & 127u) | 128u) << (8 * n);
+    v >>= 7;
+    n++;
+  }
+  r |= (uint64_t)v << (8 * n);
+  *len = n + 1;
+  return r;
+}
+
+// bytes [q0, q0 + n) of an internal key (user key from its zero-padded slot
+// of kw8 words, then the 8-byte tag)
+__device__ inline u128 ikey_span(const uint64_t* slot, uint32_t kw8, uint32_t ul, uint64_t tag, uint32_t q0,
+                                 uint32_t n) {
+  u128 r;
+  if (q0 < ul) {
+    const uint32_t w = q0 >> 3, b = q0 & 7;
+    const uint64_t a0 = slot[w];
+    const uint64_t a1 = (w + 1 < kw8) ? slot[w + 1] : 0;
+    const uint64_t a2 = (w + 2 < kw8) ? slot[w + 2] : 0;
+    r = (((u128)a1 << 64) | a0) >> (8 * b);
+    if (b) r |= (u128)a2 << (128 - 8 * b);
+    r = keep_bytes(r, ul - q0) | shl_bytes((u128)tag, ul - q0);
+  } else {
+    r = shr_bytes((u128)tag, q0 - ul);
+  }
+  return keep_bytes(r, n);
+}
+
+// overlap of block segment [a, b) with the chunk's bytes at positions >= 0:
+// source offset o, chunk offset d, length n (0: none)
+struct Ov {
+  uint32_t o, d, n;
+};
+__device__ inline Ov overlap(int64_t p0, int64_t a, int64_t b) {
+  const int64_t x0 = max(a, max(p0, (int64_t)0)), x1 = min(b, p0 + 16);
+  Ov r;
+  r.n = x0 < x1 ? (uint32_t)(x1 - x0) : 0u;
+  r.o = (uint32_t)(x0 - a);
+  r.d = (uint32_t)(x0 - p0);
+  return r;
 }
 
 // One 16-byte chunk of block message bytes [p0, p0 + 16) (positions < 0 give
-// zeros), built byte by byte.  i is the window entry holding position
-// max(p0, 0) when that position lies in the entry area.
-__device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t i, int64_t p0, uint32_t data_end, uint32_t size,
-                                uint32_t nrest, uint32_t R, const uint32_t* blk_off, const uint64_t* heap,
-                                uint32_t kw8) {
-  uint32_t st = L->st[i], en = L->st[i + 1], vs = L->vs[i], sh = L->sh[i], ul = L->ul[i];
-  uint32_t ns = ul + 8 - sh;
-  uint32_t la = vlen32(sh), lb = vlen32(ns), lc = vlen32(en - vs);
-  const uint64_t* slot = heap + (uint64_t)L->e[i] * kw8;
-  uint64_t tag = L->tag[i];
-  const uint8_t* vp = (const uint8_t*)L->vp[i];
-  uint64_t lo = 0, hi = 0;
-#pragma unroll
-  for (int k = 0; k < 16; k++) {
-    const int64_t p = p0 + k;
-    uint32_t byte = 0;
-    if (p >= 0) {
-      if (p < (int64_t)data_end) {
-        if (p >= (int64_t)en) {
-          i++;
-          st = L->st[i];
-          en = L->st[i + 1];
-          vs = L->vs[i];
-          sh = L->sh[i];
-          ul = L->ul[i];
-          ns = ul + 8 - sh;
-          la = vlen32(sh);
-          lb = vlen32(ns);
-          lc = vlen32(en - vs);
-          slot = heap + (uint64_t)L->e[i] * kw8;
-          tag = L->tag[i];
-          vp = (const uint8_t*)L->vp[i];
-        }
-        const uint32_t pp = (uint32_t)p;
-        const uint32_t ks = vs - ns;  // key delta start
-        if (pp < ks) {
-          uint32_t o = pp - st;
-          if (o < la) {
-            byte = varint_byte(sh, o, la);
-          } else if (o < la + lb) {
-            byte = varint_byte(ns, o - la, lb);
-          } else {
-            byte = varint_byte(en - vs, o - la - lb, lc);
-          }
-        } else if (pp < vs) {
-          const uint32_t q = sh + (pp - ks);
-          byte = q < ul ? (uint32_t)(slot[q >> 3] >> (8 * (q & 7))) & 0xFFu : (uint32_t)(tag >> (8 * (q - ul))) & 0xFFu;
-        } else {
-          byte = vp[pp - vs];
-        }
-      } else if (p < (int64_t)data_end + 4ll * nrest) {
-        const uint32_t q = (uint32_t)p - data_end;
-        byte = (blk_off[(uint64_t)(q >> 2) * R] >> (8 * (q & 3))) & 0xFFu;
-      } else if (p < (int64_t)size) {
-        byte = (nrest >> (8 * ((uint32_t)p - data_end - 4 * nrest))) & 0xFFu;
-      }
+// zeros) assembled from segments: each overlapping entry's header, key delta
+// and value, then restart offsets, the restart count and the type byte (0).
+// i is the window entry holding position max(p0, 0) when that lies in the
+// entry area.
+__device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t nw, uint32_t i, int64_t p0, uint32_t data_end,
+                                uint32_t size, uint32_t nrest, uint32_t R, const uint32_t* blk_off,
+                                const uint64_t* heap, uint32_t kw8) {
+  u128 acc = 0;
+  const int64_t pend = p0 + 16;
+  for (; i < nw; i++) {
+    const int64_t st = L->st[i];
+    if (st >= pend || st >= (int64_t)data_end) break;
+    const int64_t en = L->st[i + 1], vs = L->vs[i];
+    const uint32_t sh = L->sh[i], ul = L->ul[i];
+    const uint32_t ns = ul + 8 - sh;
+    const int64_t ks = vs - ns;
+    const Ov h = overlap(p0, st, ks);
+    if (h.n) {
+      uint32_t la, lb, lc;
+      const uint64_t va = pack_varint(sh, &la), vb = pack_varint(ns, &lb), vc = pack_varint((uint32_t)(en - vs), &lc);
+      const u128 H = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
+      acc |= shl_bytes(keep_bytes(shr_bytes(H, h.o), h.n), h.d);
     }
-    if (k < 8) lo |= (uint64_t)byte << (8 * k);
-    else hi |= (uint64_t)byte << (8 * (k - 8));
+    const Ov k = overlap(p0, ks, vs);
+    if (k.n) acc |= shl_bytes(ikey_span(heap + (uint64_t)L->e[i] * kw8, kw8, ul, L->tag[i], sh + k.o, k.n), k.d);
+    const Ov v = overlap(p0, vs, en);
+    if (v.n) acc |= shl_bytes(load_span((const uint8_t*)L->vp[i] + v.o, v.n), v.d);
+  }
+  if (pend > (int64_t)data_end) {
+    const int64_t rs = data_end;
+    const int64_t from = max(p0, rs);
+    const uint32_t r0 = (uint32_t)((from - rs) >> 2);
+    for (uint32_t r = r0; r < nrest; r++) {
+      const int64_t a = rs + 4ll * r;
+      if (a >= pend) break;
+      const Ov o = overlap(p0, a, a + 4);
+      if (o.n) acc |= shl_bytes(keep_bytes((u128)(blk_off[(uint64_t)r * R] >> (8 * o.o)), o.n), o.d);
+    }
+    const int64_t a = (int64_t)size - 4;
+    const Ov o = overlap(p0, a, a + 4);
+    if (o.n) acc |= shl_bytes(keep_bytes((u128)(nrest >> (8 * o.o)), o.n), o.d);
   }
   uint4 v;
-  v.x = (uint32_t)lo;
-  v.y = (uint32_t)(lo >> 32);
-  v.z = (uint32_t)hi;
-  v.w = (uint32_t)(hi >> 32);
+  v.x = (uint32_t)acc;
+  v.y = (uint32_t)(acc >> 32);
+  v.z = (uint32_t)(acc >> 64);
+  v.w = (uint32_t)(acc >> 96);
   return v;
 }
 
@@ -106,7 +161,9 @@ __device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t i, int64_t p0, uint32_
 // starts 8 entries before the previous one ended, so a chunk assigned to a
 // window (by its first byte) never reaches past the window's entries (an
 // entry is at least 4 bytes).
-__global__ void __launch_bounds__(512) k_encode(EncodeArgs A) {
+constexpr uint32_t ENC_B = 2;  // chunks per lane in flight
+
+__global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   CrcLds* T = (CrcLds*)smem;
   load_crc_tables(T, A.g_crc, threadIdx.x, blockDim.x);
@@ -157,32 +214,64 @@ __global__ void __launch_bounds__(512) k_encode(EncodeArgs A) {
       const int64_t hi = last ? n : (int64_t)L->st[nw - 8];
       uint32_t cur = 0;
       while (cc >= 0) {
-        const int64_t p0 = n - 16 * (cc + 1);
-        const int64_t P = p0 < 0 ? 0 : p0;
-        if (P >= hi) break;
-        // entry holding P: the last with st <= P (from the lane's cursor)
-        uint32_t lo_i = cur, hi_i = nw;
-        while (hi_i - lo_i > 1) {
-          const uint32_t mid = (lo_i + hi_i) >> 1;
-          if ((int64_t)L->st[mid] <= P) lo_i = mid;
-          else hi_i = mid;
+        // up to ENC_B of this lane's chunks at once: their loads are in
+        // flight together, then they are stored and folded in order
+        uint4 v[ENC_B];
+        uint32_t m = 0, slow = 0;
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_B; t++) {
+          const int64_t c = cc - 64 * (int64_t)t;
+          const int64_t p0 = n - 16 * (c + 1);
+          const int64_t P = p0 < 0 ? 0 : p0;
+          if (c < 0 || P >= hi || m != t) continue;
+          // entry holding P: the last with st <= P (from the lane's cursor)
+          uint32_t lo_i = cur, hi_i = nw;
+          while (hi_i - lo_i > 1) {
+            const uint32_t mid = (lo_i + hi_i) >> 1;
+            if ((int64_t)L->st[mid] <= P) lo_i = mid;
+            else hi_i = mid;
+          }
+          cur = lo_i;
+          const int64_t vs = L->vs[cur];
+          if (p0 >= vs && p0 + 16 <= (int64_t)L->st[cur + 1]) {
+            __builtin_memcpy(&v[t], (const uint8_t*)L->vp[cur] + (p0 - vs), 16);
+          } else {
+            slow |= 1u << t;
+          }
+          m = t + 1;
         }
-        cur = lo_i;
-        uint4 v;
-        if (p0 >= (int64_t)L->vs[cur] && p0 + 16 <= (int64_t)L->st[cur + 1]) {
-          __builtin_memcpy(&v, (const uint8_t*)L->vp[cur] + (p0 - L->vs[cur]), 16);
-        } else {
-          v = enc_chunk_slow(L, cur, p0, data_end, (uint32_t)size, nrest, R, blk_off, A.tu.heap, A.kw8);
+        // chunks that cross a segment boundary, one at a time
+        while (slow) {
+          const uint32_t t = __builtin_ctz(slow);
+          slow &= slow - 1;
+          const int64_t p0 = n - 16 * (cc - 64 * (int64_t)t + 1);
+          const int64_t P = p0 < 0 ? 0 : p0;
+          uint32_t lo_i = 0, hi_i = nw;
+          while (hi_i - lo_i > 1) {
+            const uint32_t mid = (lo_i + hi_i) >> 1;
+            if ((int64_t)L->st[mid] <= P) lo_i = mid;
+            else hi_i = mid;
+          }
+          const uint4 r = enc_chunk_slow(L, nw, lo_i, p0, data_end, (uint32_t)size, nrest, R, blk_off, A.tu.heap, A.kw8);
+#pragma unroll
+          for (uint32_t u = 0; u < ENC_B; u++)
+            if (u == t) v[u] = r;
         }
-        if (p0 >= 0) {
-          __builtin_memcpy(dst + p0, &v, 16);
-        } else {
-          const uint8_t* vb = (const uint8_t*)&v;
-          for (int k = 0; k < 16; k++)
-            if (p0 + k >= 0) dst[p0 + k] = vb[k];
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_B; t++) {
+          if (t >= m) continue;
+          const int64_t p0 = n - 16 * (cc - 64 * (int64_t)t + 1);
+          if (p0 >= 0) {
+            __builtin_memcpy(dst + p0, &v[t], 16);
+          } else {
+            const uint8_t* vb = (const uint8_t*)&v[t];
+            for (int k = 0; k < 16; k++)
+              if (p0 + k >= 0) dst[p0 + k] = vb[k];
+          }
+          acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v[t], p0);
         }
-        acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
-        cc -= 64;
+        cc -= 64 * (int64_t)m;
+        if (m < ENC_B) break;
       }
       wave_sync();
       if (last) break;
@@ -197,7 +286,224 @@ __global__ void __launch_bounds__(512) k_encode(EncodeArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Staged encoder.  Per wave: [EncLds window | piece offsets | stage].  The
+// block message (contents || type byte) sits at the end of the stage, which
+// is 16-byte aligned, so the chunk grid of the CRC (16-byte chunks aligned to
+// the message end) is the aligned grid of the stage.
 
+__device__ inline void stage_key_bytes(uint8_t* d, const uint64_t* slot, uint32_t ul, uint64_t tag, uint32_t q0,
+                                       uint32_t q1) {
+  uint64_t word = 0;
+  uint32_t wi = 0xFFFFFFFFu;
+  for (uint32_t q = q0; q < q1; q++) {
+    uint32_t byte;
+    if (q < ul) {
+      if ((q >> 3) != wi) {
+        wi = q >> 3;
+        word = slot[wi];
+      }
+      byte = (uint32_t)(word >> (8 * (q & 7))) & 0xFFu;
+    } else {
+      byte = (uint32_t)(tag >> (8 * (q - ul))) & 0xFFu;
+    }
+    *d++ = (uint8_t)byte;
+  }
+}
+
+__device__ inline void stage_varint(uint8_t* d, uint32_t v, uint32_t* k) {
+  while (v >= 128) {
+    d[(*k)++] = (uint8_t)(v | 128u);
+    v >>= 7;
+  }
+  d[(*k)++] = (uint8_t)v;
+}
+
+__global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  CrcLds* T = (CrcLds*)smem;
+  load_crc_tables(T, A.g_crc, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
+  const uint32_t waves = blockDim.x / WAVE;
+  uint8_t* wbase = smem + sizeof(CrcLds) + (size_t)wv * A.wave_lds;
+  EncLds* L = (EncLds*)wbase;
+  uint32_t* pc = (uint32_t*)(wbase + sizeof(EncLds));  // ENC_W + 1 piece offsets
+  uint8_t* stage_end = wbase + A.wave_lds;
+  const uint64_t nb = *A.nblocks;
+  for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
+    const uint32_t j = A.ob.job[b];
+    const uint32_t R = A.jobs[j].restart_interval;
+    const uint64_t s0 = A.ob.s0[b];
+    const uint32_t cnt = A.ob.cnt[b];
+    const uint32_t size = A.ob.size[b];
+    const uint32_t nrest = (cnt + R - 1) / R;
+    const uint32_t data_end = size - 4 * nrest - 4;
+    const uint32_t n = size + 1;
+    uint8_t* dst = A.out + A.of.out[A.ob.file[b]] + A.ob.off[b];
+    const uint32_t* blk_off = A.ent_off + s0;
+    const uint32_t J16 = (n + 15) / 16;
+    uint8_t* base = stage_end - n;                    // message byte p at base[p]
+    const uint32_t gshift = 16 * J16 - n;             // chunk grid: positions = 16 m - gshift
+    // --- entries, a window at a time
+    for (uint32_t k0 = 0; k0 < cnt; k0 += ENC_W) {
+      const uint32_t nw = min(cnt - k0, ENC_W);
+      uint32_t pieces = 0, a = 0;
+      if (l < nw) {
+        const uint32_t i = k0 + l;
+        const uint64_t s = s0 + i;
+        const uint32_t e = A.surv[s];
+        const uint32_t shared = (i % R == 0) ? 0u : A.shr[s];
+        const uint32_t ul = A.tu.ulen[e];
+        const uint32_t vl = A.tu.vlen[e];
+        const uint32_t st = blk_off[i];
+        const uint32_t klen = ul + 8;
+        const uint32_t ns = klen - shared;
+        const uint8_t* vp = (const uint8_t*)A.tu.vp[e];
+        const uint64_t tag = A.tu.tag[e];
+        uint8_t* d = base + st;
+        uint32_t k = 0;
+        stage_varint(d, shared, &k);
+        stage_varint(d, ns, &k);
+        stage_varint(d, vl, &k);
+        stage_key_bytes(d + k, A.tu.heap + (uint64_t)e * A.kw8, ul, tag, shared, klen);
+        const uint32_t vs = st + k + ns, en = vs + vl;
+        // value interior: whole aligned chunks inside [vs, en); edges as
+        // bytes.  a is the first grid position >= vs, z the last <= en (it
+        // can lie before the message start, hence signed).
+        a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
+        const int64_t z = (int64_t)en - (int64_t)((en + gshift) & 15u);
+        uint32_t h_end = en, t_beg = en;
+        if ((int64_t)a + 16 <= z) {
+          pieces = (uint32_t)((z - (int64_t)a) / 16);
+          h_end = a;
+          t_beg = (uint32_t)z;
+        }
+        for (uint32_t q = vs; q < h_end; q++) base[q] = vp[q - vs];
+        for (uint32_t q = t_beg; q < en; q++) base[q] = vp[q - vs];
+        L->vs[l] = vs;
+        L->vp[l] = (uint64_t)(uintptr_t)vp;
+        L->st[l] = a;  // first interior chunk position
+      }
+      const uint32_t incl = wave_incl_scan(pieces);
+      if (l < nw) pc[l] = incl - pieces;
+      const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+      if (l == 0) pc[nw] = total;
+      wave_sync();
+      for (uint32_t k = l; k < total; k += WAVE) {
+        uint32_t lo = 0, hi = nw;  // pc[lo] <= k < pc[hi]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (pc[mid] <= k) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t pos = L->st[lo] + 16 * (k - pc[lo]);
+        uint4 v;
+        __builtin_memcpy(&v, (const uint8_t*)L->vp[lo] + (pos - L->vs[lo]), 16);
+        *(uint4*)(base + pos) = v;
+      }
+      wave_sync();
+    }
+    // --- restart array, restart count, type byte
+    for (uint32_t r = l; r < nrest; r += WAVE) {
+      const uint32_t v = blk_off[(uint64_t)r * R];
+      uint8_t* d = base + data_end + 4 * r;
+      d[0] = (uint8_t)v;
+      d[1] = (uint8_t)(v >> 8);
+      d[2] = (uint8_t)(v >> 16);
+      d[3] = (uint8_t)(v >> 24);
+    }
+    if (l == 0) {
+      uint8_t* d = base + size - 4;
+      d[0] = (uint8_t)nrest;
+      d[1] = (uint8_t)(nrest >> 8);
+      d[2] = (uint8_t)(nrest >> 16);
+      d[3] = (uint8_t)(nrest >> 24);
+      d[4] = 0;
+    }
+    wave_sync();
+    // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i
+    uint32_t acc = 0;
+    const int64_t c_first = 63 - (int64_t)l;
+    if (c_first < (int64_t)J16) {
+      for (int64_t c = c_first + 64 * (((int64_t)J16 - 1 - c_first) / 64); c >= 0; c -= 64) {
+        const int64_t p0 = (int64_t)n - 16 * (c + 1);
+        const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
+        if (p0 >= 0) {
+          __builtin_memcpy(dst + p0, &v, 16);
+        } else {
+          const uint8_t* vb = (const uint8_t*)&v;
+          for (int k = 0; k < 16; k++)
+            if (p0 + k >= 0) dst[p0 + k] = vb[k];
+        }
+        acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
+      }
+    }
+    const uint32_t raw = crc_wave_join(T, acc);
+    if (l == 0) {
+      const uint32_t m = crc_mask(raw ^ 0xFFFFFFFFu);
+      __builtin_memcpy(dst + n, &m, 4);
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+// XXH64 of every surviving user key (the Bloom probes derive from it)
+__global__ void k_key_hash(const uint32_t* surv, Tuples tu, uint32_t kw8, uint64_t n, uint64_t* hash) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t e = surv[s];
+  hash[s] = xxh64_words(tu.heap + (uint64_t)e * kw8, tu.ulen[e]);
+}
+
+__device__ inline uint32_t bloom_k(uint32_t bpk) {
+  uint32_t k = bpk * 69u / 100u;
+  return k < 1 ? 1 : (k > 30 ? 30 : k);
+}
+
+__device__ inline uint8_t* window_dst(const FilterArgs& A, uint64_t w, uint32_t f) {
+  return A.out + A.of.out[f] + A.of.filter_off[f] + (A.win_off[w] - A.win_off[A.of.w0[f]]);
+}
+
+// Filters of at most FILTER_SMALL_BYTES bytes: one thread per window, bits in
+// a private LDS slot (no atomics), then stored with the probe count.
+constexpr uint32_t FILTER_SMALL_BYTES = 64;
+constexpr uint32_t FILTER_SLOT_WORDS = FILTER_SMALL_BYTES / 4 + 1;  // padded against bank conflicts
+
+__global__ void __launch_bounds__(256) k_filter_small(FilterArgs A) {
+  __shared__ uint32_t slots[256 * FILTER_SLOT_WORDS];
+  uint32_t* bits = slots + threadIdx.x * FILTER_SLOT_WORDS;
+  const uint64_t nw = *A.nwin;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t keys = A.win_keys[w];
+    if (!keys) continue;
+    const uint64_t bytes = A.win_bytes[w] - 1;
+    if (bytes > FILTER_SMALL_BYTES) continue;
+    const uint32_t f = A.win_file[w];
+    const uint32_t k = bloom_k(A.jobs[A.of.job[f]].bloom_bits_per_key);
+    const uint32_t nbits = (uint32_t)bytes * 8;
+#pragma unroll
+    for (uint32_t i = 0; i < FILTER_SMALL_BYTES / 4; i++) bits[i] = 0;
+    const uint64_t s_first = A.ob.s0[A.win_fb[w]];
+    for (uint32_t i = 0; i < keys; i++) {
+      const uint64_t h = A.hash[s_first + i];
+      uint32_t g = (uint32_t)h;
+      const uint32_t d = (uint32_t)(h >> 32);
+      for (uint32_t r = 0; r < k; r++) {
+        const uint32_t pos = g % nbits;
+        bits[pos >> 5] |= 1u << (pos & 31);
+        g += d;
+      }
+    }
+    uint8_t* dst = window_dst(A, w, f);
+    const uint8_t* src = (const uint8_t*)bits;
+    for (uint32_t q = 0; q < (uint32_t)bytes; q++) dst[q] = src[q];
+    dst[bytes] = (uint8_t)k;
+  }
+}
+
+// Larger filters: one wave per window, bits in LDS with atomics.
 __global__ void __launch_bounds__(256) k_filter(FilterArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
@@ -207,19 +513,17 @@ __global__ void __launch_bounds__(256) k_filter(FilterArgs A) {
   for (uint64_t w = (uint64_t)blockIdx.x * waves + wv; w < nw; w += (uint64_t)gridDim.x * waves) {
     const uint32_t keys = A.win_keys[w];
     if (!keys) continue;
-    const uint32_t f = A.win_file[w];
-    const uint32_t bpk = A.jobs[A.of.job[f]].bloom_bits_per_key;
-    uint32_t k = bpk * 69u / 100u;
-    k = k < 1 ? 1 : (k > 30 ? 30 : k);
     const uint64_t bytes = A.win_bytes[w] - 1;
+    if (bytes <= FILTER_SMALL_BYTES) continue;
+    const uint32_t f = A.win_file[w];
+    const uint32_t k = bloom_k(A.jobs[A.of.job[f]].bloom_bits_per_key);
     const uint64_t nbits = bytes * 8;
     const uint32_t words = (uint32_t)((bytes + 1 + 3) / 4);
     for (uint32_t i = l; i < words; i += WAVE) bits[i] = 0;
     wave_sync();
     const uint64_t s_first = A.ob.s0[A.win_fb[w]];
     for (uint32_t i = l; i < keys; i += WAVE) {
-      const uint32_t e = A.surv[s_first + i];
-      const uint64_t h = xxh64_words(A.tu.heap + (uint64_t)e * A.kw8, A.tu.ulen[e]);
+      const uint64_t h = A.hash[s_first + i];
       uint32_t g = (uint32_t)h;
       const uint32_t d = (uint32_t)(h >> 32);
       for (uint32_t r = 0; r < k; r++) {
@@ -231,7 +535,7 @@ __global__ void __launch_bounds__(256) k_filter(FilterArgs A) {
     wave_sync();
     if (l == 0) ((uint8_t*)bits)[bytes] = (uint8_t)k;
     wave_sync();
-    uint8_t* dst = A.out + A.of.out[f] + A.of.filter_off[f] + (A.win_off[w] - A.win_off[A.of.w0[f]]);
+    uint8_t* dst = window_dst(A, w, f);
     const uint8_t* src = (const uint8_t*)bits;
     const uint64_t tot = bytes + 1;
     for (uint64_t o = (uint64_t)l * 16; o < tot; o += WAVE * 16) {

@@ -85,19 +85,36 @@ __global__ void k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, cons
                               const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
                               unsigned long long* shadowed, unsigned long long* tomb, const uint32_t* active) {
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const uint32_t j = find_job(job_e0, J, p);
-  if (!active[j]) {
-    keep[p] = 0;
-    return;
+  const bool live = p < n;
+  uint32_t j = 0;
+  bool shadow = false, drop_del = false;
+  if (live) {
+    j = find_job(job_e0, J, p);
+    if (!active[j]) {
+      keep[p] = 0;
+    } else {
+      const uint32_t e = ord[p];
+      const bool first = (p == job_e0[j]) || !same_user_key(tu, kw8, ord[p - 1], e);
+      const bool del = (tu.tag[e] & 0xFF) == 0;
+      drop_del = first && jobs[j].bottommost && del;
+      shadow = !first;
+      keep[p] = (first && !drop_del) ? 1u : 0u;
+    }
   }
-  const uint32_t e = ord[p];
-  const bool first = (p == job_e0[j]) || !same_user_key(tu, kw8, ord[p - 1], e);
-  const bool del = (tu.tag[e] & 0xFF) == 0;
-  const bool drop_del = first && jobs[j].bottommost && del;
-  keep[p] = (first && !drop_del) ? 1u : 0u;
-  if (!first) atomicAdd(&shadowed[j], 1ull);
-  if (drop_del) atomicAdd(&tomb[j], 1ull);
+  // counts: one atomic per wave when the whole wave is in one job
+  const uint32_t j0 = __shfl(j, 0, WAVE);
+  const bool uniform = wave_ballot(live && j != j0) == 0;
+  if (uniform) {
+    const uint32_t ns = (uint32_t)__popcll(wave_ballot(shadow));
+    const uint32_t nd = (uint32_t)__popcll(wave_ballot(drop_del));
+    if (lane_id() == 0) {
+      if (ns) atomicAdd(&shadowed[j0], (unsigned long long)ns);
+      if (nd) atomicAdd(&tomb[j0], (unsigned long long)nd);
+    }
+  } else {
+    if (shadow) atomicAdd(&shadowed[j], 1ull);
+    if (drop_del) atomicAdd(&tomb[j], 1ull);
+  }
 }
 
 __global__ void k_scatter(const uint32_t* ord, const uint32_t* keep, const uint32_t* pos, uint64_t n,

@@ -466,28 +466,34 @@ __global__ void k_block_post(const uint64_t* nfiles_total, OutFiles of, const ui
 __global__ void k_win_size(const uint64_t* nwin_total, const uint64_t* file_w0_sorted, uint64_t nfiles,
                            OutFiles of, const JobDesc* jobs, const uint32_t* win_keys, uint64_t cap,
                            uint64_t* win_bytes, uint32_t* win_file, uint32_t* max_bytes) {
-  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t m;
+  if (threadIdx.x == 0) m = 0;
+  __syncthreads();
+  const uint64_t nw = *nwin_total;
   uint32_t mine = 0;
-  if (w < cap) {
-    if (w >= *nwin_total) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < cap; w += (uint64_t)gridDim.x * blockDim.x) {
+    if (w >= nw) {
       win_bytes[w] = 0;
-    } else {
-      const uint32_t f = find_sorted(file_w0_sorted, nfiles, w);
-      win_file[w] = f;
-      const uint32_t keys = win_keys[w];
-      uint64_t v = 0;
-      if (keys) {
-        const uint64_t bpk = jobs[of.job[f]].bloom_bits_per_key;
-        uint64_t bits = (uint64_t)keys * bpk;
-        if (bits < 64) bits = 64;
-        v = (bits + 7) / 8 + 1;
-      }
-      win_bytes[w] = v;
-      mine = (uint32_t)(v > 0xFFFFFFF0ull ? 0xFFFFFFF0ull : v);
+      continue;
     }
+    const uint32_t f = find_sorted(file_w0_sorted, nfiles, w);
+    win_file[w] = f;
+    const uint32_t keys = win_keys[w];
+    uint64_t v = 0;
+    if (keys) {
+      const uint64_t bpk = jobs[of.job[f]].bloom_bits_per_key;
+      uint64_t bits = (uint64_t)keys * bpk;
+      if (bits < 64) bits = 64;
+      v = (bits + 7) / 8 + 1;
+    }
+    win_bytes[w] = v;
+    const uint32_t vv = (uint32_t)(v > 0xFFFFFFF0ull ? 0xFFFFFFF0ull : v);
+    mine = vv > mine ? vv : mine;
   }
   mine = wave_max(mine);
-  if (lane_id() == 0 && mine) atomicMax(max_bytes, mine);
+  if (lane_id() == 0 && mine) atomicMax(&m, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && m) atomicMax(max_bytes, m);
 }
 
 // per file: the layout of filter, metaindex and index blocks and the footer

@@ -74,7 +74,7 @@ __global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long 
 __global__ void k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
                            unsigned long long* bytes_total);
 __global__ void k_crc_big(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err);
-__global__ void k_imap(WalkSet ws, const uint32_t* nr, const uint64_t* ibase, uint32_t* iblk);
+__global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev, uint32_t* iblk);
 template <int KIND, int MODE>
 __global__ void k_walk(WalkArgs A);
 __global__ void k_keys(Tuples tu, WalkSet ws, Inputs in, uint32_t kw8, const uint64_t* n_dev, unsigned long long* err);
@@ -147,6 +147,7 @@ struct EncodeArgs {
   const uint32_t* g_crc;
   const uint32_t* ent_off;  // each survivor's entry offset inside its block
   uint32_t kw8;
+  uint32_t wave_lds;        // staged encoder: LDS bytes per wave (multiple of 16)
 };
 // entries of one output block held in LDS at a time (per wave)
 constexpr uint32_t ENC_W = 64;
@@ -161,6 +162,7 @@ struct EncLds {
   uint32_t pad[3];
 };
 __global__ void k_encode(EncodeArgs A);
+__global__ void k_encode_gen(EncodeArgs A);
 struct FilterArgs {
   const JobDesc* jobs;
   OutBlocks ob;
@@ -173,10 +175,13 @@ struct FilterArgs {
   const uint32_t* win_file;
   const uint64_t* win_bytes;
   const uint64_t* win_off;    // exclusive scan of win_bytes
+  const uint64_t* hash;       // XXH64 of each survivor's user key
   uint8_t* out;
   uint32_t kw8;
   uint32_t lds_bytes;         // per wave
 };
+__global__ void k_key_hash(const uint32_t* surv, Tuples tu, uint32_t kw8, uint64_t n, uint64_t* hash);
+__global__ void k_filter_small(FilterArgs A);
 __global__ void k_filter(FilterArgs A);
 __global__ void k_index_write(OutBlocks ob, OutFiles of, Tuples tu, const uint32_t* surv, const uint64_t* ie_off,
                               const uint64_t* nblocks, uint32_t kw8, uint64_t cap, uint8_t* out);

@@ -18,7 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/luda.h"
+#include "luda.h"
 #include "kernels.h"
 
 using namespace luda;
@@ -541,18 +541,22 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   // sizes needed to allocate window arrays and the encoder's LDS
   uint32_t* stats = dbuf<uint32_t>(c, "plan_stats", 4);
   fill_u32(c, stats, 0, 4);
-  hipLaunchKernelGGL(k_plan_stats, dim3(stride_grid(c, OB)), dim3(256), 0, st, ob, job_ob0, J, OB, stats);
+  hipLaunchKernelGGL(k_plan_stats, dim3(std::min<uint32_t>(stride_grid(c, OB), c->n_cu)), dim3(256), 0, st, ob, job_ob0, J, OB,
+                     stats);
   LAUNCH_CHECK();
   uint64_t NBLK, NF, NW;
+  uint32_t max_bsize;
   {
     Mail m(c);
     const uint64_t* a = m.add(job_ob0 + J, 1);
     const uint64_t* b = m.add(job_f0 + J, 1);
     const uint64_t* w = m.add(of.w0 + FC, 1);
+    const uint32_t* x = m.add(stats, 2);
     m.flush();
     NBLK = *a;
     NF = *b;
     NW = *w;
+    max_bsize = x[0];
   }
 
   uint32_t* win_keys = dbuf<uint32_t>(c, "win_keys", NW);
@@ -567,8 +571,8 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   uint32_t* wstat = dbuf<uint32_t>(c, "win_stat", 1);
   fill_u32(c, wstat, 0, 1);
-  hipLaunchKernelGGL(k_win_size, dim3(blocks_for(NW)), dim3(256), 0, st, of.w0 + FC, of.w0, NF, of, P.d_jobs,
-                     win_keys, NW, win_bytes, win_file, wstat);
+  hipLaunchKernelGGL(k_win_size, dim3(std::min<uint32_t>(stride_grid(c, NW), c->n_cu)), dim3(256), 0, st, of.w0 + FC,
+                     of.w0, NF, of, P.d_jobs, win_keys, NW, win_bytes, win_file, wstat);
   LAUNCH_CHECK();
   uint64_t* scan_tmpw = dbuf<uint64_t>(c, "scan_tmpw", NW / 2048 + 8);
   launch_scan<uint64_t>(win_bytes, NW, nullptr, win_off, scan_tmpw, st);
@@ -628,20 +632,34 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.g_crc = c->d_crc;
     A.ent_off = ent_off;
     A.kw8 = P.kw8;
-    const int waves = 8;
-    const size_t lds = CRC_LDS_BYTES + sizeof(EncLds) * waves;
+    // staged encoder when a block message (plus the entry window) fits in
+    // LDS for at least two waves; otherwise the register generator
+    const size_t win = sizeof(EncLds) + ((4 * (ENC_W + 1) + 15) & ~size_t(15));
+    const size_t per_wave = win + ((size_t(max_bsize) + 1 + 15) & ~size_t(15)) + 16;
+    const size_t budget = c->lds_limit - 2048 - CRC_LDS_BYTES;
+    const size_t sw = std::min<size_t>(16, budget / per_wave);
+    const bool staged = sw >= 2 && per_wave < (1u << 31);
+    const int waves = staged ? (int)sw : 8;
+    const void* fn = staged ? (const void*)k_encode : (const void*)k_encode_gen;
+    A.wave_lds = staged ? (uint32_t)per_wave : 0;
+    const size_t lds = CRC_LDS_BYTES + (staged ? per_wave : sizeof(EncLds)) * waves;
     int occ = 0;
-    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, lds));
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, waves * 64, lds));
     occ = std::max(occ, 1);
     const uint64_t want = (NBLK + waves - 1) / waves;
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
     KTimer kt(c, "k_encode");
-    hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
+    if (staged) hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
+    else hipLaunchKernelGGL(k_encode_gen, dim3(grid), dim3(waves * 64), lds, st, A);
     LAUNCH_CHECK();
     kt.stop();
+    c->counters.emplace_back("encode_staged", staged ? 1.0 : 0.0);
+    c->counters.emplace_back("encode_waves_per_group", (double)waves);
+    c->counters.emplace_back("encode_groups", (double)grid);
   }
   mark(c, "encode");
   if (NW) {
+    uint64_t* hash = dbuf<uint64_t>(c, "key_hash", S);
     FilterArgs F;
     F.jobs = P.d_jobs;
     F.ob = ob;
@@ -654,19 +672,26 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     F.win_file = win_file;
     F.win_bytes = win_bytes;
     F.win_off = win_off;
+    F.hash = hash;
     F.out = out;
     F.kw8 = P.kw8;
     F.lds_bytes = (uint32_t)(((uint64_t)max_win + 16 + 15) & ~15ull);
-    const size_t budget = c->lds_limit - 2048;
-    int waves = 4;
-    while (waves > 1 && (size_t)F.lds_bytes * waves > budget) waves--;
-    if ((size_t)F.lds_bytes * waves > budget)
-      throw Fail{LUDA_UNSUPPORTED, "filter of " + std::to_string(max_win) + " bytes exceeds the filter kernel's LDS"};
-    const uint32_t grid =
-        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NW + waves - 1) / waves, (uint64_t)c->n_cu * 8));
     KTimer kt(c, "k_filter");
-    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
+    hipLaunchKernelGGL(k_key_hash, dim3(blocks_for(S)), dim3(256), 0, st, P.d_surv, P.tu, P.kw8, S, hash);
     LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_filter_small, dim3(stride_grid(c, NW)), dim3(256), 0, st, F);
+    LAUNCH_CHECK();
+    if (max_win > 64 + 1) {
+      const size_t budget = c->lds_limit - 2048;
+      int waves = 4;
+      while (waves > 1 && (size_t)F.lds_bytes * waves > budget) waves--;
+      if ((size_t)F.lds_bytes * waves > budget)
+        throw Fail{LUDA_UNSUPPORTED, "filter of " + std::to_string(max_win) + " bytes exceeds the filter kernel's LDS"};
+      const uint32_t grid =
+          (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NW + waves - 1) / waves, (uint64_t)c->n_cu * 8));
+      hipLaunchKernelGGL(k_filter, dim3(grid), dim3(waves * 64), (size_t)F.lds_bytes * waves, st, F);
+      LAUNCH_CHECK();
+    }
     kt.stop();
     hipLaunchKernelGGL(k_filter_offsets, dim3(blocks_for(NW)), dim3(256), 0, st, of, of.w0 + FC, win_file, win_off,
                        NW, out);
@@ -835,7 +860,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   WA.icnt = IX.icnt;
   WA.maxklen = d_maxk;
   if (IX.NI) {
-    hipLaunchKernelGGL(k_imap, dim3(blocks_for(NG)), dim3(256), 0, st, ix, IX.nr, IX.ibase, IX.iblk);
+    hipLaunchKernelGGL(k_imap, dim3(stride_grid(c, IX.NI)), dim3(256), 0, st, ix, IX.ibase, IX.ibase + NG, IX.iblk);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_walk<0, 0>), dim3(stride_grid(c, IX.NI)), dim3(256), 0, st, WA);
     LAUNCH_CHECK();
@@ -928,7 +953,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   uint64_t N = 0;
   uint32_t maxklen = 0;
   if (DB.NI) {
-    hipLaunchKernelGGL(k_imap, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, DB.nr, DB.ibase, DB.iblk);
+    hipLaunchKernelGGL(k_imap, dim3(stride_grid(c, DB.NI)), dim3(256), 0, st, db, DB.ibase, DB.ibase + NB, DB.iblk);
     LAUNCH_CHECK();
     {
       KTimer kt(c, "k_walk_count");
@@ -1259,7 +1284,8 @@ int luda_ctx_create(int device, luda_ctx** out) {
     c->n_cu = prop.multiProcessorCount;
     c->lds_limit = prop.sharedMemPerBlock;
     // kernels whose dynamic LDS is sized at run time may use all of it
-    const void* dyn[] = {(const void*)k_encode, (const void*)k_filter, (const void*)k_seg_compose};
+    const void* dyn[] = {(const void*)k_encode, (const void*)k_encode_gen, (const void*)k_filter,
+                         (const void*)k_seg_compose};
     for (const void* f : dyn)
       HIPCK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_limit - 2048));
     static CrcTables T;

@@ -55,6 +55,15 @@ TINY_VARIANTS = [
     dict(n_inputs=6, entries=80, p_tomb=0.6, bottommost=1, block_size=1, target_file_size=1),
     dict(entries=300, key_alphabet=4, key_len=(3, 6), val_len=(100, 200), block_size=4096, target_file_size=4096,
          restart_interval=7, bloom_bits_per_key=3),
+    # many tiny entries per block: the encoder stages a block's entries in
+    # several windows; restart arrays of one slot per entry, and of one slot
+    dict(entries=1500, key_alphabet=6, key_len=(2, 8), val_len=(0, 4), block_size=65536, restart_interval=1,
+         target_file_size=1 << 20),
+    dict(entries=1500, key_alphabet=6, key_len=(2, 8), val_len=(0, 40), block_size=65536, restart_interval=500,
+         target_file_size=1 << 20),
+    # blocks larger than the encoder's LDS stage (encoded from registers)
+    dict(entries=150, key_alphabet=5, key_len=(4, 12), val_len=(1500, 5000), block_size=1 << 20, restart_interval=16,
+         target_file_size=4 << 20),
 ]
 
 
