@@ -65,6 +65,14 @@ __device__ inline uint64_t ldg_u64_unaligned(const uint8_t* p) {
 }
 
 __device__ inline uint64_t bswap64(uint64_t x) { return __builtin_bswap64(x); }
+// 16 bytes at a global address of any alignment (one global_load_dwordx4)
+typedef uint4 __attribute__((aligned(1))) uint4_u1;
+typedef const __attribute__((address_space(1))) uint4_u1 g_uint4_u1;
+typedef const __attribute__((address_space(1))) uint4 g_uint4;
+__device__ inline uint4 ldg16(uint64_t addr) { return *(g_uint4_u1*)addr; }
+// 16 bytes at a 16-byte aligned global address
+__device__ inline uint4 ldg16a(uint64_t addr) { return *(g_uint4*)addr; }
+
 
 template <typename T>
 __device__ inline T wave_shfl(T v, int src) {
@@ -241,10 +249,7 @@ __device__ inline uint32_t crc_wave_join(const CrcLds* T, uint32_t acc) {
 // bytes before position 0 are not read
 __device__ inline uint4 ld_chunk(const uint8_t* msg, int64_t p) {
   uint4 v;
-  if (p >= 0) {
-    __builtin_memcpy(&v, msg + p, 16);
-    return v;
-  }
+  if (p >= 0) return ldg16((uint64_t)(uintptr_t)(msg + p));
   uint8_t b[16];
 #pragma unroll
   for (int k = 0; k < 16; k++) b[k] = (p + k >= 0) ? msg[p + k] : 0;

@@ -200,8 +200,7 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs A) {
           // three varint32 headers from one 16-byte load (inside the table)
           uint8_t h[16];
           {
-            uint4 v;
-            __builtin_memcpy(&v, c + o, 16);
+            const uint4 v = ldg16((uint64_t)(uintptr_t)(c + o));
             __builtin_memcpy(h, &v, 16);
           }
           const uint64_t avail = data_end - o;

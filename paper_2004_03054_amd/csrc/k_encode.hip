@@ -43,12 +43,12 @@ __device__ inline u128 keep_bytes(u128 v, uint32_t n) {
 __device__ inline u128 load_span(const uint8_t* a, uint32_t n) {
   const uintptr_t x = (uintptr_t)a;
   const uint32_t s = (uint32_t)(x & 15);
-  const uint4* p = (const uint4*)(x - s);
-  const uint4 w0 = p[0];
+  const uint64_t p = (uint64_t)(x - s);
+  const uint4 w0 = ldg16a(p);
   u128 r = ((u128)(((uint64_t)w0.w << 32) | w0.z) << 64) | (((uint64_t)w0.y << 32) | w0.x);
   r >>= 8 * s;
   if (s + n > 16) {
-    const uint4 w1 = p[1];
+    const uint4 w1 = ldg16a(p + 16);
     const u128 h = ((u128)(((uint64_t)w1.w << 32) | w1.z) << 64) | (((uint64_t)w1.y << 32) | w1.x);
     r |= h << (8 * (16 - s));
   }
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
           cur = lo_i;
           const int64_t vs = L->vs[cur];
           if (p0 >= vs && p0 + 16 <= (int64_t)L->st[cur + 1]) {
-            __builtin_memcpy(&v[t], (const uint8_t*)L->vp[cur] + (p0 - vs), 16);
+            v[t] = ldg16(L->vp[cur] + (uint64_t)(p0 - vs));
           } else {
             slow |= 1u << t;
           }
@@ -318,6 +318,14 @@ __device__ inline void stage_varint(uint8_t* d, uint32_t v, uint32_t* k) {
   d[(*k)++] = (uint8_t)v;
 }
 
+// bytes [from, to) of a 128-bit little-endian value to LDS at d[from..to)
+__device__ inline void put_bytes(uint8_t* d, u128 v, uint32_t from, uint32_t to) {
+  const uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
+  for (uint32_t q = from; q < to; q++) d[q] = (uint8_t)(q < 8 ? (lo >> (8 * q)) : (hi >> (8 * (q - 8))));
+}
+
+constexpr uint32_t ENC_KW = 8;  // key slot words held in registers while staging
+
 __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   CrcLds* T = (CrcLds*)smem;
@@ -331,65 +339,78 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   uint8_t* stage_end = wbase + A.wave_lds;
   const uint64_t nb = *A.nblocks;
   for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
-    const uint32_t j = A.ob.job[b];
-    const uint32_t R = A.jobs[j].restart_interval;
-    const uint64_t s0 = A.ob.s0[b];
-    const uint32_t cnt = A.ob.cnt[b];
-    const uint32_t size = A.ob.size[b];
+    const BlockRec B = A.blk[b];
+    const uint32_t R = B.R, cnt = B.cnt, size = B.size;
+    const uint64_t s0 = B.s0;
     const uint32_t nrest = (cnt + R - 1) / R;
     const uint32_t data_end = size - 4 * nrest - 4;
     const uint32_t n = size + 1;
-    uint8_t* dst = A.out + A.of.out[A.ob.file[b]] + A.ob.off[b];
+    uint8_t* dst = A.out + B.dst;
     const uint32_t* blk_off = A.ent_off + s0;
     const uint32_t J16 = (n + 15) / 16;
-    uint8_t* base = stage_end - n;                    // message byte p at base[p]
-    const uint32_t gshift = 16 * J16 - n;             // chunk grid: positions = 16 m - gshift
+    uint8_t* base = stage_end - n;         // message byte p at base[p]
+    const uint32_t gshift = 16 * J16 - n;  // chunk grid: positions 16 m - gshift
     // --- entries, a window at a time
     for (uint32_t k0 = 0; k0 < cnt; k0 += ENC_W) {
       const uint32_t nw = min(cnt - k0, ENC_W);
-      uint32_t pieces = 0, a = 0;
-      if (l < nw) {
+      const bool own = l < nw;
+      uint32_t pieces = 0, a = 0, st = 0, vs = 0, en = 0, h_end = 0, t_beg = 0, shared = 0, ns = 0;
+      EncRec r;
+      r.vp = 0;
+      r.tag = 0;
+      r.e = 0;
+      r.shared = 0;
+      r.ulen = 0;
+      r.vlen = 0;
+      if (own) {
         const uint32_t i = k0 + l;
-        const uint64_t s = s0 + i;
-        const uint32_t e = A.surv[s];
-        const uint32_t shared = (i % R == 0) ? 0u : A.shr[s];
-        const uint32_t ul = A.tu.ulen[e];
-        const uint32_t vl = A.tu.vlen[e];
-        const uint32_t st = blk_off[i];
-        const uint32_t klen = ul + 8;
-        const uint32_t ns = klen - shared;
-        const uint8_t* vp = (const uint8_t*)A.tu.vp[e];
-        const uint64_t tag = A.tu.tag[e];
-        uint8_t* d = base + st;
-        uint32_t k = 0;
-        stage_varint(d, shared, &k);
-        stage_varint(d, ns, &k);
-        stage_varint(d, vl, &k);
-        stage_key_bytes(d + k, A.tu.heap + (uint64_t)e * A.kw8, ul, tag, shared, klen);
-        const uint32_t vs = st + k + ns, en = vs + vl;
+        r = A.rec[s0 + i];
+        st = blk_off[i];
+        shared = (i % R == 0) ? 0u : r.shared;
+        ns = r.ulen + 8 - shared;
+        vs = st + vlen32(shared) + vlen32(ns) + vlen32(r.vlen) + ns;
+        en = vs + r.vlen;
         // value interior: whole aligned chunks inside [vs, en); edges as
         // bytes.  a is the first grid position >= vs, z the last <= en (it
         // can lie before the message start, hence signed).
         a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
         const int64_t z = (int64_t)en - (int64_t)((en + gshift) & 15u);
-        uint32_t h_end = en, t_beg = en;
+        h_end = en;
+        t_beg = en;
         if ((int64_t)a + 16 <= z) {
           pieces = (uint32_t)((z - (int64_t)a) / 16);
           h_end = a;
           t_beg = (uint32_t)z;
         }
-        for (uint32_t q = vs; q < h_end; q++) base[q] = vp[q - vs];
-        for (uint32_t q = t_beg; q < en; q++) base[q] = vp[q - vs];
         L->vs[l] = vs;
-        L->vp[l] = (uint64_t)(uintptr_t)vp;
+        L->vp[l] = r.vp;
         L->st[l] = a;  // first interior chunk position
       }
       const uint32_t incl = wave_incl_scan(pieces);
-      if (l < nw) pc[l] = incl - pieces;
+      if (own) pc[l] = incl - pieces;
       const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
       if (l == 0) pc[nw] = total;
       wave_sync();
-      for (uint32_t k = l; k < total; k += WAVE) {
+      // owner lanes: loads for the header, key delta and value edges, all in
+      // flight together with the first interior copies
+      uint64_t kw[ENC_KW];
+      u128 e0 = 0, e1 = 0, e2 = 0;
+      const uint32_t w0 = shared >> 3, wl = (r.ulen + 7) >> 3;
+      if (own) {
+        const uint64_t* slot = A.tu.heap + (uint64_t)r.e * A.kw8;
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_KW; t++) kw[t] = (w0 + t < wl) ? slot[w0 + t] : 0ull;
+        const uint8_t* vp = (const uint8_t*)r.vp;
+        const uint32_t hn = h_end - vs, tn = en - t_beg;
+        if (hn) e0 = load_span(vp, min(hn, 16u));
+        if (hn > 16) e1 = load_span(vp + 16, hn - 16);
+        if (tn) e2 = load_span(vp + (t_beg - vs), tn);
+      }
+      uint4 v[ENC_B];
+#pragma unroll
+      for (uint32_t t = 0; t < ENC_B; t++) {
+        const uint32_t k = l + WAVE * t;
+        if (k >= total) continue;
         uint32_t lo = 0, hi = nw;  // pc[lo] <= k < pc[hi]
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
@@ -397,16 +418,65 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
           else hi = mid;
         }
         const uint32_t pos = L->st[lo] + 16 * (k - pc[lo]);
-        uint4 v;
-        __builtin_memcpy(&v, (const uint8_t*)L->vp[lo] + (pos - L->vs[lo]), 16);
-        *(uint4*)(base + pos) = v;
+        v[t] = ldg16(L->vp[lo] + (pos - L->vs[lo]));
+      }
+      if (own) {
+        uint8_t* d = base + st;
+        uint32_t k = 0;
+        stage_varint(d, shared, &k);
+        stage_varint(d, ns, &k);
+        stage_varint(d, r.vlen, &k);
+        d += k;
+        const uint32_t klen = r.ulen + 8;
+        for (uint32_t q = shared; q < klen; q++) {
+          uint32_t byte;
+          if (q < r.ulen) {
+            const uint32_t t = (q >> 3) - w0;
+            uint64_t word = 0;
+#pragma unroll
+            for (uint32_t u = 0; u < ENC_KW; u++)
+              if (u == t) word = kw[u];
+            if (t >= ENC_KW) word = A.tu.heap[(uint64_t)r.e * A.kw8 + (q >> 3)];
+            byte = (uint32_t)(word >> (8 * (q & 7))) & 0xFFu;
+          } else {
+            byte = (uint32_t)(r.tag >> (8 * (q - r.ulen))) & 0xFFu;
+          }
+          *d++ = (uint8_t)byte;
+        }
+        const uint32_t hn = h_end - vs, tn = en - t_beg;
+        put_bytes(base + vs, e0, 0, min(hn, 16u));
+        if (hn > 16) put_bytes(base + vs + 16, e1, 0, hn - 16);
+        put_bytes(base + t_beg, e2, 0, tn);
+      }
+#pragma unroll
+      for (uint32_t t = 0; t < ENC_B; t++) {
+        const uint32_t k = l + WAVE * t;
+        if (k >= total) continue;
+        uint32_t lo = 0, hi = nw;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (pc[mid] <= k) lo = mid;
+          else hi = mid;
+        }
+        *(uint4*)(base + L->st[lo] + 16 * (k - pc[lo])) = v[t];
+      }
+      // remaining interior chunks of long values
+      for (uint32_t k = l + WAVE * ENC_B; k < total; k += WAVE) {
+        uint32_t lo = 0, hi = nw;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (pc[mid] <= k) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t pos = L->st[lo] + 16 * (k - pc[lo]);
+        *(uint4*)(base + pos) = ldg16(L->vp[lo] + (pos - L->vs[lo]));
       }
       wave_sync();
     }
     // --- restart array, restart count, type byte
-    for (uint32_t r = l; r < nrest; r += WAVE) {
-      const uint32_t v = blk_off[(uint64_t)r * R];
-      uint8_t* d = base + data_end + 4 * r;
+    for (uint32_t rr = l; rr < nrest; rr += WAVE) {
+      const uint32_t v = blk_off[(uint64_t)rr * R];
+      uint8_t* d = base + data_end + 4 * rr;
       d[0] = (uint8_t)v;
       d[1] = (uint8_t)(v >> 8);
       d[2] = (uint8_t)(v >> 16);

@@ -75,6 +75,21 @@ __global__ void k_u32_to_u64(const uint32_t* a, uint64_t* b, uint64_t n) {
   if (i < n) b[i] = a[i];
 }
 
+// encoder records of the output blocks (after the file layout)
+__global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
+                            BlockRec* br) {
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= cap || b >= *nblocks) return;
+  BlockRec r;
+  r.dst = of.out[ob.file[b]] + ob.off[b];
+  r.s0 = ob.s0[b];
+  r.cnt = ob.cnt[b];
+  r.size = ob.size[b];
+  r.R = jobs[ob.job[b]].restart_interval;
+  r.pad = 0;
+  br[b] = r;
+}
+
 __global__ void k_file_entries(OutFiles of, OutBlocks ob, uint64_t nf) {
   const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;

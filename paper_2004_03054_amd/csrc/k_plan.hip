@@ -60,17 +60,26 @@ __device__ inline uint32_t lcp_ikeys(const Tuples& tu, uint32_t kw8, uint64_t a,
 // per survivor: shared prefix with the previous survivor of its job, and the
 // encoded entry size as a restart point and as a delta entry
 __global__ void k_prep(const uint32_t* surv, Tuples tu, uint32_t kw8, const uint64_t* job_s0, uint32_t J,
-                       uint64_t S, uint32_t* sz_r, uint32_t* sz_n, uint32_t* shr) {
+                       uint64_t S, uint32_t* sz_r, uint32_t* sz_n, uint32_t* shr, EncRec* rec) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const uint32_t j = job_of(job_s0, J, s);
   const uint64_t e = surv[s];
-  const uint32_t klen = tu.ulen[e] + 8;
+  const uint32_t ulen = tu.ulen[e];
+  const uint32_t klen = ulen + 8;
   const uint32_t vlen = tu.vlen[e];
   const uint32_t shared = (s == job_s0[j]) ? 0 : lcp_ikeys(tu, kw8, surv[s - 1], e);
   sz_r[s] = 1 + varint_len(klen) + varint_len(vlen) + klen + vlen;
   sz_n[s] = varint_len(shared) + varint_len(klen - shared) + varint_len(vlen) + (klen - shared) + vlen;
   shr[s] = shared;
+  EncRec r;
+  r.vp = tu.vp[e];
+  r.tag = tu.tag[e];
+  r.e = (uint32_t)e;
+  r.shared = shared;
+  r.ulen = ulen;
+  r.vlen = vlen;
+  rec[s] = r;
 }
 
 struct BlockNext {

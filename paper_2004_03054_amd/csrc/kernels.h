@@ -99,8 +99,9 @@ void launch_scan(const T* in, uint64_t cap, const uint64_t* n_dev, T* out, T* sc
 constexpr uint32_t MERGE_ITEMS_PER_THREAD = 8;
 
 // plan
+struct EncRec;
 __global__ void k_prep(const uint32_t* surv, Tuples tu, uint32_t kw8, const uint64_t* job_s0, uint32_t J,
-                       uint64_t S, uint32_t* sz_r, uint32_t* sz_n, uint32_t* shr);
+                       uint64_t S, uint32_t* sz_r, uint32_t* sz_n, uint32_t* shr, EncRec* rec);
 struct BlockNext;
 struct FileNext;
 void launch_seg_exit_blocks(const SegChunk* ch, const uint32_t* nch_dev, uint32_t grid, const SegJob* sj,
@@ -133,6 +134,26 @@ __global__ void k_file_layout(const uint64_t* nfiles_total, OutFiles of, const u
                               const uint64_t* ie_off, uint64_t cap);
 
 // encode
+// per survivor, written by k_prep for the encoder
+struct EncRec {
+  uint64_t vp;      // value address
+  uint64_t tag;
+  uint32_t e;       // decoded entry (key slot)
+  uint32_t shared;  // key bytes shared with the previous survivor of its job
+  uint32_t ulen;
+  uint32_t vlen;
+};
+// per output block, written by k_block_dst for the encoder
+struct BlockRec {
+  uint64_t dst;  // offset in the output buffer
+  uint64_t s0;   // first survivor
+  uint32_t cnt;
+  uint32_t size;  // contents bytes (trailer excluded)
+  uint32_t R;     // restart interval
+  uint32_t pad;
+};
+__global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
+                            BlockRec* br);
 struct EncodeArgs {
   const JobDesc* jobs;
   OutBlocks ob;
@@ -146,6 +167,8 @@ struct EncodeArgs {
   uint8_t* out;
   const uint32_t* g_crc;
   const uint32_t* ent_off;  // each survivor's entry offset inside its block
+  const EncRec* rec;
+  const BlockRec* blk;
   uint32_t kw8;
   uint32_t wave_lds;        // staged encoder: LDS bytes per wave (multiple of 16)
 };

@@ -417,8 +417,9 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   uint32_t* sz_r = dbuf<uint32_t>(c, "sz_r", S);
   uint32_t* sz_n = dbuf<uint32_t>(c, "sz_n", S);
   uint32_t* shr = dbuf<uint32_t>(c, "shr", S);
+  EncRec* erec = dbuf<EncRec>(c, "enc_rec", S);
   hipLaunchKernelGGL(k_prep, dim3(blocks_for(S)), dim3(256), 0, st, P.d_surv, P.tu, P.kw8, P.d_job_s0, J, S, sz_r,
-                     sz_n, shr);
+                     sz_n, shr, erec);
   LAUNCH_CHECK();
   mark(c, "prep");
 
@@ -589,6 +590,9 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, NF);
   LAUNCH_CHECK();
+  BlockRec* brec = dbuf<BlockRec>(c, "blk_rec", NBLK);
+  hipLaunchKernelGGL(k_block_dst, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.d_jobs, job_ob0 + J, NBLK, brec);
+  LAUNCH_CHECK();
   O.file_out.assign(NF + 1, 0);
   O.file_entries.assign(NF, 0);
   uint32_t max_win = 0;
@@ -631,6 +635,8 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.out = out;
     A.g_crc = c->d_crc;
     A.ent_off = ent_off;
+    A.rec = erec;
+    A.blk = brec;
     A.kw8 = P.kw8;
     // staged encoder when a block message (plus the entry window) fits in
     // LDS for at least two waves; otherwise the register generator
