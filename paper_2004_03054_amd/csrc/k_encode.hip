@@ -7,8 +7,8 @@
 //   k_encode       one wave per output data block: assembles the block in an
 //                  LDS stage (value interiors as aligned 16-byte copies,
 //                  headers, keys, value edges and the tail as bytes), then
-//                  stores it in 16-byte chunks aligned to the block end and
-//                  folds each chunk into the block's CRC in registers
+//                  stores it in 64-byte units aligned to the block end and
+//                  folds each unit into the block's CRC in registers
 //   k_encode_gen   the same bytes for blocks too large for the stage: every
 //                  chunk is generated in registers from the entry records
 //   k_key_hash     one thread per surviving key: its XXH64
@@ -161,7 +161,9 @@ __device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t nw, uint32_t i, int64_
 // starts 8 entries before the previous one ended, so a chunk assigned to a
 // window (by its first byte) never reaches past the window's entries (an
 // entry is at least 4 bytes).
-constexpr uint32_t ENC_B = 2;  // chunks per lane in flight
+constexpr uint32_t ENC_B = 1;  // interior chunks per lane in flight with the owner loads
+
+constexpr uint32_t ENC_OVERLAP = 16;  // entries shared by consecutive windows (>= 64 bytes)
 
 __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -170,22 +172,21 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
   __syncthreads();
   const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
   const uint32_t waves = blockDim.x / WAVE;
+  const uint32_t* tl = crc_lane_table(T);
   EncLds* L = (EncLds*)(smem + sizeof(CrcLds)) + wv;
   const uint64_t nb = *A.nblocks;
   for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
-    const uint32_t j = A.ob.job[b];
-    const uint32_t R = A.jobs[j].restart_interval;
-    const uint64_t s0 = A.ob.s0[b];
-    const uint32_t cnt = A.ob.cnt[b];
-    const uint32_t size = A.ob.size[b];
+    const BlockRec B = A.blk[b];
+    const uint32_t R = B.R, cnt = B.cnt, size = B.size;
+    const uint64_t s0 = B.s0;
     const uint32_t nrest = (cnt + R - 1) / R;
     const uint32_t data_end = size - 4 * nrest - 4;
     const int64_t n = (int64_t)size + 1;
-    uint8_t* dst = A.out + A.of.out[A.ob.file[b]] + A.ob.off[b];
+    uint8_t* dst = A.out + B.dst;
     const uint32_t* blk_off = A.ent_off + s0;
-    const int64_t J16 = (n + 15) / 16;
-    const int64_t c_first = 63 - (int64_t)l;
-    int64_t cc = c_first < J16 ? c_first + 64 * ((J16 - 1 - c_first) / 64) : -1;
+    const int64_t JU = (n + CRC_UNIT - 1) / CRC_UNIT;
+    const int64_t u_first = 63 - (int64_t)l;
+    int64_t uu = u_first < JU ? u_first + 64 * ((JU - 1 - u_first) / 64) : -1;
     uint32_t acc = 0;
     uint32_t k0 = 0;
     for (;;) {
@@ -194,36 +195,36 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
       const bool last = (k1 == cnt);
       if (l < nw) {
         const uint32_t i = k0 + l;
-        const uint64_t s = s0 + i;
-        const uint32_t e = A.surv[s];
-        const uint32_t shared = (i % R == 0) ? 0u : A.shr[s];
-        const uint32_t ul = A.tu.ulen[e];
-        const uint32_t vl = A.tu.vlen[e];
+        const EncRec r = A.rec[s0 + i];
+        const uint32_t shared = (i % R == 0) ? 0u : r.shared;
         const uint32_t st = blk_off[i];
-        const uint32_t ns = ul + 8 - shared;
+        const uint32_t ns = r.ulen + 8 - shared;
         L->st[l] = st;
-        L->vs[l] = st + vlen32(shared) + vlen32(ns) + vlen32(vl) + ns;
-        L->e[l] = e;
+        L->vs[l] = st + vlen32(shared) + vlen32(ns) + vlen32(r.vlen) + ns;
+        L->e[l] = r.e;
         L->sh[l] = shared;
-        L->ul[l] = ul;
-        L->vp[l] = A.tu.vp[e];
-        L->tag[l] = A.tu.tag[e];
+        L->ul[l] = r.ulen;
+        L->vp[l] = r.vp;
+        L->tag[l] = r.tag;
       }
       if (l == 0) L->st[nw] = last ? data_end : blk_off[k1];
       wave_sync();
-      const int64_t hi = last ? n : (int64_t)L->st[nw - 8];
+      // units assigned to this window by their first byte; a unit never
+      // reaches past the window's entries (the next window starts
+      // ENC_OVERLAP entries, at least 64 bytes, earlier)
+      const int64_t hi = last ? n : (int64_t)L->st[nw - ENC_OVERLAP];
       uint32_t cur = 0;
-      while (cc >= 0) {
-        // up to ENC_B of this lane's chunks at once: their loads are in
-        // flight together, then they are stored and folded in order
-        uint4 v[ENC_B];
-        uint32_t m = 0, slow = 0;
+      while (uu >= 0) {
+        const int64_t p = n - (int64_t)CRC_UNIT * (uu + 1);
+        if ((p < 0 ? 0 : p) >= hi) break;
+        uint4 v[4];
+        uint32_t slow = 0;
 #pragma unroll
-        for (uint32_t t = 0; t < ENC_B; t++) {
-          const int64_t c = cc - 64 * (int64_t)t;
-          const int64_t p0 = n - 16 * (c + 1);
+        for (uint32_t q = 0; q < 4; q++) {
+          const int64_t p0 = p + 16 * q;
+          v[q] = make_uint4(0, 0, 0, 0);
+          if (p0 + 16 <= 0) continue;
           const int64_t P = p0 < 0 ? 0 : p0;
-          if (c < 0 || P >= hi || m != t) continue;
           // entry holding P: the last with st <= P (from the lane's cursor)
           uint32_t lo_i = cur, hi_i = nw;
           while (hi_i - lo_i > 1) {
@@ -233,18 +234,14 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
           }
           cur = lo_i;
           const int64_t vs = L->vs[cur];
-          if (p0 >= vs && p0 + 16 <= (int64_t)L->st[cur + 1]) {
-            v[t] = ldg16(L->vp[cur] + (uint64_t)(p0 - vs));
-          } else {
-            slow |= 1u << t;
-          }
-          m = t + 1;
+          if (p0 >= vs && p0 + 16 <= (int64_t)L->st[cur + 1]) v[q] = ldg16(L->vp[cur] + (uint64_t)(p0 - vs));
+          else slow |= 1u << q;
         }
         // chunks that cross a segment boundary, one at a time
         while (slow) {
-          const uint32_t t = __builtin_ctz(slow);
+          const uint32_t q = __builtin_ctz(slow);
           slow &= slow - 1;
-          const int64_t p0 = n - 16 * (cc - 64 * (int64_t)t + 1);
+          const int64_t p0 = p + 16 * q;
           const int64_t P = p0 < 0 ? 0 : p0;
           uint32_t lo_i = 0, hi_i = nw;
           while (hi_i - lo_i > 1) {
@@ -254,28 +251,26 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
           }
           const uint4 r = enc_chunk_slow(L, nw, lo_i, p0, data_end, (uint32_t)size, nrest, R, blk_off, A.tu.heap, A.kw8);
 #pragma unroll
-          for (uint32_t u = 0; u < ENC_B; u++)
-            if (u == t) v[u] = r;
+          for (uint32_t u = 0; u < 4; u++)
+            if (u == q) v[u] = r;
         }
 #pragma unroll
-        for (uint32_t t = 0; t < ENC_B; t++) {
-          if (t >= m) continue;
-          const int64_t p0 = n - 16 * (cc - 64 * (int64_t)t + 1);
+        for (uint32_t q = 0; q < 4; q++) {
+          const int64_t p0 = p + 16 * q;
           if (p0 >= 0) {
-            __builtin_memcpy(dst + p0, &v[t], 16);
-          } else {
-            const uint8_t* vb = (const uint8_t*)&v[t];
+            __builtin_memcpy(dst + p0, &v[q], 16);
+          } else if (p0 + 16 > 0) {
+            const uint8_t* vb = (const uint8_t*)&v[q];
             for (int k = 0; k < 16; k++)
               if (p0 + k >= 0) dst[p0 + k] = vb[k];
           }
-          acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v[t], p0);
         }
-        cc -= 64 * (int64_t)m;
-        if (m < ENC_B) break;
+        acc = crc_shift(T, 6, acc) ^ crc_unit(tl, v, p);
+        uu -= 64;
       }
       wave_sync();
       if (last) break;
-      k0 = k1 - 8;
+      k0 = k1 - ENC_OVERLAP;
     }
     const uint32_t raw = crc_wave_join(T, acc);
     if (l == 0) {
@@ -324,7 +319,7 @@ __device__ inline void put_bytes(uint8_t* d, u128 v, uint32_t from, uint32_t to)
   for (uint32_t q = from; q < to; q++) d[q] = (uint8_t)(q < 8 ? (lo >> (8 * q)) : (hi >> (8 * (q - 8))));
 }
 
-constexpr uint32_t ENC_KW = 8;  // key slot words held in registers while staging
+constexpr uint32_t ENC_KW = 4;  // key slot words held in registers while staging
 
 __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -428,15 +423,21 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
         stage_varint(d, r.vlen, &k);
         d += k;
         const uint32_t klen = r.ulen + 8;
+        uint64_t word = 0;
+        uint32_t wcur = 0xFFFFFFFFu;
         for (uint32_t q = shared; q < klen; q++) {
           uint32_t byte;
           if (q < r.ulen) {
-            const uint32_t t = (q >> 3) - w0;
-            uint64_t word = 0;
+            const uint32_t wi = q >> 3;
+            if (wi != wcur) {
+              wcur = wi;
+              const uint32_t t = wi - w0;
+              word = 0;
 #pragma unroll
-            for (uint32_t u = 0; u < ENC_KW; u++)
-              if (u == t) word = kw[u];
-            if (t >= ENC_KW) word = A.tu.heap[(uint64_t)r.e * A.kw8 + (q >> 3)];
+              for (uint32_t u = 0; u < ENC_KW; u++)
+                if (u == t) word = kw[u];
+              if (t >= ENC_KW) word = A.tu.heap[(uint64_t)r.e * A.kw8 + wi];
+            }
             byte = (uint32_t)(word >> (8 * (q & 7))) & 0xFFu;
           } else {
             byte = (uint32_t)(r.tag >> (8 * (q - r.ulen))) & 0xFFu;
@@ -491,21 +492,29 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
       d[4] = 0;
     }
     wave_sync();
-    // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i
+    // --- store and checksum: lane l takes the 64-byte units u = 63 - l + 64 i
     uint32_t acc = 0;
-    const int64_t c_first = 63 - (int64_t)l;
-    if (c_first < (int64_t)J16) {
-      for (int64_t c = c_first + 64 * (((int64_t)J16 - 1 - c_first) / 64); c >= 0; c -= 64) {
-        const int64_t p0 = (int64_t)n - 16 * (c + 1);
-        const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
-        if (p0 >= 0) {
-          __builtin_memcpy(dst + p0, &v, 16);
-        } else {
-          const uint8_t* vb = (const uint8_t*)&v;
-          for (int k = 0; k < 16; k++)
-            if (p0 + k >= 0) dst[p0 + k] = vb[k];
+    const uint32_t* tl = crc_lane_table(T);
+    const int64_t JU = ((int64_t)n + CRC_UNIT - 1) / CRC_UNIT;
+    const int64_t u_first = 63 - (int64_t)l;
+    if (u_first < JU) {
+      for (int64_t u = u_first + 64 * ((JU - 1 - u_first) / 64); u >= 0; u -= 64) {
+        const int64_t p = (int64_t)n - (int64_t)CRC_UNIT * (u + 1);
+        const uint8_t* src = stage_end - CRC_UNIT * (u + 1);
+        uint4 v[4];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; q++) {
+          v[q] = *(const uint4*)(src + 16 * q);
+          const int64_t p0 = p + 16 * q;
+          if (p0 >= 0) {
+            __builtin_memcpy(dst + p0, &v[q], 16);
+          } else if (p0 + 16 > 0) {
+            const uint8_t* vb = (const uint8_t*)&v[q];
+            for (int k = 0; k < 16; k++)
+              if (p0 + k >= 0) dst[p0 + k] = vb[k];
+          }
         }
-        acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
+        acc = crc_shift(T, 6, acc) ^ crc_unit(tl, v, p);
       }
     }
     const uint32_t raw = crc_wave_join(T, acc);

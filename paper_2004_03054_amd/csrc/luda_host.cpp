@@ -26,9 +26,10 @@ using namespace luda;
 namespace {
 
 // ---------------------------------------------------------------------------
-// CRC32C tables built on the host: slicing-by-4 and "shift by 16 * 2^k zero
-// bytes" (k = 0..6), each a set of four 256-entry tables indexed by the bytes
-// of the 32-bit register.  The device copies this image into LDS.
+// CRC32C tables built on the host and copied into LDS by the kernels: the
+// byte table in 32 copies (one per LDS bank; entry x of copy j at word
+// 32 x + j), and shifts by 64 * 2^k zero bytes (k = 0..6) applied by
+// nibbles: sh[k][j][v] = shift of (v << 4 j).
 
 constexpr uint32_t POLY = 0x82F63B78u;  // CRC32C, reflected
 constexpr int NSH = 7;
@@ -36,37 +37,38 @@ constexpr int NSH = 7;
 uint32_t step_byte(uint32_t r, uint8_t b, const uint32_t* t0) { return t0[(r ^ b) & 0xFF] ^ (r >> 8); }
 
 struct CrcTables {
-  uint32_t t4[4][256];
-  uint32_t sh[NSH][4][256];
+  uint32_t t[256][32];
+  uint32_t sh[NSH][8][16];
 };
 constexpr size_t CRC_LDS_BYTES = sizeof(CrcTables);
 
-uint32_t apply_shift(const uint32_t sh[4][256], uint32_t c) {
-  return sh[0][c & 0xFF] ^ sh[1][(c >> 8) & 0xFF] ^ sh[2][(c >> 16) & 0xFF] ^ sh[3][c >> 24];
-}
-
-void build_crc_tables(CrcTables* T) {
-  uint32_t t0[256];
+void byte_table(uint32_t* t0) {
   for (uint32_t b = 0; b < 256; b++) {
     uint32_t r = b;
     for (int k = 0; k < 8; k++) r = (r >> 1) ^ (POLY & (0u - (r & 1u)));
     t0[b] = r;
   }
-  for (int b = 0; b < 256; b++) T->t4[0][b] = t0[b];
-  for (int k = 1; k < 4; k++)
-    for (int b = 0; b < 256; b++) T->t4[k][b] = (T->t4[k - 1][b] >> 8) ^ t0[T->t4[k - 1][b] & 0xFF];
-  // shift by 16 zero bytes, directly
-  for (int i = 0; i < 4; i++)
-    for (uint32_t v = 0; v < 256; v++) {
-      uint32_t r = v << (8 * i);
-      for (int z = 0; z < 16; z++) r = step_byte(r, 0, t0);
-      T->sh[0][i][v] = r;
-    }
-  // shift by 2m = shift by m, twice
-  for (int k = 1; k < NSH; k++)
-    for (int i = 0; i < 4; i++)
-      for (uint32_t v = 0; v < 256; v++)
-        T->sh[k][i][v] = apply_shift(T->sh[k - 1], apply_shift(T->sh[k - 1], v << (8 * i)));
+}
+
+uint32_t shift_zeros(uint32_t r, uint64_t m, const uint32_t* t0) {
+  for (uint64_t z = 0; z < m; z++) r = step_byte(r, 0, t0);
+  return r;
+}
+
+uint32_t apply_shift(const uint32_t sh[8][16], uint32_t c) {
+  uint32_t r = 0;
+  for (int j = 0; j < 8; j++) r ^= sh[j][(c >> (4 * j)) & 15];
+  return r;
+}
+
+void build_crc_tables(CrcTables* T) {
+  uint32_t t0[256];
+  byte_table(t0);
+  for (int x = 0; x < 256; x++)
+    for (int j = 0; j < 32; j++) T->t[x][j] = t0[x];
+  for (int k = 0; k < NSH; k++)
+    for (int j = 0; j < 8; j++)
+      for (uint32_t v = 0; v < 16; v++) T->sh[k][j][v] = shift_zeros(v << (4 * j), 64ull << k, t0);
 }
 
 // GF(2) products mod P in the reflected representation, for the self check
@@ -641,7 +643,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     // staged encoder when a block message (plus the entry window) fits in
     // LDS for at least two waves; otherwise the register generator
     const size_t win = sizeof(EncLds) + ((4 * (ENC_W + 1) + 15) & ~size_t(15));
-    const size_t per_wave = win + ((size_t(max_bsize) + 1 + 15) & ~size_t(15)) + 16;
+    const size_t per_wave = win + ((size_t(max_bsize) + 1 + CRC_UNIT - 1) / CRC_UNIT) * CRC_UNIT + 64;
     const size_t budget = c->lds_limit - 2048 - CRC_LDS_BYTES;
     const size_t sw = std::min<size_t>(16, budget / per_wave);
     const bool staged = sw >= 2 && per_wave < (1u << 31);
@@ -1250,29 +1252,28 @@ int luda_selftest_crc(void) {
   static CrcTables T;
   build_crc_tables(&T);
   uint32_t t0[256];
-  for (uint32_t b = 0; b < 256; b++) t0[b] = T.t4[0][b];
+  byte_table(t0);
+  // every bank copy of the byte table is the table
+  for (int x = 0; x < 256; x++)
+    for (int j = 0; j < 32; j++)
+      if (T.t[x][j] != t0[x]) return 1;
+  // the byte table against the bitwise definition on one byte
+  for (uint32_t b = 0; b < 256; b += 51) {
+    uint32_t r = b;
+    for (int k = 0; k < 8; k++) r = (r & 1u) ? (r >> 1) ^ POLY : (r >> 1);
+    if (t0[b] != r) return 2;
+  }
   // shift tables and GF(2) multipliers against zero-byte processing
   uint32_t x = 0x12345678u;
   for (int k = 0; k < NSH; k++) {
-    uint32_t r = x;
-    const int m = 16 << k;
-    for (int z = 0; z < m; z++) r = step_byte(r, 0, t0);
-    if (apply_shift(T.sh[k], x) != r) return 1;
-    if (h_mulmod(x, h_xpow8n((uint64_t)m)) != r) return 3;
+    const uint64_t m = 64ull << k;
+    const uint32_t r = shift_zeros(x, m, t0);
+    if (apply_shift(T.sh[k], x) != r) return 3;
+    if (h_mulmod(x, h_xpow8n(m)) != r) return 4;
     x = x * 2654435761u + 12345u;
   }
-  for (uint64_t m = 1; m < 300; m += 37) {
-    uint32_t r = x;
-    for (uint64_t z = 0; z < m; z++) r = step_byte(r, 0, t0);
-    if (h_mulmod(x, h_xpow8n(m)) != r) return 4;
-  }
-  // slicing-by-4 against bytewise on one dword
-  uint32_t c = 0xDEADBEEFu, d = 0x01020304u;
-  uint32_t r = c;
-  for (int i = 0; i < 4; i++) r = step_byte(r, (uint8_t)(d >> (8 * i)), t0);
-  uint32_t y = c ^ d;
-  uint32_t s = T.t4[3][y & 0xFF] ^ T.t4[2][(y >> 8) & 0xFF] ^ T.t4[1][(y >> 16) & 0xFF] ^ T.t4[0][y >> 24];
-  if (r != s) return 2;
+  for (uint64_t m = 1; m < 300; m += 37)
+    if (h_mulmod(x, h_xpow8n(m)) != shift_zeros(x, m, t0)) return 5;
   return 0;
 }
 
