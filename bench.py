@@ -50,6 +50,20 @@ def device_tables(ctx, job):
     return tables
 
 
+def fingerprint(t) -> int:
+    """A 64-bit fingerprint of device bytes (for comparing outputs without
+    copying them to the host)."""
+    import torch
+    n = t.numel()
+    pad = (-n) % 8
+    if pad:
+        t = torch.cat([t, torch.zeros(pad, dtype=torch.uint8, device=t.device)])
+    w = t.view(torch.int64)
+    idx = torch.arange(w.numel(), dtype=torch.int64, device=t.device)
+    mult = idx * 0x5851F42D4C957F2D + 0x14057B7EF767814F  # wraps mod 2^64
+    return int(((w ^ (w >> 29)) * (mult | 1)).sum().item()) ^ n
+
+
 def kernel_times(ctx):
     """Device time of each timed kernel in the last call (launches of the same
     kernel, e.g. merge rounds, summed)."""
@@ -69,12 +83,19 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="table size scale (1.0 = 64 MiB tables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=3)
+    ap.add_argument("--mode", choices=["plain", "batch"], default="plain",
+                    help="plain: one large compaction (default); batch: many uneven jobs, "
+                         "one batched pass vs one call per job")
+    ap.add_argument("--jobs", type=int, default=256, help="batch mode: number of jobs")
+    ap.add_argument("--oracle-jobs", type=int, default=2, help="batch mode: jobs checked against the oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (jobs are independent: "
               "several GPUs would each run their own jobs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "batch":
+        return batch_main(args)
     import numpy as np
     import torch
     from paper_2004_03054_amd import Context
@@ -195,6 +216,104 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kavg.items()},
         "kernels": other,
         "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def batch_main(args):
+    """Many independent uneven jobs: one batched pass over every stage vs one
+    plain call per job, on the same device-resident inputs."""
+    import numpy as np
+    import torch
+    from paper_2004_03054_amd import Context
+    from workload import config3_job
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = Context(0)
+    jobs, tables, in_bytes = [], [], 0
+    t0 = time.time()
+    for j in range(args.jobs):
+        job = config3_job(j, scale=args.scale)
+        tabs = device_tables(ctx, job)
+        tables.append(tabs)
+        jobs.append((job.name, job.options()))
+        in_bytes += sum(int(t.numel()) for t in tabs)
+        del job
+        if (j + 1) % 16 == 0:
+            log(f"[bench] {j + 1} jobs on the device, {in_bytes / 2**30:.2f} GiB, {time.time() - t0:.0f}s")
+    log(f"[bench] {args.jobs} jobs, {in_bytes / 2**30:.2f} GiB of input tables resident")
+    batch = [(tables[j], jobs[j][1]) for j in range(args.jobs)]
+    # verification pass (outside timing): batched outputs == per-job outputs
+    res_b = ctx.compact_batch(batch, device_inputs=True, materialize=fingerprint)
+    fp_b = [r.files for r in res_b]
+    status_b = [r.status for r in res_b]
+    del res_b
+    fp_p = []
+    for j in range(args.jobs):
+        r = ctx.compact_dev(tables[j], jobs[j][1], materialize=fingerprint)
+        fp_p.append(r.files)
+        assert r.status == 0 and status_b[j] == 0, (j, r.name, ctx.last_error())
+    same = fp_p == fp_b
+    log(f"[bench] batched outputs identical to per-job outputs: {same}")
+    torch.cuda.synchronize()
+    # timed: plain loop, then batched
+    steps = max(1, args.steps)
+    tp = time.perf_counter()
+    for _ in range(steps):
+        for j in range(args.jobs):
+            ctx.compact_dev(tables[j], jobs[j][1], materialize=False)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - tp) / steps
+    tb = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.compact_batch(batch, device_inputs=True, materialize=False)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - tb) / steps
+    assert all(r.status == 0 for r in out)
+    value = in_bytes / batch_s / 1e9
+    plain = in_bytes / plain_s / 1e9
+    log(f"[bench] batched {batch_s * 1e3:.1f} ms ({value:.1f} GB/s), plain loop {plain_s * 1e3:.1f} ms "
+        f"({plain:.1f} GB/s)")
+    kt = kernel_times(ctx)
+    cpu = None
+    if args.oracle_jobs > 0:
+        import oracle
+        from workload import config3_job as mk
+        tot_b, tot_t, exact = 0, 0.0, True
+        for j in range(args.oracle_jobs):
+            job = mk(j, scale=args.scale)
+            ins = oracle.build_input_tables(job)
+            host = [t.cpu().numpy().tobytes() for t in tables[j]]
+            t2 = time.perf_counter()
+            ref = oracle.compact(ins, job.options())
+            tot_t += time.perf_counter() - t2
+            tot_b += sum(len(x) for x in ins)
+            r = ctx.compact(host, job.options())
+            exact = exact and ins == host and ref.status == 0 and ref.files == r.files
+        cpu = {"value": round(tot_b / tot_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"jobs 0..{args.oracle_jobs - 1} of the batch ({tot_b / 2**20:.0f} MiB), {tot_t:.1f} s",
+               "bit_exact": bool(exact)}
+    out = {
+        "metric": "compaction input GB/s (batched)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": round(batch_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"batch-{args.jobs}-jobs" + ("" if args.scale == 1.0 else f"-scale{args.scale:g}"),
+                   "jobs": args.jobs, "input_bytes": in_bytes, "inputs_resident": "hbm", "outputs": "hbm"},
+        "plain_loop_gbps": round(plain, 2),
+        "batched_over_plain": round(plain_s / batch_s, 3),
+        "outputs_identical": bool(same),
+        "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

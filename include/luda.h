@@ -172,6 +172,50 @@ int luda_debug_read(luda_ctx *ctx, const char *name, void *dst, uint64_t offset,
 /* Host-side self check of the CRC32C shift tables (no device needed). */
 int luda_selftest_crc(void);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop in front of the batched compaction.  Jobs are
+ * submitted as they arrive (any thread); a job is admitted when the device
+ * memory it is expected to hold (its working set and outputs, estimated as
+ * 2 x its input bytes) fits under the budget beside the jobs already
+ * admitted.  Each worker (its own context and HIP stream) repeatedly takes
+ * the admitted jobs waiting at that moment, up to max_batch_jobs, and runs
+ * them as one batched pass (luda_compact_batch); with several workers,
+ * batches that arrive while others are on the GPU run on the device at the
+ * same time.  A job's outputs are identical to those of luda_compact_dev on
+ * the same inputs, whatever it is batched with.
+ */
+typedef struct luda_server luda_server;
+
+typedef struct {
+  uint64_t hbm_budget;     /* bytes (> 0) */
+  uint32_t max_batch_jobs; /* jobs per batched pass; 0 = no limit */
+  uint32_t workers;        /* concurrent batched passes (1..8) */
+  uint32_t host_outputs;   /* 1: results are copied to host memory before completion */
+} luda_server_cfg;
+
+/* Create a server on a HIP device.  LUDA_INVALID_ARG for a bad config. */
+int luda_server_create(int device, const luda_server_cfg *cfg, luda_server **out);
+
+/* Submit a job whose inputs are in device memory; the input bytes are
+ * borrowed until the job completes (the descriptor is copied).  Returns
+ * LUDA_OK and a ticket, or LUDA_INVALID_ARG. */
+int luda_server_submit(luda_server *s, const luda_job *job, uint64_t *ticket);
+
+/* Collect a job: with wait != 0 blocks until it completes.  Returns LUDA_OK
+ * and moves its result into *out (free it with luda_result_free(NULL, out)),
+ * 1 if it has not completed (wait == 0), or LUDA_INVALID_ARG for an unknown
+ * ticket.  *latency_ms (may be NULL) receives completion minus submission
+ * time. */
+int luda_server_poll(luda_server *s, uint64_t ticket, int wait, luda_result *out, double *latency_ms);
+
+/* Counters since creation: jobs completed, batched passes run, the largest
+ * batch, and the peak of admitted bytes.  Returns the number of values. */
+int luda_server_stats(luda_server *s, uint64_t *jobs, uint64_t *batches, uint64_t *max_batch,
+                      uint64_t *peak_admitted);
+
+/* Stop the workers (after the jobs already submitted) and free the server. */
+void luda_server_destroy(luda_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,9 +52,16 @@ class LudaJob(C.Structure):
     _fields_ = [("inputs", C.POINTER(LudaBuf)), ("n_inputs", C.c_uint32), ("options", LudaOptions)]
 
 
+class LudaServerCfg(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_batch_jobs", C.c_uint32), ("workers", C.c_uint32),
+                ("host_outputs", C.c_uint32)]
+
+
 EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compact", "luda_compact_dev",
            "luda_compact_batch", "luda_build_tables_dev", "luda_result_free", "luda_status_str",
-           "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters"]
+           "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters",
+           "luda_server_create", "luda_server_submit", "luda_server_poll", "luda_server_stats",
+           "luda_server_destroy"]
 
 _lib = None
 
@@ -96,6 +103,16 @@ def lib():
     L.luda_debug_read.restype = C.c_int
     L.luda_selftest_crc.argtypes = []
     L.luda_selftest_crc.restype = C.c_int
+    L.luda_server_create.argtypes = [C.c_int, C.POINTER(LudaServerCfg), C.POINTER(C.c_void_p)]
+    L.luda_server_create.restype = C.c_int
+    L.luda_server_submit.argtypes = [C.c_void_p, C.POINTER(LudaJob), C.POINTER(C.c_uint64)]
+    L.luda_server_submit.restype = C.c_int
+    L.luda_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.POINTER(LudaResult), C.POINTER(C.c_double)]
+    L.luda_server_poll.restype = C.c_int
+    L.luda_server_stats.argtypes = [C.c_void_p] + [C.POINTER(C.c_uint64)] * 4
+    L.luda_server_stats.restype = C.c_int
+    L.luda_server_destroy.argtypes = [C.c_void_p]
+    L.luda_server_destroy.restype = None
     _lib = L
     return L
 
@@ -153,7 +170,17 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
                  entries_in=r.entries_in, entries_out=r.entries_out, dropped_shadowed=r.dropped_shadowed,
                  dropped_tombstones=r.dropped_tombstones, bytes_in=r.bytes_in, bytes_out=r.bytes_out,
                  ms_total=r.ms_total)
-    if r.status == 0 and r.num_files and not materialize:
+    if r.status == 0 and r.num_files and callable(materialize):
+        # apply a function to each device output table in place (no copy)
+        import torch  # device memory plumbing only
+        for i in range(r.num_files):
+            f = r.files[i]
+            res.file_entries.append(f.num_entries)
+            res.file_sizes.append(f.size)
+            t = (torch.as_tensor(_DevView(r.data + f.offset, f.size), device="cuda") if f.size and device
+                 else torch.empty(0, dtype=torch.uint8, device="cuda"))
+            res.files.append(materialize(t))
+    elif r.status == 0 and r.num_files and not materialize:
         res.files = [None] * r.num_files
         res.file_entries = [r.files[i].num_entries for i in range(r.num_files)]
         res.file_sizes = [r.files[i].size for i in range(r.num_files)]
@@ -303,3 +330,60 @@ class Context:
 
 def selftest_crc() -> int:
     return lib().luda_selftest_crc()
+
+
+class Server:
+    """The served form: jobs with device inputs are submitted as they arrive
+    and collected by ticket (luda_server_* of include/luda.h)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 64 << 30, max_batch_jobs: int = 0, workers: int = 2,
+                 host_outputs: bool = True):
+        self._h = C.c_void_p()
+        cfg = LudaServerCfg(hbm_budget, max_batch_jobs, workers, 1 if host_outputs else 0)
+        rc = lib().luda_server_create(device, C.byref(cfg), C.byref(self._h))
+        if rc != 0:
+            raise RuntimeError(f"luda_server_create failed: {STATUS.get(rc, rc)}")
+        self._host = host_outputs
+        self._keep = {}
+
+    def submit(self, inputs: Sequence, opts: dict) -> int:
+        """inputs: torch uint8 cuda tensors (kept alive until collected)."""
+        bufs = _dev_bufs(inputs)
+        job = LudaJob()
+        job.inputs = C.cast(bufs, C.POINTER(LudaBuf))
+        job.n_inputs = len(inputs)
+        job.options = options(opts)
+        t = C.c_uint64()
+        rc = lib().luda_server_submit(self._h, C.byref(job), C.byref(t))
+        if rc != 0:
+            raise RuntimeError(f"luda_server_submit failed: {STATUS.get(rc, rc)}")
+        self._keep[t.value] = (bufs, list(inputs))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True, materialize=True):
+        """(Result, latency_ms), or None if not complete (wait=False)."""
+        r = LudaResult()
+        lat = C.c_double()
+        rc = lib().luda_server_poll(self._h, ticket, 1 if wait else 0, C.byref(r), C.byref(lat))
+        if rc == 1:
+            return None
+        if rc != 0:
+            raise RuntimeError(f"luda_server_poll failed: {STATUS.get(rc, rc)}")
+        self._keep.pop(ticket, None)
+        return _take(None, r, device=not self._host, materialize=materialize), lat.value
+
+    def stats(self) -> dict:
+        v = [C.c_uint64() for _ in range(4)]
+        lib().luda_server_stats(self._h, *[C.byref(x) for x in v])
+        return dict(jobs=v[0].value, batches=v[1].value, max_batch=v[2].value, peak_admitted=v[3].value)
+
+    def close(self):
+        if self._h:
+            lib().luda_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

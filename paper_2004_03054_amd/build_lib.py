@@ -18,14 +18,15 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libluda.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_decode.hip", "k_merge.hip", "k_plan.hip", "k_encode.hip", "k_misc.hip", "luda_host.cpp"]
+SOURCES = ["k_decode.hip", "k_merge.hip", "k_plan.hip", "k_encode.hip", "k_misc.hip", "luda_host.cpp",
+           "luda_server.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions stay off (nothing here is floating point anyway)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
-    "-I" + os.path.join(ROOT, "include"),
+    "-I" + os.path.join(ROOT, "include"), "-pthread",
 ]
 
 
@@ -43,7 +44,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 2)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

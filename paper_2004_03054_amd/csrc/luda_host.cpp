@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "luda.h"
+#include "luda_host_internal.h"
 #include "kernels.h"
 
 using namespace luda;
@@ -470,8 +471,14 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   mark(c, "block_cuts");
 
-  // --- output blocks (capacity: one per survivor)
-  const uint64_t OB = S;
+  // --- output blocks
+  uint64_t OB = 0;
+  {
+    Mail m(c);
+    const uint64_t* nb = m.add(job_ob0 + J, 1);
+    m.flush();
+    OB = std::max<uint64_t>(*nb, 1);
+  }
   OutBlocks ob;
   ob.s0 = dbuf<uint64_t>(c, "ob_s0", OB);
   ob.cnt = dbuf<uint32_t>(c, "ob_cnt", OB);
@@ -1242,6 +1249,22 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
 }
 
 }  // namespace
+
+int luda::result_to_host(luda_ctx* c, luda_result* r) {
+  ResultInternal* ri = (ResultInternal*)r->internal;
+  if (!ri || !ri->dev || !r->data_size) return LUDA_OK;
+  uint8_t* h = (uint8_t*)malloc(r->data_size);
+  if (!h) return LUDA_NOMEM;
+  if (hipMemcpyAsync(h, r->data, r->data_size, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    free(h);
+    return LUDA_DEVICE;
+  }
+  release_dev(c, ri);
+  ri->host_data = true;
+  r->data = h;
+  return LUDA_OK;
+}
 
 // ---------------------------------------------------------------------------
 // C-ABI

@@ -1,0 +1,195 @@
+// Served form of the compaction library (include/luda.h, luda_server_*):
+// jobs arrive one by one, are admitted under a device-memory budget, and
+// workers run the admitted jobs that are waiting together as one batched
+// pass.  Each worker owns a context, so its passes run on their own HIP
+// stream; with several workers, passes overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "luda.h"
+#include "luda_host_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServedJob {
+  std::vector<luda_buf> inputs;
+  luda_options opt{};
+  uint64_t est = 0;  // admitted bytes
+  Clock::time_point t_submit, t_done;
+  luda_result res{};
+  bool done = false;
+};
+
+}  // namespace
+
+struct luda_server {
+  luda_server_cfg cfg{};
+  int device = 0;
+  std::vector<luda_ctx*> ctxs;
+  std::vector<std::thread> threads;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> pending;
+  std::unordered_map<uint64_t, std::unique_ptr<ServedJob>> jobs;
+  uint64_t next_ticket = 1;
+  uint64_t admitted = 0, peak = 0;
+  uint64_t n_done = 0, n_batches = 0, max_batch = 0;
+  bool stop = false;
+};
+
+namespace {
+
+// a waiting job can start now: budget permitting, or alone on an idle server
+bool can_take(const luda_server* s) {
+  if (s->pending.empty()) return false;
+  const ServedJob* j = s->jobs.at(s->pending.front()).get();
+  return s->admitted == 0 || s->admitted + j->est <= s->cfg.hbm_budget;
+}
+
+void worker(luda_server* s, luda_ctx* ctx) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    std::vector<ServedJob*> batch;
+    uint64_t est = 0;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stop || can_take(s); });
+      if (s->stop && s->pending.empty()) return;
+      while (!s->pending.empty() && (s->cfg.max_batch_jobs == 0 || batch.size() < s->cfg.max_batch_jobs)) {
+        ServedJob* j = s->jobs.at(s->pending.front()).get();
+        if (s->admitted + j->est > s->cfg.hbm_budget && !(s->admitted == 0 && batch.empty())) break;
+        s->admitted += j->est;
+        est += j->est;
+        batch.push_back(j);
+        s->pending.pop_front();
+      }
+      s->peak = std::max(s->peak, s->admitted);
+    }
+    if (batch.empty()) continue;
+    std::vector<luda_job> cj(batch.size());
+    std::vector<luda_result> res(batch.size());
+    for (size_t k = 0; k < batch.size(); k++) {
+      cj[k].inputs = batch[k]->inputs.data();
+      cj[k].n_inputs = (uint32_t)batch[k]->inputs.size();
+      cj[k].options = batch[k]->opt;
+    }
+    luda_compact_batch(ctx, cj.data(), (uint32_t)cj.size(), 1, res.data());
+    if (s->cfg.host_outputs)
+      for (auto& r : res) luda::result_to_host(ctx, &r);
+    const Clock::time_point now = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (size_t k = 0; k < batch.size(); k++) {
+        batch[k]->res = res[k];
+        batch[k]->done = true;
+        batch[k]->t_done = now;
+      }
+      s->admitted -= est;
+      s->n_done += batch.size();
+      s->n_batches++;
+      s->max_batch = std::max<uint64_t>(s->max_batch, batch.size());
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int luda_server_create(int device, const luda_server_cfg* cfg, luda_server** out) {
+  if (!cfg || !out || cfg->hbm_budget == 0 || cfg->workers == 0 || cfg->workers > 8) return LUDA_INVALID_ARG;
+  *out = nullptr;
+  luda_server* s = new luda_server();
+  s->cfg = *cfg;
+  s->device = device;
+  for (uint32_t w = 0; w < cfg->workers; w++) {
+    luda_ctx* c = nullptr;
+    const int rc = luda_ctx_create(device, &c);
+    if (rc != LUDA_OK) {
+      for (luda_ctx* x : s->ctxs) luda_ctx_destroy(x);
+      delete s;
+      return rc;
+    }
+    s->ctxs.push_back(c);
+  }
+  for (luda_ctx* c : s->ctxs) s->threads.emplace_back(worker, s, c);
+  *out = s;
+  return LUDA_OK;
+}
+
+int luda_server_submit(luda_server* s, const luda_job* job, uint64_t* ticket) {
+  if (!s || !job || !ticket || (job->n_inputs && !job->inputs)) return LUDA_INVALID_ARG;
+  auto j = std::make_unique<ServedJob>();
+  uint64_t bytes = 0;
+  for (uint32_t i = 0; i < job->n_inputs; i++) {
+    j->inputs.push_back(job->inputs[i]);
+    bytes += job->inputs[i].size;
+  }
+  j->opt = job->options;
+  j->est = std::max<uint64_t>(2 * bytes, 1);
+  j->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return LUDA_INVALID_ARG;
+    *ticket = s->next_ticket++;
+    s->pending.push_back(*ticket);
+    s->jobs.emplace(*ticket, std::move(j));
+  }
+  s->cv_work.notify_one();
+  return LUDA_OK;
+}
+
+int luda_server_poll(luda_server* s, uint64_t ticket, int wait, luda_result* out, double* latency_ms) {
+  if (!s || !out) return LUDA_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return LUDA_INVALID_ARG;
+  ServedJob* j = it->second.get();
+  if (wait) s->cv_done.wait(lk, [&] { return j->done; });
+  if (!j->done) return 1;
+  *out = j->res;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(j->t_done - j->t_submit).count();
+  s->jobs.erase(it);
+  return LUDA_OK;
+}
+
+int luda_server_stats(luda_server* s, uint64_t* jobs, uint64_t* batches, uint64_t* max_batch,
+                      uint64_t* peak_admitted) {
+  if (!s) return 0;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (jobs) *jobs = s->n_done;
+  if (batches) *batches = s->n_batches;
+  if (max_batch) *max_batch = s->max_batch;
+  if (peak_admitted) *peak_admitted = s->peak;
+  return 4;
+}
+
+void luda_server_destroy(luda_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& t : s->threads) t.join();
+  for (auto& kv : s->jobs)
+    if (kv.second->done) luda_result_free(nullptr, &kv.second->res);
+  for (luda_ctx* c : s->ctxs) luda_ctx_destroy(c);
+  delete s;
+}
+
+}  // extern "C"
