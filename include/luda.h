@@ -169,6 +169,27 @@ int luda_last_counters(luda_ctx *ctx, const char **names, double *values, int ca
  * Returns LUDA_OK, or LUDA_INVALID_ARG for an unknown name or range. */
 int luda_debug_read(luda_ctx *ctx, const char *name, void *dst, uint64_t offset, uint64_t bytes);
 
+/* Launch parameters of a context.  They change only how work is laid out on
+ * the device, never the output bytes. */
+typedef struct {
+  uint32_t crc_waves;     /* waves per workgroup of the data-block checksum kernel: 4, 8 or 16 (default 8) */
+  uint32_t encode_waves;  /* most waves per workgroup of the block encoder, 2..16 (default 16; LDS may
+                             allow fewer) */
+  uint32_t stride_blocks; /* workgroups per compute unit of the grid-stride kernels, 1..64 (default 16) */
+} luda_params;
+
+int luda_get_params(luda_ctx *ctx, luda_params *out);
+/* LUDA_INVALID_ARG for a value outside the ranges above. */
+int luda_set_params(luda_ctx *ctx, const luda_params *p);
+
+/* Autotuner: runs the given jobs (as luda_compact_batch) rounds + 1 times
+ * for each candidate setting, coordinate by coordinate, keeps the setting
+ * with the least wall time in the context and returns it (and its time in
+ * *best_ms, may be NULL).  Outputs are discarded.  Returns LUDA_OK or the
+ * first failure of a run. */
+int luda_autotune(luda_ctx *ctx, const luda_job *jobs, uint32_t n_jobs, int device_inputs, uint32_t rounds,
+                  luda_params *best, double *best_ms);
+
 /* Host-side self check of the CRC32C shift tables (no device needed). */
 int luda_selftest_crc(void);
 

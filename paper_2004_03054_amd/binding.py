@@ -52,6 +52,10 @@ class LudaJob(C.Structure):
     _fields_ = [("inputs", C.POINTER(LudaBuf)), ("n_inputs", C.c_uint32), ("options", LudaOptions)]
 
 
+class LudaParams(C.Structure):
+    _fields_ = [("crc_waves", C.c_uint32), ("encode_waves", C.c_uint32), ("stride_blocks", C.c_uint32)]
+
+
 class LudaServerCfg(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_batch_jobs", C.c_uint32), ("workers", C.c_uint32),
                 ("host_outputs", C.c_uint32)]
@@ -61,7 +65,7 @@ EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compa
            "luda_compact_batch", "luda_build_tables_dev", "luda_result_free", "luda_status_str",
            "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters",
            "luda_server_create", "luda_server_submit", "luda_server_poll", "luda_server_stats",
-           "luda_server_destroy"]
+           "luda_server_destroy", "luda_get_params", "luda_set_params", "luda_autotune"]
 
 _lib = None
 
@@ -103,6 +107,13 @@ def lib():
     L.luda_debug_read.restype = C.c_int
     L.luda_selftest_crc.argtypes = []
     L.luda_selftest_crc.restype = C.c_int
+    L.luda_get_params.argtypes = [C.c_void_p, C.POINTER(LudaParams)]
+    L.luda_get_params.restype = C.c_int
+    L.luda_set_params.argtypes = [C.c_void_p, C.POINTER(LudaParams)]
+    L.luda_set_params.restype = C.c_int
+    L.luda_autotune.argtypes = [C.c_void_p, C.POINTER(LudaJob), C.c_uint32, C.c_int, C.c_uint32,
+                                C.POINTER(LudaParams), C.POINTER(C.c_double)]
+    L.luda_autotune.restype = C.c_int
     L.luda_server_create.argtypes = [C.c_int, C.POINTER(LudaServerCfg), C.POINTER(C.c_void_p)]
     L.luda_server_create.restype = C.c_int
     L.luda_server_submit.argtypes = [C.c_void_p, C.POINTER(LudaJob), C.POINTER(C.c_uint64)]
@@ -296,6 +307,43 @@ class Context:
                 if o.status == 0:
                     o.status = rc
         return out
+
+    def _jobs(self, jobs: Sequence, device_inputs: bool):
+        J = len(jobs)
+        cjobs = (LudaJob * max(1, J))()
+        keep = []
+        for j, (inputs, opts) in enumerate(jobs):
+            if device_inputs:
+                bufs = _dev_bufs(inputs)
+            else:
+                bufs, arrs = _bufs(inputs)
+                keep.append(arrs)
+            keep.append(bufs)
+            cjobs[j].inputs = C.cast(bufs, C.POINTER(LudaBuf))
+            cjobs[j].n_inputs = len(inputs)
+            cjobs[j].options = options(opts)
+        return cjobs, keep
+
+    def params(self) -> dict:
+        p = LudaParams()
+        lib().luda_get_params(self._h, C.byref(p))
+        return dict(crc_waves=p.crc_waves, encode_waves=p.encode_waves, stride_blocks=p.stride_blocks)
+
+    def set_params(self, crc_waves: int, encode_waves: int, stride_blocks: int):
+        rc = lib().luda_set_params(self._h, C.byref(LudaParams(crc_waves, encode_waves, stride_blocks)))
+        if rc != 0:
+            raise ValueError(f"luda_set_params: {STATUS.get(rc, rc)}")
+
+    def autotune(self, jobs: Sequence, device_inputs: bool, rounds: int = 2) -> tuple:
+        """(best params dict, best ms) over the given jobs; the context keeps them."""
+        cjobs, _keep = self._jobs(jobs, device_inputs)
+        p = LudaParams()
+        ms = C.c_double()
+        rc = lib().luda_autotune(self._h, cjobs, len(jobs), 1 if device_inputs else 0, rounds, C.byref(p),
+                                 C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"luda_autotune: {STATUS.get(rc, rc)} {self.last_error()}")
+        return dict(crc_waves=p.crc_waves, encode_waves=p.encode_waves, stride_blocks=p.stride_blocks), ms.value
 
     def build_tables_dev(self, keys, koff, tags, vals, voff, opts: dict) -> Result:
         """Write ordered entries (device tensors) into tables on the device."""

@@ -104,7 +104,7 @@ __device__ inline void finish_crc(const WalkSet& ws, const Inputs& in, uint32_t 
   ok[b] = good;
 }
 
-__global__ void __launch_bounds__(512) k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok,
+__global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok,
                                                   unsigned long long* err, unsigned long long* bytes_total) {
   __shared__ CrcLds T;
   load_crc_tables(&T, g_crc, threadIdx.x, blockDim.x);

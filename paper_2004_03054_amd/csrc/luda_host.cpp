@@ -100,6 +100,7 @@ struct DBuf {
 
 struct luda_ctx {
   int device = 0;
+  luda_params tp{8, 16, 16};  // launch parameters (luda_set_params / luda_autotune)
   hipStream_t own = nullptr;
   hipStream_t stream = nullptr;
   uint32_t* d_crc = nullptr;  // CrcTables image
@@ -169,7 +170,7 @@ inline uint32_t blocks_for(uint64_t n, uint32_t t = 256) {
 
 // grid of a grid-stride kernel over at most cap items
 uint32_t stride_grid(const luda_ctx* c, uint64_t cap, uint32_t t = 256) {
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((cap + t - 1) / t, (uint64_t)c->n_cu * 16));
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((cap + t - 1) / t, (uint64_t)c->n_cu * c->tp.stride_blocks));
 }
 
 void fill_u32(luda_ctx* c, void* p, uint32_t v, uint64_t n) {
@@ -652,7 +653,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     const size_t win = sizeof(EncLds) + ((4 * (ENC_W + 1) + 15) & ~size_t(15));
     const size_t per_wave = win + ((size_t(max_bsize) + 1 + CRC_UNIT - 1) / CRC_UNIT) * CRC_UNIT + 64;
     const size_t budget = c->lds_limit - 2048 - CRC_LDS_BYTES;
-    const size_t sw = std::min<size_t>(16, budget / per_wave);
+    const size_t sw = std::min<size_t>(c->tp.encode_waves, budget / per_wave);
     const bool staged = sw >= 2 && per_wave < (1u << 31);
     const int waves = staged ? (int)sw : 8;
     const void* fn = staged ? (const void*)k_encode : (const void*)k_encode_gen;
@@ -932,13 +933,14 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     launch_scan<uint64_t>(nrb64, NB, nullptr, DB.ibase, scan_b, st);
     LAUNCH_CHECK();
     {
+      const uint32_t cw = c->tp.crc_waves;
       int occ = 0;
-      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_crc_wave, 512, 0));
+      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_crc_wave, cw * 64, 0));
       occ = std::max(occ, 1);
       const uint32_t grid =
-          (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NB + 7) / 8, (uint64_t)c->n_cu * occ));
+          (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((NB + cw - 1) / cw, (uint64_t)c->n_cu * occ));
       KTimer kt(c, "k_crc_data");
-      hipLaunchKernelGGL(k_crc_wave, dim3(grid), dim3(512), 0, st, db, in, c->d_crc, DB.ok, err, d_bytes);
+      hipLaunchKernelGGL(k_crc_wave, dim3(grid), dim3(cw * 64), 0, st, db, in, c->d_crc, DB.ok, err, d_bytes);
       LAUNCH_CHECK();
       kt.stop();
     }
@@ -1527,6 +1529,77 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     out->status = out->error.status = f.status;
     return f.status;
   }
+  return LUDA_OK;
+}
+
+static bool params_ok(const luda_params* p) {
+  return p && (p->crc_waves == 4 || p->crc_waves == 8 || p->crc_waves == 16) && p->encode_waves >= 2 &&
+         p->encode_waves <= 16 && p->stride_blocks >= 1 && p->stride_blocks <= 64;
+}
+
+int luda_get_params(luda_ctx* c, luda_params* p) {
+  if (!c || !p) return LUDA_INVALID_ARG;
+  *p = c->tp;
+  return LUDA_OK;
+}
+
+int luda_set_params(luda_ctx* c, const luda_params* p) {
+  if (!c || !params_ok(p)) return LUDA_INVALID_ARG;
+  c->tp = *p;
+  return LUDA_OK;
+}
+
+int luda_autotune(luda_ctx* c, const luda_job* jobs, uint32_t n_jobs, int device_inputs, uint32_t rounds,
+                  luda_params* best, double* best_ms) {
+  if (!c || !jobs || !n_jobs || !best || rounds == 0) return LUDA_INVALID_ARG;
+  std::vector<luda_result> res(n_jobs);
+  auto run = [&](const luda_params& p, double* ms) -> int {
+    c->tp = p;
+    double t_min = 1e300;
+    for (uint32_t r = 0; r < rounds + 1; r++) {  // the first run warms the buffers
+      const auto t0 = std::chrono::steady_clock::now();
+      const int rc = luda_compact_batch(c, jobs, n_jobs, device_inputs, res.data());
+      const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      int bad = rc;
+      for (auto& x : res) {
+        if (x.status != LUDA_OK && bad == LUDA_OK) bad = x.status;
+        luda_result_free(c, &x);
+      }
+      if (bad != LUDA_OK) return bad;
+      if (r) t_min = std::min(t_min, t);
+    }
+    *ms = t_min;
+    return LUDA_OK;
+  };
+  luda_params cur = c->tp;
+  double cur_ms = 0;
+  int rc = run(cur, &cur_ms);
+  if (rc != LUDA_OK) return rc;
+  // coordinate descent over the three parameters
+  const uint32_t crc_c[] = {4, 8, 16}, enc_c[] = {4, 8, 12, 16}, str_c[] = {4, 8, 16, 32};
+  for (int dim = 0; dim < 3; dim++) {
+    const uint32_t* cand = dim == 0 ? crc_c : dim == 1 ? enc_c : str_c;
+    const int nc = dim == 1 ? 4 : (dim == 0 ? 3 : 4);
+    for (int k = 0; k < nc; k++) {
+      luda_params p = cur;
+      (dim == 0 ? p.crc_waves : dim == 1 ? p.encode_waves : p.stride_blocks) = cand[k];
+      if (p.crc_waves == cur.crc_waves && p.encode_waves == cur.encode_waves && p.stride_blocks == cur.stride_blocks)
+        continue;
+      double ms = 0;
+      rc = run(p, &ms);
+      if (rc != LUDA_OK) {
+        c->tp = cur;
+        return rc;
+      }
+      if (ms < cur_ms) {
+        cur = p;
+        cur_ms = ms;
+      }
+    }
+  }
+  c->tp = cur;
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
   return LUDA_OK;
 }
 

@@ -124,3 +124,24 @@ def test_batch_matches_alone():
 def test_full_size(make, label):
     res, ref = run_both(make(), label, device=True)
     say(f"[gpu] {label}: {len(ref.files)} files, {res.entries_in} entries in, {res.entries_out} out")
+
+
+def test_launch_params_do_not_change_bytes():
+    """Every launch setting the autotuner may pick gives the same outputs."""
+    job = config3_job(6, scale=1 / 64)
+    ins = oracle.build_input_tables(job)
+    ref = oracle.compact(ins, job.options())
+    c = ctx()
+    saved = c.params()
+    try:
+        for cw, ew, sb in [(4, 2, 1), (16, 4, 64), (8, 16, 4), (16, 16, 32)]:
+            c.set_params(cw, ew, sb)
+            res = c.compact(ins, job.options())
+            assert res.status == 0, (cw, ew, sb, res.name)
+            assert_same_files(res.files, ref.files, f"params {cw}/{ew}/{sb}")
+        best, ms = c.autotune([(ins, job.options())], device_inputs=False, rounds=1)
+        say(f"[gpu] autotune picked {best} ({ms:.2f} ms)")
+        res = c.compact(ins, job.options())
+        assert_same_files(res.files, ref.files, "autotuned")
+    finally:
+        c.set_params(**saved)
