@@ -363,9 +363,10 @@ struct ResultInternal {
 };
 
 void release_dev(luda_ctx* c, ResultInternal* ri) {
-  if (!ri || !ri->dev || --ri->dev->refs > 0) return;
+  if (!ri || !ri->dev) return;
   DevBlock* d = ri->dev;
-  ri->dev = nullptr;
+  ri->dev = nullptr;  // this result no longer holds the buffer, whoever frees it
+  if (--d->refs > 0) return;
   if (c && d->cap > c->spare_out.cap) {
     if (c->spare_out.p) (void)hipFree(c->spare_out.p);
     c->spare_out.p = d->p;
