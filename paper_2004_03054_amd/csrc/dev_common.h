@@ -217,6 +217,7 @@ constexpr uint32_t CRC_POLY = 0x82F63B78u;  // CRC32C, reflected
 struct CrcLds {
   uint32_t t[256][32];
   uint32_t sh[7][8][16];
+  uint32_t ss[3][8][16];  // shifts by 16, 32 and 48 zero bytes, by nibbles
 };
 
 // this lane's copy of the byte table (stride 32 words between entries)
@@ -238,6 +239,14 @@ __device__ __forceinline__ uint32_t crc_shift(const CrcLds* T, uint32_t k, uint3
   return r;
 }
 
+// shift a raw CRC over 16 * (m + 1) zero bytes (m = 0..2)
+__device__ __forceinline__ uint32_t crc_sub_shift(const CrcLds* T, uint32_t m, uint32_t c) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < 8; j++) r ^= T->ss[m][j][(c >> (4 * j)) & 15u];
+  return r;
+}
+
 // mask bytes at message positions < 0 and complement positions 0..3
 __device__ __forceinline__ uint32_t crc_edge(uint32_t d, int64_t p) {
   if (p >= 4) return d;
@@ -252,8 +261,10 @@ __device__ __forceinline__ uint32_t crc_edge(uint32_t d, int64_t p) {
 }
 
 // raw CRC (from state 0) of one 64-byte unit held in registers that starts at
-// message position p (bytes before position 0 are ignored)
-__device__ __forceinline__ uint32_t crc_unit(const uint32_t* tl, uint4 v[4], int64_t p) {
+// message position p (bytes before position 0 are ignored).  The four
+// 16-byte chunks run as independent chains (four lookups in flight per lane)
+// and are joined by shifts of 48, 32 and 16 bytes.
+__device__ __forceinline__ uint32_t crc_unit(const CrcLds* T, const uint32_t* tl, uint4 v[4], int64_t p) {
   if (p < 4) {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
@@ -264,15 +275,24 @@ __device__ __forceinline__ uint32_t crc_unit(const uint32_t* tl, uint4 v[4], int
       v[q].w = crc_edge(v[q].w, pq + 12);
     }
   }
-  uint32_t r = 0;
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    r = crc_step4(tl, r, v[q].x);
-    r = crc_step4(tl, r, v[q].y);
-    r = crc_step4(tl, r, v[q].z);
-    r = crc_step4(tl, r, v[q].w);
-  }
-  return r;
+  uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+  r0 = crc_step4(tl, r0, v[0].x);
+  r1 = crc_step4(tl, r1, v[1].x);
+  r2 = crc_step4(tl, r2, v[2].x);
+  r3 = crc_step4(tl, r3, v[3].x);
+  r0 = crc_step4(tl, r0, v[0].y);
+  r1 = crc_step4(tl, r1, v[1].y);
+  r2 = crc_step4(tl, r2, v[2].y);
+  r3 = crc_step4(tl, r3, v[3].y);
+  r0 = crc_step4(tl, r0, v[0].z);
+  r1 = crc_step4(tl, r1, v[1].z);
+  r2 = crc_step4(tl, r2, v[2].z);
+  r3 = crc_step4(tl, r3, v[3].z);
+  r0 = crc_step4(tl, r0, v[0].w);
+  r1 = crc_step4(tl, r1, v[1].w);
+  r2 = crc_step4(tl, r2, v[2].w);
+  r3 = crc_step4(tl, r3, v[3].w);
+  return crc_sub_shift(T, 2, r0) ^ crc_sub_shift(T, 1, r1) ^ crc_sub_shift(T, 0, r2) ^ r3;
 }
 
 // join the per-lane Horner sums: lane l's last unit is followed by 63 - l
@@ -322,7 +342,7 @@ __device__ __forceinline__ uint32_t wave_raw_crc(const CrcLds* T, const uint8_t*
       uint4 v[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) v[q] = ld_chunk(msg, p + 16 * q);
-      acc = crc_shift(T, 6, acc) ^ crc_unit(tl, v, p);
+      acc = crc_shift(T, 6, acc) ^ crc_unit(T, tl, v, p);
     }
   }
   return crc_wave_join(T, acc);

@@ -161,7 +161,7 @@ __device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t nw, uint32_t i, int64_
 // starts 8 entries before the previous one ended, so a chunk assigned to a
 // window (by its first byte) never reaches past the window's entries (an
 // entry is at least 4 bytes).
-constexpr uint32_t ENC_B = 1;  // interior chunks per lane in flight with the owner loads
+constexpr uint32_t ENC_B = 2;  // whole value chunks per lane in flight with the byte tasks
 
 constexpr uint32_t ENC_OVERLAP = 16;  // entries shared by consecutive windows (>= 64 bytes)
 
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
               if (p0 + k >= 0) dst[p0 + k] = vb[k];
           }
         }
-        acc = crc_shift(T, 6, acc) ^ crc_unit(tl, v, p);
+        acc = crc_shift(T, 6, acc) ^ crc_unit(T, tl, v, p);
         uu -= 64;
       }
       wave_sync();
@@ -281,45 +281,10 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Staged encoder.  Per wave: [EncLds window | piece offsets | stage].  The
+// Staged encoder.  Per wave: [EncWin entry window | stage].  The
 // block message (contents || type byte) sits at the end of the stage, which
 // is 16-byte aligned, so the chunk grid of the CRC (16-byte chunks aligned to
 // the message end) is the aligned grid of the stage.
-
-__device__ inline void stage_key_bytes(uint8_t* d, const uint64_t* slot, uint32_t ul, uint64_t tag, uint32_t q0,
-                                       uint32_t q1) {
-  uint64_t word = 0;
-  uint32_t wi = 0xFFFFFFFFu;
-  for (uint32_t q = q0; q < q1; q++) {
-    uint32_t byte;
-    if (q < ul) {
-      if ((q >> 3) != wi) {
-        wi = q >> 3;
-        word = slot[wi];
-      }
-      byte = (uint32_t)(word >> (8 * (q & 7))) & 0xFFu;
-    } else {
-      byte = (uint32_t)(tag >> (8 * (q - ul))) & 0xFFu;
-    }
-    *d++ = (uint8_t)byte;
-  }
-}
-
-__device__ inline void stage_varint(uint8_t* d, uint32_t v, uint32_t* k) {
-  while (v >= 128) {
-    d[(*k)++] = (uint8_t)(v | 128u);
-    v >>= 7;
-  }
-  d[(*k)++] = (uint8_t)v;
-}
-
-// bytes [from, to) of a 128-bit little-endian value to LDS at d[from..to)
-__device__ inline void put_bytes(uint8_t* d, u128 v, uint32_t from, uint32_t to) {
-  const uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
-  for (uint32_t q = from; q < to; q++) d[q] = (uint8_t)(q < 8 ? (lo >> (8 * q)) : (hi >> (8 * (q - 8))));
-}
-
-constexpr uint32_t ENC_KW = 4;  // key slot words held in registers while staging
 
 __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -329,8 +294,7 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
   const uint32_t waves = blockDim.x / WAVE;
   uint8_t* wbase = smem + sizeof(CrcLds) + (size_t)wv * A.wave_lds;
-  EncLds* L = (EncLds*)wbase;
-  uint32_t* pc = (uint32_t*)(wbase + sizeof(EncLds));  // ENC_W + 1 piece offsets
+  EncWin* W = (EncWin*)wbase;
   uint8_t* stage_end = wbase + A.wave_lds;
   const uint64_t nb = *A.nblocks;
   for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
@@ -345,132 +309,129 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
     const uint32_t J16 = (n + 15) / 16;
     uint8_t* base = stage_end - n;         // message byte p at base[p]
     const uint32_t gshift = 16 * J16 - n;  // chunk grid: positions 16 m - gshift
-    // --- entries, a window at a time
-    for (uint32_t k0 = 0; k0 < cnt; k0 += ENC_W) {
-      const uint32_t nw = min(cnt - k0, ENC_W);
-      const bool own = l < nw;
-      uint32_t pieces = 0, a = 0, st = 0, vs = 0, en = 0, h_end = 0, t_beg = 0, shared = 0, ns = 0;
-      EncRec r;
-      r.vp = 0;
-      r.tag = 0;
-      r.e = 0;
-      r.shared = 0;
-      r.ulen = 0;
-      r.vlen = 0;
-      if (own) {
+    // --- entries, a window at a time: one lane per entry lays out its
+    // entry, then all lanes write the header, key delta and value-edge bytes
+    // (byte tasks) and copy the whole aligned chunks of the values
+    for (uint32_t k0 = 0; k0 < cnt; k0 += ENC_SW) {
+      const uint32_t nw = min(cnt - k0, ENC_SW);
+      uint32_t tasks = 0, pieces = 0;
+      if (l < nw) {
         const uint32_t i = k0 + l;
-        r = A.rec[s0 + i];
-        st = blk_off[i];
-        shared = (i % R == 0) ? 0u : r.shared;
-        ns = r.ulen + 8 - shared;
-        vs = st + vlen32(shared) + vlen32(ns) + vlen32(r.vlen) + ns;
-        en = vs + r.vlen;
-        // value interior: whole aligned chunks inside [vs, en); edges as
-        // bytes.  a is the first grid position >= vs, z the last <= en (it
-        // can lie before the message start, hence signed).
-        a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
+        const EncRec r = A.rec[s0 + i];
+        const uint32_t st = blk_off[i];
+        const uint32_t shared = (i % R == 0) ? 0u : r.shared;
+        const uint32_t ns = r.ulen + 8 - shared;
+        uint32_t la, lb, lc;
+        const uint64_t va = pack_varint(shared, &la), vb = pack_varint(ns, &lb), vc = pack_varint(r.vlen, &lc);
+        const u128 H = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
+        const uint32_t hl = la + lb + lc;
+        const uint32_t vs = st + hl + ns, en = vs + r.vlen;
+        // a: first grid position >= vs; z: last grid position <= en (it can
+        // lie before the message start, hence signed)
+        const uint32_t a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
         const int64_t z = (int64_t)en - (int64_t)((en + gshift) & 15u);
-        h_end = en;
-        t_beg = en;
+        uint32_t h_end = en, t_beg = en;
         if ((int64_t)a + 16 <= z) {
           pieces = (uint32_t)((z - (int64_t)a) / 16);
           h_end = a;
           t_beg = (uint32_t)z;
         }
-        L->vs[l] = vs;
-        L->vp[l] = r.vp;
-        L->st[l] = a;  // first interior chunk position
+        W->vp[l] = r.vp;
+        W->tag[l] = r.tag;
+        W->h0[l] = (uint64_t)H;
+        W->h1[l] = (uint64_t)(H >> 64);
+        W->st[l] = st;
+        W->hl[l] = hl;
+        W->ns[l] = ns;
+        W->sh[l] = shared;
+        W->ul[l] = r.ulen;
+        W->e[l] = r.e;
+        W->vs[l] = vs;
+        W->a[l] = a;
+        W->hn[l] = h_end - vs;
+        W->tb[l] = t_beg;
+        tasks = hl + ns + (h_end - vs) + (en - t_beg);
       }
-      const uint32_t incl = wave_incl_scan(pieces);
-      if (own) pc[l] = incl - pieces;
-      const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-      if (l == 0) pc[nw] = total;
+      const uint32_t ti = wave_incl_scan(tasks), pi = wave_incl_scan(pieces);
+      if (l < nw) {
+        W->pb[l] = ti - tasks;
+        W->pc[l] = pi - pieces;
+      }
+      const uint32_t ntasks = __shfl(ti, WAVE - 1, WAVE), npieces = __shfl(pi, WAVE - 1, WAVE);
+      if (l == 0) {
+        W->pb[nw] = ntasks;
+        W->pc[nw] = npieces;
+      }
       wave_sync();
-      // owner lanes: loads for the header, key delta and value edges, all in
-      // flight together with the first interior copies
-      uint64_t kw[ENC_KW];
-      u128 e0 = 0, e1 = 0, e2 = 0;
-      const uint32_t w0 = shared >> 3, wl = (r.ulen + 7) >> 3;
-      if (own) {
-        const uint64_t* slot = A.tu.heap + (uint64_t)r.e * A.kw8;
-#pragma unroll
-        for (uint32_t t = 0; t < ENC_KW; t++) kw[t] = (w0 + t < wl) ? slot[w0 + t] : 0ull;
-        const uint8_t* vp = (const uint8_t*)r.vp;
-        const uint32_t hn = h_end - vs, tn = en - t_beg;
-        if (hn) e0 = load_span(vp, min(hn, 16u));
-        if (hn > 16) e1 = load_span(vp + 16, hn - 16);
-        if (tn) e2 = load_span(vp + (t_beg - vs), tn);
-      }
+      // whole aligned chunks of the values, the first ENC_B per lane in flight
+      // with the byte tasks below
       uint4 v[ENC_B];
 #pragma unroll
       for (uint32_t t = 0; t < ENC_B; t++) {
         const uint32_t k = l + WAVE * t;
-        if (k >= total) continue;
+        if (k >= npieces) continue;
         uint32_t lo = 0, hi = nw;  // pc[lo] <= k < pc[hi]
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (pc[mid] <= k) lo = mid;
+          if (W->pc[mid] <= k) lo = mid;
           else hi = mid;
         }
-        const uint32_t pos = L->st[lo] + 16 * (k - pc[lo]);
-        v[t] = ldg16(L->vp[lo] + (pos - L->vs[lo]));
+        const uint32_t pos = W->a[lo] + 16 * (k - W->pc[lo]);
+        v[t] = ldg16(W->vp[lo] + (pos - W->vs[lo]));
       }
-      if (own) {
-        uint8_t* d = base + st;
-        uint32_t k = 0;
-        stage_varint(d, shared, &k);
-        stage_varint(d, ns, &k);
-        stage_varint(d, r.vlen, &k);
-        d += k;
-        const uint32_t klen = r.ulen + 8;
-        uint64_t word = 0;
-        uint32_t wcur = 0xFFFFFFFFu;
-        for (uint32_t q = shared; q < klen; q++) {
-          uint32_t byte;
-          if (q < r.ulen) {
-            const uint32_t wi = q >> 3;
-            if (wi != wcur) {
-              wcur = wi;
-              const uint32_t t = wi - w0;
-              word = 0;
-#pragma unroll
-              for (uint32_t u = 0; u < ENC_KW; u++)
-                if (u == t) word = kw[u];
-              if (t >= ENC_KW) word = A.tu.heap[(uint64_t)r.e * A.kw8 + wi];
-            }
+      for (uint32_t k = l; k < ntasks; k += WAVE) {
+        uint32_t lo = 0, hi = nw;  // pb[lo] <= k < pb[hi]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (W->pb[mid] <= k) lo = mid;
+          else hi = mid;
+        }
+        uint32_t o = k - W->pb[lo];
+        const uint32_t hl = W->hl[lo], ns = W->ns[lo];
+        uint32_t byte, d;
+        if (o < hl) {
+          byte = (uint32_t)((o < 8 ? W->h0[lo] >> (8 * o) : W->h1[lo] >> (8 * (o - 8))) & 0xFFu);
+          d = W->st[lo] + o;
+        } else if (o < hl + ns) {
+          const uint32_t q = W->sh[lo] + (o - hl), ul = W->ul[lo];
+          if (q < ul) {
+            const uint64_t word = A.tu.heap[(uint64_t)W->e[lo] * A.kw8 + (q >> 3)];
             byte = (uint32_t)(word >> (8 * (q & 7))) & 0xFFu;
           } else {
-            byte = (uint32_t)(r.tag >> (8 * (q - r.ulen))) & 0xFFu;
+            byte = (uint32_t)(W->tag[lo] >> (8 * (q - ul))) & 0xFFu;
           }
-          *d++ = (uint8_t)byte;
+          d = W->st[lo] + o;
+        } else {
+          o -= hl + ns;
+          const uint32_t hn = W->hn[lo], vs = W->vs[lo];
+          const uint32_t off = (o < hn) ? o : (W->tb[lo] - vs) + (o - hn);
+          byte = ((const uint8_t*)W->vp[lo])[off];
+          d = vs + off;
         }
-        const uint32_t hn = h_end - vs, tn = en - t_beg;
-        put_bytes(base + vs, e0, 0, min(hn, 16u));
-        if (hn > 16) put_bytes(base + vs + 16, e1, 0, hn - 16);
-        put_bytes(base + t_beg, e2, 0, tn);
+        base[d] = (uint8_t)byte;
       }
 #pragma unroll
       for (uint32_t t = 0; t < ENC_B; t++) {
         const uint32_t k = l + WAVE * t;
-        if (k >= total) continue;
+        if (k >= npieces) continue;
         uint32_t lo = 0, hi = nw;
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (pc[mid] <= k) lo = mid;
+          if (W->pc[mid] <= k) lo = mid;
           else hi = mid;
         }
-        *(uint4*)(base + L->st[lo] + 16 * (k - pc[lo])) = v[t];
+        *(uint4*)(base + W->a[lo] + 16 * (k - W->pc[lo])) = v[t];
       }
-      // remaining interior chunks of long values
-      for (uint32_t k = l + WAVE * ENC_B; k < total; k += WAVE) {
+      // remaining whole chunks of long values
+      for (uint32_t k = l + WAVE * ENC_B; k < npieces; k += WAVE) {
         uint32_t lo = 0, hi = nw;
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (pc[mid] <= k) lo = mid;
+          if (W->pc[mid] <= k) lo = mid;
           else hi = mid;
         }
-        const uint32_t pos = L->st[lo] + 16 * (k - pc[lo]);
-        *(uint4*)(base + pos) = ldg16(L->vp[lo] + (pos - L->vs[lo]));
+        const uint32_t pos = W->a[lo] + 16 * (k - W->pc[lo]);
+        *(uint4*)(base + pos) = ldg16(W->vp[lo] + (pos - W->vs[lo]));
       }
       wave_sync();
     }
@@ -514,7 +475,7 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
               if (p0 + k >= 0) dst[p0 + k] = vb[k];
           }
         }
-        acc = crc_shift(T, 6, acc) ^ crc_unit(tl, v, p);
+        acc = crc_shift(T, 6, acc) ^ crc_unit(T, tl, v, p);
       }
     }
     const uint32_t raw = crc_wave_join(T, acc);

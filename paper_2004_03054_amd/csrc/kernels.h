@@ -184,6 +184,27 @@ struct EncLds {
   uint32_t ul[ENC_W];       // user key length
   uint32_t pad[3];
 };
+// the staged encoder's entry window (per wave)
+constexpr uint32_t ENC_SW = 32;
+struct EncWin {
+  uint64_t vp[ENC_SW];    // value address
+  uint64_t tag[ENC_SW];
+  uint64_t h0[ENC_SW];    // header bytes 0..7 (varints shared, non_shared, value_len)
+  uint64_t h1[ENC_SW];    // header bytes 8..14
+  uint32_t st[ENC_SW];    // entry start (block offset)
+  uint32_t hl[ENC_SW];    // header bytes
+  uint32_t ns[ENC_SW];    // key delta bytes
+  uint32_t sh[ENC_SW];    // key bytes shared with the previous entry
+  uint32_t ul[ENC_SW];    // user key length
+  uint32_t e[ENC_SW];     // decoded entry (key slot)
+  uint32_t vs[ENC_SW];    // value start (block offset)
+  uint32_t a[ENC_SW];     // first whole aligned chunk of the value
+  uint32_t hn[ENC_SW];    // value bytes before it
+  uint32_t tb[ENC_SW];    // first value byte after the last whole chunk
+  uint32_t pb[ENC_SW + 1];  // byte tasks: offsets (header, key delta, value edges)
+  uint32_t pc[ENC_SW + 1];  // whole-chunk copies: offsets
+  uint32_t pad[2];
+};
 __global__ void k_encode(EncodeArgs A);
 __global__ void k_encode_gen(EncodeArgs A);
 struct FilterArgs {

@@ -40,6 +40,7 @@ uint32_t step_byte(uint32_t r, uint8_t b, const uint32_t* t0) { return t0[(r ^ b
 struct CrcTables {
   uint32_t t[256][32];
   uint32_t sh[NSH][8][16];
+  uint32_t ss[3][8][16];  // shifts by 16, 32, 48 zero bytes
 };
 constexpr size_t CRC_LDS_BYTES = sizeof(CrcTables);
 
@@ -70,6 +71,9 @@ void build_crc_tables(CrcTables* T) {
   for (int k = 0; k < NSH; k++)
     for (int j = 0; j < 8; j++)
       for (uint32_t v = 0; v < 16; v++) T->sh[k][j][v] = shift_zeros(v << (4 * j), 64ull << k, t0);
+  for (int m = 0; m < 3; m++)
+    for (int j = 0; j < 8; j++)
+      for (uint32_t v = 0; v < 16; v++) T->ss[m][j][v] = shift_zeros(v << (4 * j), 16ull * (m + 1), t0);
 }
 
 // GF(2) products mod P in the reflected representation, for the self check
@@ -651,7 +655,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.kw8 = P.kw8;
     // staged encoder when a block message (plus the entry window) fits in
     // LDS for at least two waves; otherwise the register generator
-    const size_t win = sizeof(EncLds) + ((4 * (ENC_W + 1) + 15) & ~size_t(15));
+    const size_t win = (sizeof(EncWin) + 15) & ~size_t(15);
     const size_t per_wave = win + ((size_t(max_bsize) + 1 + CRC_UNIT - 1) / CRC_UNIT) * CRC_UNIT + 64;
     const size_t budget = c->lds_limit - 2048 - CRC_LDS_BYTES;
     const size_t sw = std::min<size_t>(c->tp.encode_waves, budget / per_wave);
@@ -1300,6 +1304,10 @@ int luda_selftest_crc(void) {
   }
   for (uint64_t m = 1; m < 300; m += 37)
     if (h_mulmod(x, h_xpow8n(m)) != shift_zeros(x, m, t0)) return 5;
+  for (int m = 0; m < 3; m++) {
+    if (apply_shift(T.ss[m], x) != shift_zeros(x, 16ull * (m + 1), t0)) return 6;
+    x = x * 2654435761u + 12345u;
+  }
   return 0;
 }
 
