@@ -199,52 +199,31 @@ __device__ inline uint32_t put_varint(uint8_t* d, uint64_t v) {
 // bits), raw(A || B) = shift(raw(A), |B|) ^ raw(B), and leading zero bytes
 // leave raw() unchanged.
 //
-// A wave folds a message as 64-byte units aligned to the message end: unit u
-// (u = 0 is the last) covers bytes [n - 64(u+1), n - 64u).  Lane l owns the
-// units u = 63 - l + 64 i, so one wave step reads 4 KiB contiguously.  A lane
-// runs the byte-at-a-time CRC over each of its units from a zero state, with
-// a byte table replicated once per LDS bank (lane l reads copy l % 32, so the
-// lookups never conflict), keeps a Horner sum over its units (a shift by 4096
-// zero bytes between them) and the lanes are joined by a 6-level tree of
-// shifts by 64 * 2^k bytes.  Shifts are applied by nibbles (eight lookups in
-// 16-entry tables).  Long messages are split into segments joined by
-// multiplication with x^(8 len) mod P computed in GF(2).
+// A wave folds a message as 16-byte chunks aligned to the message end: chunk
+// c (c = 0 is the last) covers bytes [n - 16(c+1), n - 16c).  Lane l owns the
+// chunks c = 63 - l + 64 i, so one wave step reads 1 KiB contiguously and a
+// block's chunks are spread over the lanes within one chunk.  A chunk is
+// folded by slicing-by-4 (four independent lookups per 4 bytes); each lane
+// keeps a Horner sum over its chunks (a shift by 1024 zero bytes between
+// them) and the lanes are joined by a 6-level tree of shifts by 16 * 2^k
+// bytes.  Shifts are four table lookups; long messages are split into
+// segments joined by multiplication with x^(8 len) mod P computed in GF(2).
 
 constexpr uint32_t CRC_POLY = 0x82F63B78u;  // CRC32C, reflected
 
-// LDS image: the byte table in 32 bank copies, and shifts by 64 * 2^k zero
-// bytes (k = 0..6) by nibbles: sh[k][j][v] = shift of (v << 4 j)
+// LDS image: slicing-by-4 tables and shifts by 16 * 2^k zero bytes, k = 0..6
 struct CrcLds {
-  uint32_t t[256][32];
-  uint32_t sh[7][8][16];
-  uint32_t ss[3][8][16];  // shifts by 16, 32 and 48 zero bytes, by nibbles
+  uint32_t t4[4][256];
+  uint32_t sh[7][4][256];
 };
 
-// this lane's copy of the byte table (stride 32 words between entries)
-__device__ __forceinline__ const uint32_t* crc_lane_table(const CrcLds* T) { return &T->t[0][0] + (lane_id() & 31); }
-
-// four message bytes (little endian in d) into the CRC register r
-__device__ __forceinline__ uint32_t crc_step4(const uint32_t* tl, uint32_t r, uint32_t d) {
-  r ^= d;
-#pragma unroll
-  for (int k = 0; k < 4; k++) r = tl[(r & 0xFFu) * 32] ^ (r >> 8);
-  return r;
+__device__ __forceinline__ uint32_t crc_dword(const uint32_t (*t4)[256], uint32_t c, uint32_t d) {
+  const uint32_t x = c ^ d;
+  return t4[3][x & 0xFF] ^ t4[2][(x >> 8) & 0xFF] ^ t4[1][(x >> 16) & 0xFF] ^ t4[0][x >> 24];
 }
 
-// shift a raw CRC over 64 * 2^k zero bytes
-__device__ __forceinline__ uint32_t crc_shift(const CrcLds* T, uint32_t k, uint32_t c) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int j = 0; j < 8; j++) r ^= T->sh[k][j][(c >> (4 * j)) & 15u];
-  return r;
-}
-
-// shift a raw CRC over 16 * (m + 1) zero bytes (m = 0..2)
-__device__ __forceinline__ uint32_t crc_sub_shift(const CrcLds* T, uint32_t m, uint32_t c) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int j = 0; j < 8; j++) r ^= T->ss[m][j][(c >> (4 * j)) & 15u];
-  return r;
+__device__ __forceinline__ uint32_t crc_shift(const uint32_t (*sh)[256], uint32_t c) {
+  return sh[0][c & 0xFF] ^ sh[1][(c >> 8) & 0xFF] ^ sh[2][(c >> 16) & 0xFF] ^ sh[3][c >> 24];
 }
 
 // mask bytes at message positions < 0 and complement positions 0..3
@@ -260,55 +239,38 @@ __device__ __forceinline__ uint32_t crc_edge(uint32_t d, int64_t p) {
   return (d & keep) ^ flip;
 }
 
-// raw CRC (from state 0) of one 64-byte unit held in registers that starts at
-// message position p (bytes before position 0 are ignored).  The four
-// 16-byte chunks run as independent chains (four lookups in flight per lane)
-// and are joined by shifts of 48, 32 and 16 bytes.
-__device__ __forceinline__ uint32_t crc_unit(const CrcLds* T, const uint32_t* tl, uint4 v[4], int64_t p) {
+// raw CRC, from register state r, of one 16-byte chunk held in registers
+// that starts at message position p (bytes before position 0 are ignored)
+__device__ __forceinline__ uint32_t crc_chunk_from(const CrcLds* T, uint32_t r, uint4 v, int64_t p) {
   if (p < 4) {
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int64_t pq = p + 16 * q;
-      v[q].x = crc_edge(v[q].x, pq);
-      v[q].y = crc_edge(v[q].y, pq + 4);
-      v[q].z = crc_edge(v[q].z, pq + 8);
-      v[q].w = crc_edge(v[q].w, pq + 12);
-    }
+    v.x = crc_edge(v.x, p);
+    v.y = crc_edge(v.y, p + 4);
+    v.z = crc_edge(v.z, p + 8);
+    v.w = crc_edge(v.w, p + 12);
   }
-  uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-  r0 = crc_step4(tl, r0, v[0].x);
-  r1 = crc_step4(tl, r1, v[1].x);
-  r2 = crc_step4(tl, r2, v[2].x);
-  r3 = crc_step4(tl, r3, v[3].x);
-  r0 = crc_step4(tl, r0, v[0].y);
-  r1 = crc_step4(tl, r1, v[1].y);
-  r2 = crc_step4(tl, r2, v[2].y);
-  r3 = crc_step4(tl, r3, v[3].y);
-  r0 = crc_step4(tl, r0, v[0].z);
-  r1 = crc_step4(tl, r1, v[1].z);
-  r2 = crc_step4(tl, r2, v[2].z);
-  r3 = crc_step4(tl, r3, v[3].z);
-  r0 = crc_step4(tl, r0, v[0].w);
-  r1 = crc_step4(tl, r1, v[1].w);
-  r2 = crc_step4(tl, r2, v[2].w);
-  r3 = crc_step4(tl, r3, v[3].w);
-  return crc_sub_shift(T, 2, r0) ^ crc_sub_shift(T, 1, r1) ^ crc_sub_shift(T, 0, r2) ^ r3;
+  r = crc_dword(T->t4, r, v.x);
+  r = crc_dword(T->t4, r, v.y);
+  r = crc_dword(T->t4, r, v.z);
+  r = crc_dword(T->t4, r, v.w);
+  return r;
 }
 
-// join the per-lane Horner sums: lane l's last unit is followed by 63 - l
-// units.  Returns the raw CRC to every lane.
+__device__ __forceinline__ uint32_t crc_chunk(const CrcLds* T, uint4 v, int64_t p) {
+  return crc_chunk_from(T, 0u, v, p);
+}
+
+// join the per-lane Horner sums: lane l's last chunk is followed by 63 - l
+// chunks.  Returns the raw CRC to every lane.
 __device__ __forceinline__ uint32_t crc_wave_join(const CrcLds* T, uint32_t acc) {
 #pragma unroll
   for (int k = 0; k < 6; k++) {
     uint32_t other = __shfl_down(acc, 1u << k, WAVE);
     if (lane_id() + (1u << k) >= WAVE) other = 0;
-    acc = crc_shift(T, k, acc) ^ other;
+    acc = crc_shift(T->sh[k], acc) ^ other;
   }
   return __shfl(acc, 0, WAVE);
 }
 
-// load the 16 message bytes at positions [p, p + 16) of msg (p + 16 > 0);
-// bytes before position 0 are not read
 __device__ __forceinline__ uint32_t ld_dword_from(const uint8_t* msg, int64_t p) {
   if (p >= 0) return ldg_u32_unaligned(msg + p);
   uint32_t v = 0;
@@ -318,6 +280,8 @@ __device__ __forceinline__ uint32_t ld_dword_from(const uint8_t* msg, int64_t p)
   return v;
 }
 
+// load the 16 message bytes at positions [p, p + 16) of msg (p + 16 > 0);
+// bytes before position 0 are not read
 __device__ __forceinline__ uint4 ld_chunk(const uint8_t* msg, int64_t p) {
   if (p >= 0) return ldg16((uint64_t)(uintptr_t)(msg + p));
   if (p + 16 <= 0) return make_uint4(0, 0, 0, 0);
@@ -326,23 +290,27 @@ __device__ __forceinline__ uint4 ld_chunk(const uint8_t* msg, int64_t p) {
 }
 
 // Raw CRC (first 4 message bytes complemented) of message bytes
-// [s0, s0 + len) of a message that starts at msg; len is a multiple of 64 or
+// [s0, s0 + len) of a message that starts at msg; len is a multiple of 16 or
 // s0 <= 0 (a segment starting before the message counts only its bytes
-// inside it).  Units are aligned to the segment end.  Every lane must call.
+// inside it).  Chunks are aligned to the segment end; a lane's chunks are
+// loaded two at a time.  Every lane must call.
 __device__ __forceinline__ uint32_t wave_raw_crc(const CrcLds* T, const uint8_t* msg, int64_t s0, uint64_t len) {
   const uint32_t l = lane_id();
-  const uint32_t* tl = crc_lane_table(T);
   const int64_t send = s0 + (int64_t)len;
-  const int64_t J = (int64_t)((len + CRC_UNIT - 1) / CRC_UNIT);
+  const int64_t J = (int64_t)((len + 15) / 16);
   uint32_t acc = 0;
-  const int64_t u_first = 63 - (int64_t)l;
-  if (u_first < J) {
-    for (int64_t u = u_first + 64 * ((J - 1 - u_first) / 64); u >= 0; u -= 64) {
-      const int64_t p = send - (int64_t)CRC_UNIT * (u + 1);
-      uint4 v[4];
-#pragma unroll
-      for (int q = 0; q < 4; q++) v[q] = ld_chunk(msg, p + 16 * q);
-      acc = crc_shift(T, 6, acc) ^ crc_unit(T, tl, v, p);
+  const int64_t c_first = 63 - (int64_t)l;
+  if (c_first < J) {
+    int64_t c = c_first + 64 * ((J - 1 - c_first) / 64);
+    for (; c >= 64; c -= 128) {
+      const int64_t p0 = send - 16 * (c + 1), p1 = p0 + 1024;
+      const uint4 v0 = ld_chunk(msg, p0), v1 = ld_chunk(msg, p1);
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v0, p0);
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v1, p1);
+    }
+    if (c >= 0) {
+      const int64_t p0 = send - 16 * (c + 1);
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, ld_chunk(msg, p0), p0);
     }
   }
   return crc_wave_join(T, acc);
@@ -372,12 +340,12 @@ __device__ __host__ inline uint32_t gf2_xpow8n(uint64_t n) {
 }
 
 // Raw CRC of a whole message of n bytes by one workgroup of 16 waves: wave w
-// folds segment w (segments of L bytes, L a multiple of 64, aligned to the
+// folds segment w (segments of L bytes, L a multiple of 16, aligned to the
 // message end; leading segments may start before the message and contribute
 // only their bytes inside it), and the segments are joined by multiplication
 // with x^(8 L) mod P.  Every thread must call; the result is valid in thread 0.
 __device__ __forceinline__ uint32_t wg16_raw_crc(const CrcLds* T, const uint8_t* msg, uint64_t n, uint32_t* part) {
-  const uint64_t L = ((n + 15) / 16 + CRC_UNIT - 1) / CRC_UNIT * CRC_UNIT;
+  const uint64_t L = (((n + 15) / 16) + 15) / 16 * 16;
   const uint32_t w = threadIdx.x / WAVE;
   const int64_t s0 = (int64_t)n - (int64_t)(16 - w) * (int64_t)L;
   const uint32_t raw = (s0 + (int64_t)L > 0) ? wave_raw_crc(T, msg, s0, L) : 0u;

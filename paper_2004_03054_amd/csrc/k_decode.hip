@@ -104,10 +104,8 @@ __device__ inline void finish_crc(const WalkSet& ws, const Inputs& in, uint32_t 
   ok[b] = good;
 }
 
-// One wave per data block.  Blocks of up to two wave steps (two 64-byte
-// units per lane, 8 KiB) are folded from registers loaded in one go, with the
-// stored checksum; the next block's handle is loaded while the current block
-// is folded.  Longer blocks take the plain loop of wave_raw_crc.
+// One wave per data block; the next block's handle is loaded while the
+// current block is folded, and the stored checksum is loaded before the fold.
 struct CrcBlk {
   const uint8_t* p;
   uint64_t n;  // message bytes (contents + type byte); 0: none
@@ -149,7 +147,6 @@ __global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const 
   const uint64_t nb = *ws.n_dev;
   const uint32_t waves = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
   const uint64_t stride = (uint64_t)gridDim.x * waves;
-  const uint32_t* tl = crc_lane_table(&T);
   const uint32_t l = lane_id();
   uint64_t bytes = 0;
   uint64_t b = (uint64_t)blockIdx.x * waves + wv;
@@ -158,29 +155,14 @@ __global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const 
     const CrcBlk kn = crc_blk(ws, b + stride, nb);
     if (k.skip) {
       if (l == 0) ok[b] = 0;
-    } else if (k.n <= 2 * 64 * CRC_UNIT) {
-      const int64_t J = (int64_t)((k.n + CRC_UNIT - 1) / CRC_UNIT);
-      const int64_t ua = 127 - (int64_t)l, ub = 63 - (int64_t)l;  // ua comes first in the message
-      const int64_t pa = (int64_t)k.n - (int64_t)CRC_UNIT * (ua + 1), pb = (int64_t)k.n - (int64_t)CRC_UNIT * (ub + 1);
-      uint4 va[4], vb[4];
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        va[q] = ua < J ? ld_chunk(k.p, pa + 16 * q) : make_uint4(0, 0, 0, 0);
-        vb[q] = ub < J ? ld_chunk(k.p, pb + 16 * q) : make_uint4(0, 0, 0, 0);
-      }
+    } else {
       uint32_t stored = 0, type = 0;
       if (l == 0) {
         stored = ldg_u32_unaligned(k.p + k.n);
         type = k.p[k.n - 1];
       }
-      const uint32_t ca = ua < J ? crc_unit(&T, tl, va, pa) : 0u;
-      const uint32_t cb = ub < J ? crc_unit(&T, tl, vb, pb) : 0u;
-      const uint32_t raw = crc_wave_join(&T, crc_shift(&T, 6, ca) ^ cb);
-      if (l == 0) check_crc(ws, in, (uint32_t)b, raw, stored, type, ok, err);
-      bytes += k.n + 4;
-    } else {
       const uint32_t raw = wave_raw_crc(&T, k.p, 0, k.n);
-      if (l == 0) finish_crc(ws, in, (uint32_t)b, raw, ok, err);
+      if (l == 0) check_crc(ws, in, (uint32_t)b, raw, stored, type, ok, err);
       bytes += k.n + 4;
     }
     k = kn;

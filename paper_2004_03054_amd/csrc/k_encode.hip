@@ -164,6 +164,7 @@ __device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t nw, uint32_t i, int64_
 constexpr uint32_t ENC_B = 2;  // whole value chunks per lane in flight with the byte tasks
 
 constexpr uint32_t ENC_OVERLAP = 16;  // entries shared by consecutive windows (>= 64 bytes)
+constexpr uint32_t GEN_UNIT = 64;     // bytes a lane folds per step in k_encode_gen
 
 __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -172,8 +173,13 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
   __syncthreads();
   const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
   const uint32_t waves = blockDim.x / WAVE;
-  const uint32_t* tl = crc_lane_table(T);
   EncLds* L = (EncLds*)(smem + sizeof(CrcLds)) + wv;
+  // a lane folds 64-byte units (four chunks in sequence); units are joined
+  // by multiplications with x^(8 m) mod P for m = 4096 (between a lane's
+  // units) and 64 * 2^k (lanes)
+  uint32_t kj[7];
+#pragma unroll
+  for (int k = 0; k < 7; k++) kj[k] = gf2_xpow8n((uint64_t)GEN_UNIT << k);
   const uint64_t nb = *A.nblocks;
   for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
     const BlockRec B = A.blk[b];
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
     const int64_t n = (int64_t)size + 1;
     uint8_t* dst = A.out + B.dst;
     const uint32_t* blk_off = A.ent_off + s0;
-    const int64_t JU = (n + CRC_UNIT - 1) / CRC_UNIT;
+    const int64_t JU = (n + GEN_UNIT - 1) / GEN_UNIT;
     const int64_t u_first = 63 - (int64_t)l;
     int64_t uu = u_first < JU ? u_first + 64 * ((JU - 1 - u_first) / 64) : -1;
     uint32_t acc = 0;
@@ -215,7 +221,7 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
       const int64_t hi = last ? n : (int64_t)L->st[nw - ENC_OVERLAP];
       uint32_t cur = 0;
       while (uu >= 0) {
-        const int64_t p = n - (int64_t)CRC_UNIT * (uu + 1);
+        const int64_t p = n - (int64_t)GEN_UNIT * (uu + 1);
         if ((p < 0 ? 0 : p) >= hi) break;
         uint4 v[4];
         uint32_t slow = 0;
@@ -265,16 +271,24 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
               if (p0 + k >= 0) dst[p0 + k] = vb[k];
           }
         }
-        acc = crc_shift(T, 6, acc) ^ crc_unit(T, tl, v, p);
+        uint32_t ur = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; q++) ur = crc_chunk_from(T, ur, v[q], p + 16 * q);
+        acc = gf2_mulmod(acc, kj[6]) ^ ur;
         uu -= 64;
       }
       wave_sync();
       if (last) break;
       k0 = k1 - ENC_OVERLAP;
     }
-    const uint32_t raw = crc_wave_join(T, acc);
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      uint32_t other = __shfl_down(acc, 1u << k, WAVE);
+      if (l + (1u << k) >= WAVE) other = 0;
+      acc = gf2_mulmod(acc, kj[k]) ^ other;
+    }
     if (l == 0) {
-      const uint32_t m = crc_mask(raw ^ 0xFFFFFFFFu);
+      const uint32_t m = crc_mask(acc ^ 0xFFFFFFFFu);
       __builtin_memcpy(dst + n, &m, 4);
     }
   }
@@ -453,30 +467,21 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
       d[4] = 0;
     }
     wave_sync();
-    // --- store and checksum: lane l takes the 64-byte units u = 63 - l + 64 i
+    // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i
     uint32_t acc = 0;
-    const uint32_t* tl = crc_lane_table(T);
-    const int64_t JU = ((int64_t)n + CRC_UNIT - 1) / CRC_UNIT;
-    const int64_t u_first = 63 - (int64_t)l;
-    if (u_first < JU) {
-      for (int64_t u = u_first + 64 * ((JU - 1 - u_first) / 64); u >= 0; u -= 64) {
-        const int64_t p = (int64_t)n - (int64_t)CRC_UNIT * (u + 1);
-        const uint8_t* src = stage_end - CRC_UNIT * (u + 1);
-        uint4 v[4];
-#pragma unroll
-        for (uint32_t q = 0; q < 4; q++) {
-          v[q] = *(const uint4*)(src + 16 * q);
-          const int64_t p0 = p + 16 * q;
-          if (p0 >= 0) {
-            __builtin_memcpy(dst + p0, &v[q], 16);
-          } else if (p0 + 16 > 0) {
-            const uint8_t* vb = (const uint8_t*)&v[q];
-            for (int k = 0; k < 16; k++)
-              if (p0 + k >= 0) dst[p0 + k] = vb[k];
-          }
-        }
-        acc = crc_shift(T, 6, acc) ^ crc_unit(T, tl, v, p);
+    const int64_t c_first = 63 - (int64_t)l;
+    for (int64_t c = c_first < (int64_t)J16 ? c_first + 64 * (((int64_t)J16 - 1 - c_first) / 64) : -1; c >= 0;
+         c -= 64) {
+      const int64_t p0 = (int64_t)n - 16 * (c + 1);
+      const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
+      if (p0 >= 0) {
+        __builtin_memcpy(dst + p0, &v, 16);
+      } else {
+        const uint8_t* vb = (const uint8_t*)&v;
+        for (int k = 0; k < 16; k++)
+          if (p0 + k >= 0) dst[p0 + k] = vb[k];
       }
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
     }
     const uint32_t raw = crc_wave_join(T, acc);
     if (l == 0) {

@@ -27,10 +27,9 @@ using namespace luda;
 namespace {
 
 // ---------------------------------------------------------------------------
-// CRC32C tables built on the host and copied into LDS by the kernels: the
-// byte table in 32 copies (one per LDS bank; entry x of copy j at word
-// 32 x + j), and shifts by 64 * 2^k zero bytes (k = 0..6) applied by
-// nibbles: sh[k][j][v] = shift of (v << 4 j).
+// CRC32C tables built on the host and copied into LDS by the kernels:
+// slicing-by-4 tables and "shift by 16 * 2^k zero bytes" (k = 0..6), each a
+// set of four 256-entry tables indexed by the bytes of the 32-bit register.
 
 constexpr uint32_t POLY = 0x82F63B78u;  // CRC32C, reflected
 constexpr int NSH = 7;
@@ -38,9 +37,8 @@ constexpr int NSH = 7;
 uint32_t step_byte(uint32_t r, uint8_t b, const uint32_t* t0) { return t0[(r ^ b) & 0xFF] ^ (r >> 8); }
 
 struct CrcTables {
-  uint32_t t[256][32];
-  uint32_t sh[NSH][8][16];
-  uint32_t ss[3][8][16];  // shifts by 16, 32, 48 zero bytes
+  uint32_t t4[4][256];
+  uint32_t sh[NSH][4][256];
 };
 constexpr size_t CRC_LDS_BYTES = sizeof(CrcTables);
 
@@ -57,23 +55,19 @@ uint32_t shift_zeros(uint32_t r, uint64_t m, const uint32_t* t0) {
   return r;
 }
 
-uint32_t apply_shift(const uint32_t sh[8][16], uint32_t c) {
-  uint32_t r = 0;
-  for (int j = 0; j < 8; j++) r ^= sh[j][(c >> (4 * j)) & 15];
-  return r;
+uint32_t apply_shift(const uint32_t sh[4][256], uint32_t c) {
+  return sh[0][c & 0xFF] ^ sh[1][(c >> 8) & 0xFF] ^ sh[2][(c >> 16) & 0xFF] ^ sh[3][c >> 24];
 }
 
 void build_crc_tables(CrcTables* T) {
   uint32_t t0[256];
   byte_table(t0);
-  for (int x = 0; x < 256; x++)
-    for (int j = 0; j < 32; j++) T->t[x][j] = t0[x];
+  for (int b = 0; b < 256; b++) T->t4[0][b] = t0[b];
+  for (int k = 1; k < 4; k++)
+    for (int b = 0; b < 256; b++) T->t4[k][b] = (T->t4[k - 1][b] >> 8) ^ t0[T->t4[k - 1][b] & 0xFF];
   for (int k = 0; k < NSH; k++)
-    for (int j = 0; j < 8; j++)
-      for (uint32_t v = 0; v < 16; v++) T->sh[k][j][v] = shift_zeros(v << (4 * j), 64ull << k, t0);
-  for (int m = 0; m < 3; m++)
-    for (int j = 0; j < 8; j++)
-      for (uint32_t v = 0; v < 16; v++) T->ss[m][j][v] = shift_zeros(v << (4 * j), 16ull * (m + 1), t0);
+    for (int i = 0; i < 4; i++)
+      for (uint32_t v = 0; v < 256; v++) T->sh[k][i][v] = shift_zeros(v << (8 * i), 16ull << k, t0);
 }
 
 // GF(2) products mod P in the reflected representation, for the self check
@@ -656,7 +650,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     // staged encoder when a block message (plus the entry window) fits in
     // LDS for at least two waves; otherwise the register generator
     const size_t win = (sizeof(EncWin) + 15) & ~size_t(15);
-    const size_t per_wave = win + ((size_t(max_bsize) + 1 + CRC_UNIT - 1) / CRC_UNIT) * CRC_UNIT + 64;
+    const size_t per_wave = win + ((size_t(max_bsize) + 1 + 15) & ~size_t(15)) + 16;
     const size_t budget = c->lds_limit - 2048 - CRC_LDS_BYTES;
     const size_t sw = std::min<size_t>(c->tp.encode_waves, budget / per_wave);
     const bool staged = sw >= 2 && per_wave < (1u << 31);
@@ -1283,31 +1277,29 @@ int luda_selftest_crc(void) {
   build_crc_tables(&T);
   uint32_t t0[256];
   byte_table(t0);
-  // every bank copy of the byte table is the table
-  for (int x = 0; x < 256; x++)
-    for (int j = 0; j < 32; j++)
-      if (T.t[x][j] != t0[x]) return 1;
-  // the byte table against the bitwise definition on one byte
-  for (uint32_t b = 0; b < 256; b += 51) {
+  // the byte table against the bitwise definition
+  for (uint32_t b = 0; b < 256; b++) {
     uint32_t r = b;
     for (int k = 0; k < 8; k++) r = (r & 1u) ? (r >> 1) ^ POLY : (r >> 1);
-    if (t0[b] != r) return 2;
+    if (t0[b] != r || T.t4[0][b] != r) return 1;
   }
+  // slicing-by-4 against bytewise on one dword
+  const uint32_t c = 0xDEADBEEFu, d = 0x01020304u;
+  uint32_t r = c;
+  for (int i = 0; i < 4; i++) r = step_byte(r, (uint8_t)(d >> (8 * i)), t0);
+  const uint32_t y = c ^ d;
+  if (r != (T.t4[3][y & 0xFF] ^ T.t4[2][(y >> 8) & 0xFF] ^ T.t4[1][(y >> 16) & 0xFF] ^ T.t4[0][y >> 24])) return 2;
   // shift tables and GF(2) multipliers against zero-byte processing
   uint32_t x = 0x12345678u;
   for (int k = 0; k < NSH; k++) {
-    const uint64_t m = 64ull << k;
-    const uint32_t r = shift_zeros(x, m, t0);
-    if (apply_shift(T.sh[k], x) != r) return 3;
-    if (h_mulmod(x, h_xpow8n(m)) != r) return 4;
+    const uint64_t m = 16ull << k;
+    const uint32_t z = shift_zeros(x, m, t0);
+    if (apply_shift(T.sh[k], x) != z) return 3;
+    if (h_mulmod(x, h_xpow8n(m)) != z) return 4;
     x = x * 2654435761u + 12345u;
   }
   for (uint64_t m = 1; m < 300; m += 37)
     if (h_mulmod(x, h_xpow8n(m)) != shift_zeros(x, m, t0)) return 5;
-  for (int m = 0; m < 3; m++) {
-    if (apply_shift(T.ss[m], x) != shift_zeros(x, 16ull * (m + 1), t0)) return 6;
-    x = x * 2654435761u + 12345u;
-  }
   return 0;
 }
 
