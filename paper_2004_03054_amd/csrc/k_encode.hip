@@ -311,8 +311,24 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   EncWin* W = (EncWin*)wbase;
   uint8_t* stage_end = wbase + A.wave_lds;
   const uint64_t nb = *A.nblocks;
-  for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
-    const BlockRec B = A.blk[b];
+  const uint64_t stride = (uint64_t)gridDim.x * waves;
+  // the next block's record and its first window of entry records are
+  // loaded while the current block is stored and checksummed
+  uint64_t b = (uint64_t)blockIdx.x * waves + wv;
+  BlockRec Bn;
+  EncRec rn;
+  uint32_t stn = 0;
+  if (b < nb) {
+    Bn = A.blk[b];
+    if (l < min(Bn.cnt, ENC_SW)) {
+      rn = A.rec[Bn.s0 + l];
+      stn = A.ent_off[Bn.s0 + l];
+    }
+  }
+  for (; b < nb; b += stride) {
+    const BlockRec B = Bn;
+    const EncRec r0 = rn;
+    const uint32_t st0 = stn;
     const uint32_t R = B.R, cnt = B.cnt, size = B.size;
     const uint64_t s0 = B.s0;
     const uint32_t nrest = (cnt + R - 1) / R;
@@ -331,8 +347,8 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
       uint32_t tasks = 0, pieces = 0;
       if (l < nw) {
         const uint32_t i = k0 + l;
-        const EncRec r = A.rec[s0 + i];
-        const uint32_t st = blk_off[i];
+        const EncRec r = k0 ? A.rec[s0 + i] : r0;
+        const uint32_t st = k0 ? blk_off[i] : st0;
         const uint32_t shared = (i % R == 0) ? 0u : r.shared;
         const uint32_t ns = r.ulen + 8 - shared;
         uint32_t la, lb, lc;
@@ -467,6 +483,14 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
       d[4] = 0;
     }
     wave_sync();
+    // next block's records (in flight during the store and checksum)
+    if (b + stride < nb) {
+      Bn = A.blk[b + stride];
+      if (l < min(Bn.cnt, ENC_SW)) {
+        rn = A.rec[Bn.s0 + l];
+        stn = A.ent_off[Bn.s0 + l];
+      }
+    }
     // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i
     uint32_t acc = 0;
     const int64_t c_first = 63 - (int64_t)l;

@@ -153,8 +153,8 @@ __device__ inline T block_excl_scan(T v, T* sh, T* total) {
   return base + x - v;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_scan_tiles(const T* in, uint64_t cap, const uint64_t* n_dev, T* out,
+template <typename TI, typename T>
+__global__ void __launch_bounds__(256) k_scan_tiles(const TI* in, uint64_t cap, const uint64_t* n_dev, T* out,
                                                     T* tile_sums) {
   __shared__ T sh[4];
   const uint64_t n = n_dev ? *n_dev : cap;
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_scan_tiles(const T* in, uint64_t cap, c
   T s = 0;
 #pragma unroll
   for (uint32_t k = 0; k < SCAN_PER; k++) {
-    vals[k] = (base + k < n) ? in[base + k] : (T)0;
+    vals[k] = (base + k < n) ? (T)in[base + k] : (T)0;
     s += vals[k];
   }
   T total;
@@ -207,17 +207,52 @@ __global__ void __launch_bounds__(256) k_scan_add(T* out, uint64_t cap, const ui
     if (base + k < n) out[base + k] += add;
 }
 
-template <typename T>
-void launch_scan(const T* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st) {
-  const uint64_t ntiles = cap ? (cap + SCAN_TILE - 1) / SCAN_TILE : 1;
-  hipLaunchKernelGGL(k_scan_tiles<T>, dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, in, cap, n_dev, out,
+// one workgroup for short arrays: passes of SCAN_TILE elements with a carry
+template <typename TI, typename T>
+__global__ void __launch_bounds__(256) k_scan_one(const TI* in, uint64_t cap, const uint64_t* n_dev, T* out) {
+  __shared__ T sh[4];
+  const uint64_t n = n_dev ? *n_dev : cap;
+  T carry = 0;
+  for (uint64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+    const uint64_t base = t0 + (uint64_t)threadIdx.x * SCAN_PER;
+    T vals[SCAN_PER];
+    T s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER; k++) {
+      vals[k] = (base + k < n) ? (T)in[base + k] : (T)0;
+      s += vals[k];
+    }
+    T total;
+    T pre = carry + block_excl_scan<T>(s, sh, &total);
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER; k++) {
+      if (base + k < n) out[base + k] = pre;
+      pre += vals[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+template <typename TI, typename T>
+void launch_scan(const TI* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st) {
+  if (cap <= SCAN_ONE_MAX) {
+    hipLaunchKernelGGL((k_scan_one<TI, T>), dim3(1), dim3(SCAN_THREADS), 0, st, in, cap, n_dev, out);
+    return;
+  }
+  const uint64_t ntiles = (cap + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL((k_scan_tiles<TI, T>), dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, in, cap, n_dev, out,
                      scratch);
   hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(SCAN_THREADS), 0, st, scratch, cap, n_dev, scratch + ntiles);
   hipLaunchKernelGGL(k_scan_add<T>, dim3((uint32_t)ntiles), dim3(SCAN_THREADS), 0, st, out, cap, n_dev, scratch,
                      scratch + ntiles);
 }
 
-template void launch_scan<uint32_t>(const uint32_t*, uint64_t, const uint64_t*, uint32_t*, uint32_t*, hipStream_t);
-template void launch_scan<uint64_t>(const uint64_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t*, hipStream_t);
+template void launch_scan<uint32_t, uint32_t>(const uint32_t*, uint64_t, const uint64_t*, uint32_t*, uint32_t*,
+                                              hipStream_t);
+template void launch_scan<uint32_t, uint64_t>(const uint32_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t*,
+                                              hipStream_t);
+template void launch_scan<uint64_t, uint64_t>(const uint64_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t*,
+                                              hipStream_t);
 
 }  // namespace luda

@@ -70,11 +70,6 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
   }
 }
 
-__global__ void k_u32_to_u64(const uint32_t* a, uint64_t* b, uint64_t n) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
-}
-
 // encoder records of the output blocks (after the file layout)
 __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
                             BlockRec* br) {

@@ -94,8 +94,11 @@ __global__ void k_scatter(const uint32_t* ord, const uint32_t* keep, const uint3
                           uint32_t* surv);
 // exclusive scan of n values (n from the device when n_dev is given; cap
 // bounds it): out[0..n) and out[n] = total.  scratch holds cap/2048 + 2.
-template <typename T>
-void launch_scan(const T* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st);
+// Input values of type TI are summed as T.  Up to SCAN_ONE_MAX elements one
+// workgroup does it in one launch.
+constexpr uint64_t SCAN_ONE_MAX = 16384;
+template <typename TI, typename T>
+void launch_scan(const TI* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st);
 constexpr uint32_t MERGE_ITEMS_PER_THREAD = 8;
 
 // plan
@@ -252,7 +255,6 @@ __global__ void k_ranges(const uint64_t* ient, const uint64_t* ibase, const uint
                          uint64_t* out);
 __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0);
 __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats);
-__global__ void k_u32_to_u64(const uint32_t* a, uint64_t* b, uint64_t n);
 __global__ void k_file_entries(OutFiles of, OutBlocks ob, uint64_t nf);
 __global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen);
 __global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,

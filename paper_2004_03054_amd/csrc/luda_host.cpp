@@ -494,7 +494,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   uint64_t* ob_excl = dbuf<uint64_t>(c, "ob_excl", OB + 1);
   uint64_t* scan_tmp = dbuf<uint64_t>(c, "scan_tmp64", OB / 2048 + 8);
-  launch_scan<uint64_t>(ob.full, OB, nullptr, ob_excl, scan_tmp, st);
+  launch_scan<uint64_t, uint64_t>(ob.full, OB, nullptr, ob_excl, scan_tmp, st);
   LAUNCH_CHECK();
 
   // --- file cuts over output blocks: chunk list built on the device
@@ -546,7 +546,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   hipLaunchKernelGGL(k_file_pre, dim3(blocks_for(FC)), dim3(256), 0, st, job_f0, J, job_ob0, file_first, ob_excl,
                      FC, of);
   LAUNCH_CHECK();
-  launch_scan<uint64_t>(of.nwin, FC, nullptr, of.w0, scan_tmp, st);
+  launch_scan<uint64_t, uint64_t>(of.nwin, FC, nullptr, of.w0, scan_tmp, st);
   LAUNCH_CHECK();
   // sizes needed to allocate window arrays and the encoder's LDS
   uint32_t* stats = dbuf<uint32_t>(c, "plan_stats", 4);
@@ -585,17 +585,14 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
                      of.w0, NF, of, P.d_jobs, win_keys, NW, win_bytes, win_file, wstat);
   LAUNCH_CHECK();
   uint64_t* scan_tmpw = dbuf<uint64_t>(c, "scan_tmpw", NW / 2048 + 8);
-  launch_scan<uint64_t>(win_bytes, NW, nullptr, win_off, scan_tmpw, st);
+  launch_scan<uint64_t, uint64_t>(win_bytes, NW, nullptr, win_off, scan_tmpw, st);
   LAUNCH_CHECK();
-  uint64_t* ie64 = dbuf<uint64_t>(c, "ie64", NBLK);
   uint64_t* ie_off = dbuf<uint64_t>(c, "ie_off", NBLK + 1);
-  hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob.ie_size, ie64, NBLK);
-  LAUNCH_CHECK();
-  launch_scan<uint64_t>(ie64, NBLK, nullptr, ie_off, scan_tmp, st);
+  launch_scan<uint32_t, uint64_t>(ob.ie_size, NBLK, nullptr, ie_off, scan_tmp, st);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_file_layout, dim3(blocks_for(NF)), dim3(256), 0, st, job_f0 + J, of, win_off, ie_off, NF);
   LAUNCH_CHECK();
-  launch_scan<uint64_t>(of.size, NF, nullptr, of.out, scan_tmp, st);
+  launch_scan<uint64_t, uint64_t>(of.size, NF, nullptr, of.out, scan_tmp, st);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, NF);
   LAUNCH_CHECK();
@@ -841,7 +838,6 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   IX.nr = dbuf<uint32_t>(c, "ix_nr", NG);
   IX.ibase = dbuf<uint64_t>(c, "ix_ibase", (uint64_t)NG + 1);
   IX.ok = dbuf<uint8_t>(c, "ix_ok", NG);
-  uint64_t* nr64 = dbuf<uint64_t>(c, "nr64", NG);
   if (NG) {
     hipLaunchKernelGGL(k_footer, dim3(blocks_for(NG)), dim3(256), 0, st, in, ix, err);
     LAUNCH_CHECK();
@@ -849,10 +845,9 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_crc_big, dim3(NG), dim3(1024), 0, st, ix, in, c->d_crc, IX.ok, err);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NG)), dim3(256), 0, st, IX.nr, nr64, (uint64_t)NG);
-    LAUNCH_CHECK();
+
     uint64_t* scan_g = dbuf<uint64_t>(c, "scan_tmp_g", NG / 2048 + 8);
-    launch_scan<uint64_t>(nr64, NG, nullptr, IX.ibase, scan_g, st);
+    launch_scan<uint32_t, uint64_t>(IX.nr, NG, nullptr, IX.ibase, scan_g, st);
     LAUNCH_CHECK();
     Mail m(c);
     const uint64_t* p = m.add(IX.ibase + NG, 1);
@@ -879,11 +874,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_walk<0, 0>), dim3(stride_grid(c, IX.NI)), dim3(256), 0, st, WA);
     LAUNCH_CHECK();
-    uint64_t* c64 = dbuf<uint64_t>(c, "icnt64", IX.NI);
-    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(IX.NI)), dim3(256), 0, st, IX.icnt, c64, IX.NI);
-    LAUNCH_CHECK();
     uint64_t* scan_i = dbuf<uint64_t>(c, "scan_tmp_i", IX.NI / 2048 + 8);
-    launch_scan<uint64_t>(c64, IX.NI, nullptr, IX.ient, scan_i, st);
+    launch_scan<uint32_t, uint64_t>(IX.icnt, IX.NI, nullptr, IX.ient, scan_i, st);
     LAUNCH_CHECK();
     Mail m(c);
     const uint64_t* p = m.add(IX.ient + IX.NI, 1);
@@ -925,11 +917,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   if (NB) {
     hipLaunchKernelGGL(k_blk_nr, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, in, DB.nr, err);
     LAUNCH_CHECK();
-    uint64_t* nrb64 = dbuf<uint64_t>(c, "db_nr64", NB);
-    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(NB)), dim3(256), 0, st, DB.nr, nrb64, NB);
-    LAUNCH_CHECK();
     uint64_t* scan_b = dbuf<uint64_t>(c, "scan_tmp_b", NB / 2048 + 8);
-    launch_scan<uint64_t>(nrb64, NB, nullptr, DB.ibase, scan_b, st);
+    launch_scan<uint32_t, uint64_t>(DB.nr, NB, nullptr, DB.ibase, scan_b, st);
     LAUNCH_CHECK();
     {
       const uint32_t cw = c->tp.crc_waves;
@@ -977,11 +966,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       LAUNCH_CHECK();
       kt.stop();
     }
-    uint64_t* c64 = dbuf<uint64_t>(c, "icnt64", DB.NI);
-    hipLaunchKernelGGL(k_u32_to_u64, dim3(blocks_for(DB.NI)), dim3(256), 0, st, DB.icnt, c64, DB.NI);
-    LAUNCH_CHECK();
     uint64_t* scan_e = dbuf<uint64_t>(c, "scan_tmp_e", DB.NI / 2048 + 8);
-    launch_scan<uint64_t>(c64, DB.NI, nullptr, DB.ient, scan_e, st);
+    launch_scan<uint32_t, uint64_t>(DB.icnt, DB.NI, nullptr, DB.ient, scan_e, st);
     LAUNCH_CHECK();
     Mail m(c);
     const uint64_t* p = m.add(DB.ient + DB.NI, 1);
@@ -1151,7 +1137,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
                        shadowed, tomb, d_active);
     LAUNCH_CHECK();
   }
-  launch_scan<uint32_t>(keep, N, nullptr, kpos, scan32, st);
+  launch_scan<uint32_t, uint32_t>(keep, N, nullptr, kpos, scan32, st);
   LAUNCH_CHECK();
   if (N) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N)), dim3(256), 0, st, ord, keep, kpos, N, surv);
