@@ -78,6 +78,14 @@ __device__ inline uint4 ldg16(uint64_t addr) {
   return v;
 #endif
 }
+// one byte at a global address
+__device__ inline uint32_t ldg_u8(uint64_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(1))) uint8_t*)addr;
+#else
+  return *(const uint8_t*)addr;
+#endif
+}
 // 16 bytes at a 16-byte aligned global address
 __device__ inline uint4 ldg16a(uint64_t addr) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -216,6 +224,16 @@ struct CrcLds {
   uint32_t t4[4][256];
   uint32_t sh[7][4][256];
 };
+// The same with tables of 11-bit indices: the raw CRC of a 4-byte word x is
+// linear in x, so it is the xor of the CRCs of its bit fields [0, 11),
+// [11, 22) and [22, 32), three lookups per word instead of four.  The global
+// table image has this layout; kernels that need only CrcLds copy its head.
+struct CrcLds11 {
+  CrcLds b;
+  uint32_t u0[2048];
+  uint32_t u1[2048];
+  uint32_t u2[1024];
+};
 
 __device__ __forceinline__ uint32_t crc_dword(const uint32_t (*t4)[256], uint32_t c, uint32_t d) {
   const uint32_t x = c ^ d;
@@ -289,29 +307,55 @@ __device__ __forceinline__ uint4 ld_chunk(const uint8_t* msg, int64_t p) {
                     ld_dword_from(msg, p + 12));
 }
 
+__device__ __forceinline__ uint32_t crc_dword11(const CrcLds11* T, uint32_t c, uint32_t d) {
+  const uint32_t x = c ^ d;
+  return T->u0[x & 0x7FF] ^ T->u1[(x >> 11) & 0x7FF] ^ T->u2[x >> 22];
+}
+
+__device__ __forceinline__ uint32_t crc_chunk11(const CrcLds11* T, uint4 v) {
+  uint32_t r = crc_dword11(T, 0u, v.x);
+  r = crc_dword11(T, r, v.y);
+  r = crc_dword11(T, r, v.z);
+  return crc_dword11(T, r, v.w);
+}
+
+// raw CRC of one 16-byte chunk with no message position below 4 in it
+__device__ __forceinline__ uint32_t crc_chunk_plain(const CrcLds* T, uint4 v) {
+  uint32_t r = crc_dword(T->t4, 0u, v.x);
+  r = crc_dword(T->t4, r, v.y);
+  r = crc_dword(T->t4, r, v.z);
+  return crc_dword(T->t4, r, v.w);
+}
+
 // Raw CRC (first 4 message bytes complemented) of message bytes
 // [s0, s0 + len) of a message that starts at msg; len is a multiple of 16 or
 // s0 <= 0 (a segment starting before the message counts only its bytes
-// inside it).  Chunks are aligned to the segment end; a lane's chunks are
-// loaded two at a time.  Every lane must call.
+// inside it).  Chunks are aligned to the segment end.  A lane takes its
+// chunks first to last; the ones that reach below message position 4 come
+// first and are folded by the edge rules, the rest plainly, CRC_Q chunks at
+// a time with all their loads issued before the first fold.  Every lane
+// must call.
+constexpr int CRC_Q = 5;
 __device__ __forceinline__ uint32_t wave_raw_crc(const CrcLds* T, const uint8_t* msg, int64_t s0, uint64_t len) {
   const uint32_t l = lane_id();
   const int64_t send = s0 + (int64_t)len;
   const int64_t J = (int64_t)((len + 15) / 16);
   uint32_t acc = 0;
   const int64_t c_first = 63 - (int64_t)l;
-  if (c_first < J) {
-    int64_t c = c_first + 64 * ((J - 1 - c_first) / 64);
-    for (; c >= 64; c -= 128) {
-      const int64_t p0 = send - 16 * (c + 1), p1 = p0 + 1024;
-      const uint4 v0 = ld_chunk(msg, p0), v1 = ld_chunk(msg, p1);
-      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v0, p0);
-      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v1, p1);
-    }
-    if (c >= 0) {
-      const int64_t p0 = send - 16 * (c + 1);
-      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, ld_chunk(msg, p0), p0);
-    }
+  int64_t c = c_first < J ? c_first + 64 * ((J - 1 - c_first) / 64) : -1;
+  for (; c >= 0 && send - 16 * (c + 1) < 4; c -= 64) {
+    const int64_t p0 = send - 16 * (c + 1);
+    acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, ld_chunk(msg, p0), p0);
+  }
+  const uint8_t* e = msg + send;  // chunk c is [e - 16 (c + 1), e - 16 c)
+  for (; c >= 0; c -= 64 * CRC_Q) {
+    uint4 v[CRC_Q];
+#pragma unroll
+    for (int q = 0; q < CRC_Q; q++)
+      if (c - 64 * q >= 0) v[q] = ldg16((uint64_t)(uintptr_t)(e - 16 * (c - 64 * q + 1)));
+#pragma unroll
+    for (int q = 0; q < CRC_Q; q++)
+      if (c - 64 * q >= 0) acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, v[q]);
   }
   return crc_wave_join(T, acc);
 }
@@ -359,11 +403,12 @@ __device__ __forceinline__ uint32_t wg16_raw_crc(const CrcLds* T, const uint8_t*
   return acc;
 }
 
-// cooperative load of the global CRC tables into LDS
-__device__ __forceinline__ void load_crc_tables(CrcLds* dst, const uint32_t* src, int tid, int nthreads) {
+// cooperative load of the global CRC tables (the head of the image) into LDS
+template <typename L = CrcLds>
+__device__ __forceinline__ void load_crc_tables(L* dst, const uint32_t* src, int tid, int nthreads) {
   uint4* d = (uint4*)dst;
   const uint4* s4 = (const uint4*)src;
-  const int n = (int)(sizeof(CrcLds) / 16);
+  const int n = (int)(sizeof(L) / 16);
   for (int i = tid; i < n; i += nthreads) d[i] = s4[i];
 }
 

@@ -104,8 +104,12 @@ __device__ inline void finish_crc(const WalkSet& ws, const Inputs& in, uint32_t 
   ok[b] = good;
 }
 
-// One wave per data block; the next block's handle is loaded while the
-// current block is folded, and the stored checksum is loaded before the fold.
+// One wave per data block.  Block handles are loaded two blocks ahead and
+// a lane's first CRC_Q chunks one block ahead, so that the loads of the next
+// block are in flight while the current one is folded.  Every load of the
+// loop is issued by every lane (a lane with nothing to load reads a fixed
+// valid address and drops the data): the wait for one load then never has
+// to wait for the loads issued after it.
 struct CrcBlk {
   const uint8_t* p;
   uint64_t n;  // message bytes (contents + type byte); 0: none
@@ -113,61 +117,117 @@ struct CrcBlk {
 };
 
 __device__ __forceinline__ CrcBlk crc_blk(const WalkSet& ws, uint64_t b, uint64_t nb) {
+  const uint64_t bb = b < nb ? b : nb - 1;  // nb > 0
   CrcBlk r;
-  r.p = nullptr;
-  r.n = 0;
-  r.skip = false;
-  if (b < nb) {
-    r.skip = ws.skip[b] != 0;
-    r.p = (const uint8_t*)ws.ptr[b];
-    r.n = (uint64_t)ws.size[b] + 1;
-  }
+  r.skip = ws.skip[bb] != 0;
+  r.p = (const uint8_t*)ws.ptr[bb];
+  const uint32_t sz = ws.size[bb];
+  r.n = (b < nb && !r.skip) ? (uint64_t)sz + 1 : 0;
   return r;
 }
 
 // masked CRC32C of (contents || type byte) against the trailer, type 0
-__device__ inline void check_crc(const WalkSet& ws, const Inputs& in, uint32_t b, uint32_t raw, uint32_t stored,
-                                 uint32_t type, uint8_t* ok, unsigned long long* err) {
-  uint8_t good = 1;
+__device__ inline uint8_t check_crc(const WalkSet& ws, const Inputs& in, uint32_t b, uint32_t raw, uint32_t stored,
+                                    uint32_t type, unsigned long long* err) {
   if ((raw ^ 0xFFFFFFFFu) != crc_unmask(stored)) {
-    blk_err(ws, in, b, P_TRAILER, 0, EC_CHECKSUM, err);
-    good = 0;
-  } else if (type != 0) {
-    blk_err(ws, in, b, P_TRAILER, 0, EC_UNSUPPORTED, err);
-    good = 0;
+    if (lane_id() == 0) blk_err(ws, in, b, P_TRAILER, 0, EC_CHECKSUM, err);
+    return 0;
   }
-  ok[b] = good;
+  if (type != 0) {
+    if (lane_id() == 0) blk_err(ws, in, b, P_TRAILER, 0, EC_UNSUPPORTED, err);
+    return 0;
+  }
+  return 1;
+}
+
+// A lane's chunks of a message of n bytes (16-byte chunks aligned to the
+// message end, lane l taking c = 63 - l + 64 i, first to last).
+__device__ __forceinline__ int64_t crc_top_chunk(uint64_t n) {
+  const int64_t J = (int64_t)((n + 15) / 16), c0 = 63 - (int64_t)lane_id();
+  return c0 < J ? c0 + 64 * ((J - 1 - c0) / 64) : -1;
+}
+
+// The first CRC_Q chunks of this lane.  A chunk that starts before the
+// message is read from the message start (the bytes before it are shifted
+// in by the fold): a data block and its trailer are followed by at least the
+// 48-byte footer of their table, so 16 bytes from any block start are
+// readable.
+__device__ __forceinline__ void crc_load_first(const CrcBlk& k, uint64_t safe, uint4 (&v)[CRC_Q]) {
+  const int64_t ct = crc_top_chunk(k.n);
+#pragma unroll
+  for (int q = 0; q < CRC_Q; q++) {
+    const int64_t c = ct - 64 * q, p = (int64_t)k.n - 16 * (c + 1);
+    v[q] = ldg16(c >= 0 ? (uint64_t)(uintptr_t)k.p + (uint64_t)(p > 0 ? p : 0) : safe);
+  }
+}
+
+__device__ __forceinline__ uint4 bytes_up(uint4 v, uint32_t s) {  // byte k <- byte k - s, zeros below s
+  unsigned __int128 x = ((unsigned __int128)(((uint64_t)v.w << 32) | v.z) << 64) | (((uint64_t)v.y << 32) | v.x);
+  x <<= 8 * s;
+  return make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
+}
+
+// this lane's Horner sum over its chunks; v holds the first CRC_Q of them.
+// Only a lane's first chunk can reach below message position 4.
+__device__ __forceinline__ uint32_t crc_fold(const CrcLds11* T, const CrcBlk& k, const uint4 (&v)[CRC_Q]) {
+  const int64_t ct = crc_top_chunk(k.n), n = (int64_t)k.n;
+  uint32_t acc = 0;
+  if (ct >= 0) {
+    const int64_t p0 = n - 16 * (ct + 1);
+    if (p0 < 4) acc = crc_chunk(&T->b, p0 < 0 ? bytes_up(v[0], (uint32_t)-p0) : v[0], p0);
+    else acc = crc_chunk11(T, v[0]);
+  }
+#pragma unroll
+  for (int q = 1; q < CRC_Q; q++)
+    if (ct - 64 * q >= 0) acc = crc_shift(T->b.sh[6], acc) ^ crc_chunk11(T, v[q]);
+  const uint8_t* e = k.p + n;  // chunk c is [e - 16 (c + 1), e - 16 c)
+  for (int64_t c = ct - 64 * CRC_Q; c >= 0; c -= 64 * CRC_Q) {
+    uint4 w[CRC_Q];
+#pragma unroll
+    for (int q = 0; q < CRC_Q; q++)
+      if (c - 64 * q >= 0) w[q] = ldg16((uint64_t)(uintptr_t)(e - 16 * (c - 64 * q + 1)));
+#pragma unroll
+    for (int q = 0; q < CRC_Q; q++)
+      if (c - 64 * q >= 0) acc = crc_shift(T->b.sh[6], acc) ^ crc_chunk11(T, w[q]);
+  }
+  return acc;
 }
 
 __global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok,
                                                   unsigned long long* err, unsigned long long* bytes_total) {
-  __shared__ CrcLds T;
+  __shared__ CrcLds11 T;
   load_crc_tables(&T, g_crc, threadIdx.x, blockDim.x);
   __syncthreads();
   const uint64_t nb = *ws.n_dev;
+  if (nb == 0) return;
   const uint32_t waves = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
   const uint64_t stride = (uint64_t)gridDim.x * waves;
-  const uint32_t l = lane_id();
+  const uint64_t safe = (uint64_t)(uintptr_t)g_crc;
   uint64_t bytes = 0;
   uint64_t b = (uint64_t)blockIdx.x * waves + wv;
-  CrcBlk k = crc_blk(ws, b, nb);
+  CrcBlk k = crc_blk(ws, b, nb), kn = crc_blk(ws, b + stride, nb);
+  uint4 v[CRC_Q];
+  crc_load_first(k, safe, v);
   for (; b < nb; b += stride) {
-    const CrcBlk kn = crc_blk(ws, b + stride, nb);
-    if (k.skip) {
-      if (l == 0) ok[b] = 0;
-    } else {
-      uint32_t stored = 0, type = 0;
-      if (l == 0) {
-        stored = ldg_u32_unaligned(k.p + k.n);
-        type = k.p[k.n - 1];
-      }
-      const uint32_t raw = wave_raw_crc(&T, k.p, 0, k.n);
-      if (l == 0) check_crc(ws, in, (uint32_t)b, raw, stored, type, ok, err);
+    const CrcBlk knn = crc_blk(ws, b + 2 * stride, nb);
+    const uint64_t ta = k.n ? (uint64_t)(uintptr_t)(k.p + k.n - 1) : safe;  // type byte, then the stored CRC
+    const uint32_t type = ldg_u8(ta);
+    const uint32_t stored = ldg_u8(ta + 1) | (ldg_u8(ta + 2) << 8) | (ldg_u8(ta + 3) << 16) | (ldg_u8(ta + 4) << 24);
+    uint4 vn[CRC_Q];
+    crc_load_first(kn, safe, vn);
+    uint8_t good = 0;
+    if (!k.skip) {
+      const uint32_t raw = crc_wave_join(&T.b, crc_fold(&T, k, v));
+      good = check_crc(ws, in, (uint32_t)b, raw, stored, type, err);
       bytes += k.n + 4;
     }
+    ok[b] = good;
+#pragma unroll
+    for (int q = 0; q < CRC_Q; q++) v[q] = vn[q];
     k = kn;
+    kn = knn;
   }
-  if (l == 0 && bytes) atomicAdd(bytes_total, (unsigned long long)bytes);
+  if (lane_id() == 0 && bytes) atomicAdd(bytes_total, (unsigned long long)bytes);
 }
 
 // one workgroup of 16 waves per block: wave w folds segment w (segments of

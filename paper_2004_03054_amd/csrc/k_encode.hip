@@ -7,10 +7,11 @@
 //   k_encode       one wave per output data block: assembles the block in an
 //                  LDS stage (value interiors as aligned 16-byte copies,
 //                  headers, keys, value edges and the tail as bytes), then
-//                  stores it in 64-byte units aligned to the block end and
-//                  folds each unit into the block's CRC in registers
+//                  stores it in 16-byte chunks aligned to the block end and
+//                  folds each chunk into the block's CRC in registers
 //   k_encode_gen   the same bytes for blocks too large for the stage: every
-//                  chunk is generated in registers from the entry records
+//                  64-byte unit is generated in registers from the entry
+//                  records
 //   k_key_hash     one thread per surviving key: its XXH64
 //   k_filter_small one thread per small filter window: bits in a private LDS
 //                  slot
@@ -161,7 +162,8 @@ __device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t nw, uint32_t i, int64_
 // starts 8 entries before the previous one ended, so a chunk assigned to a
 // window (by its first byte) never reaches past the window's entries (an
 // entry is at least 4 bytes).
-constexpr uint32_t ENC_B = 2;  // whole value chunks per lane in flight with the byte tasks
+constexpr uint32_t ENC_B = 4;  // whole value chunks per lane in flight together
+constexpr uint32_t ENC_T = 4;  // byte tasks per lane in flight together
 
 constexpr uint32_t ENC_OVERLAP = 16;  // entries shared by consecutive windows (>= 64 bytes)
 constexpr uint32_t GEN_UNIT = 64;     // bytes a lane folds per step in k_encode_gen
@@ -381,6 +383,13 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
         W->hn[l] = h_end - vs;
         W->tb[l] = t_beg;
         tasks = hl + ns + (h_end - vs) + (en - t_beg);
+        if (i % R == 0) {  // restart slot of this entry
+          uint8_t* d = base + data_end + 4 * (i / R);
+          d[0] = (uint8_t)st;
+          d[1] = (uint8_t)(st >> 8);
+          d[2] = (uint8_t)(st >> 16);
+          d[3] = (uint8_t)(st >> 24);
+        }
       }
       const uint32_t ti = wave_incl_scan(tasks), pi = wave_incl_scan(pieces);
       if (l < nw) {
@@ -409,36 +418,48 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
         const uint32_t pos = W->a[lo] + 16 * (k - W->pc[lo]);
         v[t] = ldg16(W->vp[lo] + (pos - W->vs[lo]));
       }
-      for (uint32_t k = l; k < ntasks; k += WAVE) {
-        uint32_t lo = 0, hi = nw;  // pb[lo] <= k < pb[hi]
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (W->pb[mid] <= k) lo = mid;
-          else hi = mid;
-        }
-        uint32_t o = k - W->pb[lo];
-        const uint32_t hl = W->hl[lo], ns = W->ns[lo];
-        uint32_t byte, d;
-        if (o < hl) {
-          byte = (uint32_t)((o < 8 ? W->h0[lo] >> (8 * o) : W->h1[lo] >> (8 * (o - 8))) & 0xFFu);
-          d = W->st[lo] + o;
-        } else if (o < hl + ns) {
-          const uint32_t q = W->sh[lo] + (o - hl), ul = W->ul[lo];
-          if (q < ul) {
-            const uint64_t word = A.tu.heap[(uint64_t)W->e[lo] * A.kw8 + (q >> 3)];
-            byte = (uint32_t)(word >> (8 * (q & 7))) & 0xFFu;
-          } else {
-            byte = (uint32_t)(W->tag[lo] >> (8 * (q - ul))) & 0xFFu;
+      // byte tasks, ENC_T per lane at a time: the sources of a batch are
+      // worked out first so that its global loads are in flight together
+      for (uint32_t kb = 0; kb < ntasks; kb += WAVE * ENC_T) {
+        uint32_t byte[ENC_T], d[ENC_T];
+        uint64_t src[ENC_T];
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_T; t++) {
+          const uint32_t k = kb + l + WAVE * t;
+          src[t] = 0;
+          byte[t] = 0;
+          d[t] = ~0u;
+          if (k >= ntasks) continue;
+          uint32_t lo = 0, hi = nw;  // pb[lo] <= k < pb[hi]
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (W->pb[mid] <= k) lo = mid;
+            else hi = mid;
           }
-          d = W->st[lo] + o;
-        } else {
-          o -= hl + ns;
-          const uint32_t hn = W->hn[lo], vs = W->vs[lo];
-          const uint32_t off = (o < hn) ? o : (W->tb[lo] - vs) + (o - hn);
-          byte = ((const uint8_t*)W->vp[lo])[off];
-          d = vs + off;
+          uint32_t o = k - W->pb[lo];
+          const uint32_t hl = W->hl[lo], ns = W->ns[lo];
+          if (o < hl) {
+            byte[t] = (uint32_t)((o < 8 ? W->h0[lo] >> (8 * o) : W->h1[lo] >> (8 * (o - 8))) & 0xFFu);
+            d[t] = W->st[lo] + o;
+          } else if (o < hl + ns) {
+            const uint32_t q = W->sh[lo] + (o - hl), ul = W->ul[lo];
+            if (q < ul) src[t] = (uint64_t)(uintptr_t)A.tu.heap + (uint64_t)W->e[lo] * A.kw8 * 8 + q;
+            else byte[t] = (uint32_t)(W->tag[lo] >> (8 * (q - ul))) & 0xFFu;
+            d[t] = W->st[lo] + o;
+          } else {
+            o -= hl + ns;
+            const uint32_t hn = W->hn[lo], vs = W->vs[lo];
+            const uint32_t off = (o < hn) ? o : (W->tb[lo] - vs) + (o - hn);
+            src[t] = W->vp[lo] + off;
+            d[t] = vs + off;
+          }
         }
-        base[d] = (uint8_t)byte;
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_T; t++)
+          if (src[t]) byte[t] = ldg_u8(src[t]);
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_T; t++)
+          if (d[t] != ~0u) base[d[t]] = (uint8_t)byte[t];
       }
 #pragma unroll
       for (uint32_t t = 0; t < ENC_B; t++) {
@@ -452,28 +473,30 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
         }
         *(uint4*)(base + W->a[lo] + 16 * (k - W->pc[lo])) = v[t];
       }
-      // remaining whole chunks of long values
-      for (uint32_t k = l + WAVE * ENC_B; k < npieces; k += WAVE) {
-        uint32_t lo = 0, hi = nw;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (W->pc[mid] <= k) lo = mid;
-          else hi = mid;
+      // remaining whole chunks of long values, ENC_B per lane at a time
+      for (uint32_t kb = WAVE * ENC_B; kb < npieces; kb += WAVE * ENC_B) {
+        uint32_t pos[ENC_B];
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_B; t++) {
+          const uint32_t k = kb + l + WAVE * t;
+          pos[t] = ~0u;
+          if (k >= npieces) continue;
+          uint32_t lo = 0, hi = nw;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (W->pc[mid] <= k) lo = mid;
+            else hi = mid;
+          }
+          pos[t] = W->a[lo] + 16 * (k - W->pc[lo]);
+          v[t] = ldg16(W->vp[lo] + (pos[t] - W->vs[lo]));
         }
-        const uint32_t pos = W->a[lo] + 16 * (k - W->pc[lo]);
-        *(uint4*)(base + pos) = ldg16(W->vp[lo] + (pos - W->vs[lo]));
+#pragma unroll
+        for (uint32_t t = 0; t < ENC_B; t++)
+          if (pos[t] != ~0u) *(uint4*)(base + pos[t]) = v[t];
       }
       wave_sync();
     }
-    // --- restart array, restart count, type byte
-    for (uint32_t rr = l; rr < nrest; rr += WAVE) {
-      const uint32_t v = blk_off[(uint64_t)rr * R];
-      uint8_t* d = base + data_end + 4 * rr;
-      d[0] = (uint8_t)v;
-      d[1] = (uint8_t)(v >> 8);
-      d[2] = (uint8_t)(v >> 16);
-      d[3] = (uint8_t)(v >> 24);
-    }
+    // --- restart count, type byte
     if (l == 0) {
       uint8_t* d = base + size - 4;
       d[0] = (uint8_t)nrest;
@@ -491,11 +514,13 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
         stn = A.ent_off[Bn.s0 + l];
       }
     }
-    // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i
+    // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i,
+    // first to last; only a lane's first chunk can reach below message
+    // position 4
     uint32_t acc = 0;
     const int64_t c_first = 63 - (int64_t)l;
-    for (int64_t c = c_first < (int64_t)J16 ? c_first + 64 * (((int64_t)J16 - 1 - c_first) / 64) : -1; c >= 0;
-         c -= 64) {
+    int64_t c = c_first < (int64_t)J16 ? c_first + 64 * (((int64_t)J16 - 1 - c_first) / 64) : -1;
+    if (c >= 0 && (int64_t)n - 16 * (c + 1) < 4) {
       const int64_t p0 = (int64_t)n - 16 * (c + 1);
       const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
       if (p0 >= 0) {
@@ -505,7 +530,14 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
         for (int k = 0; k < 16; k++)
           if (p0 + k >= 0) dst[p0 + k] = vb[k];
       }
-      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
+      acc = crc_chunk(T, v, p0);
+      c -= 64;
+    }
+    for (; c >= 0; c -= 64) {
+      const uint32_t p0 = n - 16 * (uint32_t)(c + 1);
+      const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
+      __builtin_memcpy(dst + p0, &v, 16);
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, v);
     }
     const uint32_t raw = crc_wave_join(T, acc);
     if (l == 0) {

@@ -39,8 +39,11 @@ uint32_t step_byte(uint32_t r, uint8_t b, const uint32_t* t0) { return t0[(r ^ b
 struct CrcTables {
   uint32_t t4[4][256];
   uint32_t sh[NSH][4][256];
+  uint32_t u0[2048], u1[2048], u2[1024];  // 11-bit fields of a word
 };
-constexpr size_t CRC_LDS_BYTES = sizeof(CrcTables);
+// LDS bytes of the slicing and shift tables (the head of the image), what
+// the encoder stages next to its blocks
+constexpr size_t CRC_LDS_BYTES = sizeof(uint32_t) * 4 * 256 * (1 + NSH);
 
 void byte_table(uint32_t* t0) {
   for (uint32_t b = 0; b < 256; b++) {
@@ -68,6 +71,14 @@ void build_crc_tables(CrcTables* T) {
   for (int k = 0; k < NSH; k++)
     for (int i = 0; i < 4; i++)
       for (uint32_t v = 0; v < 256; v++) T->sh[k][i][v] = shift_zeros(v << (8 * i), 16ull << k, t0);
+  auto word = [&](uint32_t x) {
+    return T->t4[3][x & 0xFF] ^ T->t4[2][(x >> 8) & 0xFF] ^ T->t4[1][(x >> 16) & 0xFF] ^ T->t4[0][x >> 24];
+  };
+  for (uint32_t i = 0; i < 2048; i++) {
+    T->u0[i] = word(i);
+    T->u1[i] = word(i << 11);
+  }
+  for (uint32_t i = 0; i < 1024; i++) T->u2[i] = word(i << 22);
 }
 
 // GF(2) products mod P in the reflected representation, for the self check
@@ -668,6 +679,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     c->counters.emplace_back("encode_staged", staged ? 1.0 : 0.0);
     c->counters.emplace_back("encode_waves_per_group", (double)waves);
     c->counters.emplace_back("encode_groups", (double)grid);
+    c->counters.emplace_back("encode_groups_per_cu", (double)occ);
   }
   mark(c, "encode");
   if (NW) {
@@ -931,6 +943,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       hipLaunchKernelGGL(k_crc_wave, dim3(grid), dim3(cw * 64), 0, st, db, in, c->d_crc, DB.ok, err, d_bytes);
       LAUNCH_CHECK();
       kt.stop();
+      c->counters.emplace_back("crc_groups_per_cu", (double)occ);
+      c->counters.emplace_back("crc_groups", (double)grid);
     }
     Mail m(c);
     const uint64_t* p = m.add(DB.ibase + NB, 1);
@@ -1275,6 +1289,12 @@ int luda_selftest_crc(void) {
   for (int i = 0; i < 4; i++) r = step_byte(r, (uint8_t)(d >> (8 * i)), t0);
   const uint32_t y = c ^ d;
   if (r != (T.t4[3][y & 0xFF] ^ T.t4[2][(y >> 8) & 0xFF] ^ T.t4[1][(y >> 16) & 0xFF] ^ T.t4[0][y >> 24])) return 2;
+  // 11-bit field tables against bytewise on a few words
+  for (uint32_t w : {0xDEADBEEFu, 0x01020304u, 0xFFFFFFFFu, 0x80000001u, 0x7FF003FFu}) {
+    uint32_t q = 0;
+    for (int i = 0; i < 4; i++) q = step_byte(q, (uint8_t)(w >> (8 * i)), t0);
+    if (q != (T.u0[w & 0x7FF] ^ T.u1[(w >> 11) & 0x7FF] ^ T.u2[w >> 22])) return 6;
+  }
   // shift tables and GF(2) multipliers against zero-byte processing
   uint32_t x = 0x12345678u;
   for (int k = 0; k < NSH; k++) {
