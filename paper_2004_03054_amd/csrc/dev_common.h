@@ -42,10 +42,12 @@ __device__ inline void report_err(unsigned long long* slot, uint64_t key) {
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
+// orders the LDS accesses of one wave's lanes (a wave's LDS operations are
+// performed in issue order, so only the compiler must not move them across)
 __device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ inline uint32_t rd_u32_bytes(const uint8_t* p) {
@@ -66,6 +68,7 @@ __device__ inline uint64_t ldg_u64_unaligned(const uint8_t* p) {
 
 __device__ inline uint64_t bswap64(uint64_t x) { return __builtin_bswap64(x); }
 // 16 bytes at a global address of any alignment (one global_load_dwordx4)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // buffer load/store operand
 typedef uint4 __attribute__((aligned(1))) uint4_u1;
 typedef const __attribute__((address_space(1))) uint4_u1 g_uint4_u1;
 typedef const __attribute__((address_space(1))) uint4 g_uint4;

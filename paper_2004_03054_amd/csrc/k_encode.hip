@@ -297,254 +297,385 @@ __global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Staged encoder.  Per wave: [EncWin entry window | stage].  The
-// block message (contents || type byte) sits at the end of the stage, which
-// is 16-byte aligned, so the chunk grid of the CRC (16-byte chunks aligned to
-// the message end) is the aligned grid of the stage.
+// Staged encoder.  Per wave: [EncWin entry window | stage].  The block
+// message (contents || type byte) sits at the end of the stage, which is
+// 16-byte aligned, so the chunk grid of the CRC (16-byte chunks aligned to the
+// message end) is the aligned grid of the stage.
+//
+// Blocks are software-pipelined: while block X is stored and checksummed
+// from registers, the loads that fill block X+1 (its first window of value
+// chunks and bytes) are in flight, its entry records were loaded one block
+// ahead and its handle two blocks ahead.  Every global load and store of the
+// common path is issued by every lane (a lane with nothing to load reads a
+// fixed valid address; stores go through a buffer descriptor of the block,
+// and a lane with nothing to store uses an offset past its end, which the
+// hardware drops), so each wait is for exactly the loads it needs.
+
+constexpr uint32_t ENC_QS = 5;           // chunks per lane held in registers: blocks up to 5 KiB pipelined
+constexpr uint32_t ENC_OOB = 0x80000000u;  // a buffer offset past any block
+
+struct EncH {  // one block, the same in every lane
+  uint64_t dst, s0;
+  uint32_t cnt, size, R;
+  bool valid;
+};
+
+__device__ __forceinline__ EncH enc_handle(const EncodeArgs& A, uint64_t b, uint64_t nb) {
+  const BlockRec r = A.blk[b < nb ? b : nb - 1];  // nb > 0
+  EncH h;
+  h.dst = r.dst;
+  h.s0 = r.s0;
+  h.cnt = r.cnt;
+  h.size = r.size;
+  h.R = r.R;
+  h.valid = b < nb;
+  return h;
+}
+
+struct EncE {  // this lane's entry of a window
+  EncRec r;
+  uint32_t st;
+};
+
+// entry k0 + l of block H (lanes past the block's end read its last entry)
+__device__ __forceinline__ EncE enc_entry(const EncodeArgs& A, const EncH& H, uint32_t k0) {
+  const uint32_t i = min(k0 + lane_id(), H.cnt - 1);  // cnt >= 1
+  EncE e;
+  e.r = A.rec[H.s0 + i];
+  e.st = A.ent_off[H.s0 + i];
+  return e;
+}
+
+struct EncL {
+  uint32_t nw, ntasks, npieces;
+  uint32_t rs;  // restart slot of this lane's entry: its index + 1, or 0
+  uint32_t st;
+};
+
+// lays out entries k0 .. k0 + nw - 1 (lane l: entry k0 + l) into the window
+__device__ __forceinline__ EncL enc_layout(EncWin* W, const EncH& H, uint32_t k0, const EncE& E, uint32_t gshift) {
+  const uint32_t l = lane_id();
+  EncL L;
+  L.nw = min(H.cnt - k0, ENC_SW);
+  L.rs = 0;
+  L.st = E.st;
+  uint32_t tasks = 0, pieces = 0;
+  if (l < L.nw) {
+    const uint32_t i = k0 + l;
+    const EncRec& r = E.r;
+    const uint32_t st = E.st;
+    const uint32_t shared = (i % H.R == 0) ? 0u : r.shared;
+    const uint32_t ns = r.ulen + 8 - shared;
+    uint32_t la, lb, lc;
+    const uint64_t va = pack_varint(shared, &la), vb = pack_varint(ns, &lb), vc = pack_varint(r.vlen, &lc);
+    const u128 Hd = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
+    const uint32_t hl = la + lb + lc;
+    const uint32_t vs = st + hl + ns, en = vs + r.vlen;
+    // a: first grid position >= vs; z: last grid position <= en (it can lie
+    // before the message start, hence signed)
+    const uint32_t a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
+    const int64_t z = (int64_t)en - (int64_t)((en + gshift) & 15u);
+    uint32_t h_end = en, t_beg = en;
+    if ((int64_t)a + 16 <= z) {
+      pieces = (uint32_t)((z - (int64_t)a) / 16);
+      h_end = a;
+      t_beg = (uint32_t)z;
+    }
+    W->vp[l] = r.vp;
+    W->tag[l] = r.tag;
+    W->h0[l] = (uint64_t)Hd;
+    W->h1[l] = (uint64_t)(Hd >> 64);
+    W->st[l] = st;
+    W->hl[l] = hl;
+    W->ns[l] = ns;
+    W->sh[l] = shared;
+    W->ul[l] = r.ulen;
+    W->e[l] = r.e;
+    W->vs[l] = vs;
+    W->a[l] = a;
+    W->hn[l] = h_end - vs;
+    W->tb[l] = t_beg;
+    tasks = hl + ns + (h_end - vs) + (en - t_beg);
+    if (i % H.R == 0) L.rs = i / H.R + 1;
+  }
+  const uint32_t ti = wave_incl_scan(tasks), pi = wave_incl_scan(pieces);
+  if (l < L.nw) {
+    W->pb[l] = ti - tasks;
+    W->pc[l] = pi - pieces;
+  }
+  L.ntasks = __shfl(ti, WAVE - 1, WAVE);
+  L.npieces = __shfl(pi, WAVE - 1, WAVE);
+  if (l == 0) {
+    W->pb[L.nw] = L.ntasks;
+    W->pc[L.nw] = L.npieces;
+  }
+  wave_sync();
+  return L;
+}
+
+// one batch of a window's stage writes, loaded into registers: whole aligned
+// value chunks kp0 + l + 64 t and byte tasks kt0 + l + 64 t
+struct EncIss {
+  uint4 v[ENC_B];
+  uint32_t pos[ENC_B];  // stage position of the chunk, ~0: none
+  uint32_t bl[ENC_T];   // loaded byte
+  uint32_t bd[ENC_T];   // stage position of the byte | its value << 20 (0x100: the loaded one); ~0: none
+};
+constexpr uint32_t ENC_LOADED = 0x100u << 20;
+
+__device__ __forceinline__ uint32_t win_find(const uint32_t* off, uint32_t nw, uint32_t k) {
+  uint32_t lo = 0, hi = nw;  // off[lo] <= k < off[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= k) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void enc_issue(const EncWin* W, const EncodeArgs& A, const EncL& L, uint32_t kp0,
+                                          uint32_t kt0, uint64_t safe, EncIss& I) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (uint32_t t = 0; t < ENC_B; t++) {
+    const uint32_t k = kp0 + l + WAVE * t;
+    uint64_t src = safe;
+    I.pos[t] = ~0u;
+    if (k < L.npieces) {
+      const uint32_t lo = win_find(W->pc, L.nw, k);
+      I.pos[t] = W->a[lo] + 16 * (k - W->pc[lo]);
+      src = W->vp[lo] + (I.pos[t] - W->vs[lo]);
+    }
+    I.v[t] = ldg16(src);
+  }
+#pragma unroll
+  for (uint32_t t = 0; t < ENC_T; t++) {
+    const uint32_t k = kt0 + l + WAVE * t;
+    uint64_t src = safe;
+    I.bd[t] = ~0u;
+    if (k < L.ntasks) {
+      const uint32_t lo = win_find(W->pb, L.nw, k);
+      uint32_t o = k - W->pb[lo];
+      const uint32_t hl = W->hl[lo], ns = W->ns[lo];
+      if (o < hl) {
+        const uint32_t v = (uint32_t)((o < 8 ? W->h0[lo] >> (8 * o) : W->h1[lo] >> (8 * (o - 8))) & 0xFFu);
+        I.bd[t] = (W->st[lo] + o) | (v << 20);
+      } else if (o < hl + ns) {
+        const uint32_t q = W->sh[lo] + (o - hl), ul = W->ul[lo];
+        uint32_t v = ENC_LOADED;
+        if (q < ul) src = (uint64_t)(uintptr_t)A.tu.heap + (uint64_t)W->e[lo] * A.kw8 * 8 + q;
+        else v = ((uint32_t)(W->tag[lo] >> (8 * (q - ul))) & 0xFFu) << 20;
+        I.bd[t] = (W->st[lo] + o) | v;
+      } else {
+        o -= hl + ns;
+        const uint32_t hn = W->hn[lo], vs = W->vs[lo];
+        const uint32_t off = (o < hn) ? o : (W->tb[lo] - vs) + (o - hn);
+        src = W->vp[lo] + off;
+        I.bd[t] = (vs + off) | ENC_LOADED;
+      }
+    }
+    I.bl[t] = ldg_u8(src);
+  }
+}
+
+__device__ __forceinline__ void enc_put(uint8_t* base, const EncIss& I) {
+#pragma unroll
+  for (uint32_t t = 0; t < ENC_T; t++)
+    if (I.bd[t] != ~0u) base[I.bd[t] & 0xFFFFFu] = (uint8_t)(I.bd[t] >> 20 == 0x100u ? I.bl[t] : I.bd[t] >> 20);
+#pragma unroll
+  for (uint32_t t = 0; t < ENC_B; t++)
+    if (I.pos[t] != ~0u) *(uint4*)(base + I.pos[t]) = I.v[t];
+}
+
+__device__ __forceinline__ void put_u32(uint8_t* d, uint32_t v) {
+  d[0] = (uint8_t)v;
+  d[1] = (uint8_t)(v >> 8);
+  d[2] = (uint8_t)(v >> 16);
+  d[3] = (uint8_t)(v >> 24);
+}
+
+struct EncG {  // the stage geometry of a block
+  uint32_t n, J16, gshift, nrest, data_end;
+  uint8_t* base;  // message byte p at base[p]
+};
+
+__device__ __forceinline__ EncG enc_geom(const EncH& H, uint8_t* stage_end) {
+  EncG g;
+  g.n = H.size + 1;
+  g.J16 = (g.n + 15) / 16;
+  g.gshift = 16 * g.J16 - g.n;
+  g.nrest = (H.cnt + H.R - 1) / H.R;
+  g.data_end = H.size - 4 * g.nrest - 4;
+  g.base = stage_end - g.n;
+  return g;
+}
+
+// writes the rest of block H into the stage once its first batch I (of the
+// first window, laid out as L) has arrived: the first batch, the remaining
+// batches and windows, the restart array, restart count and type byte
+__device__ __forceinline__ void enc_commit(EncWin* W, const EncodeArgs& A, const EncH& H, const EncG& g,
+                                           const EncL& L0, const EncIss& I0, uint64_t safe) {
+  const uint32_t l = lane_id();
+  enc_put(g.base, I0);
+  if (L0.rs) put_u32(g.base + g.data_end + 4 * (L0.rs - 1), L0.st);
+  EncL L = L0;
+  uint32_t kp = WAVE * ENC_B, kt = WAVE * ENC_T;
+  for (uint32_t k0 = 0;;) {
+    while (kp < L.npieces || kt < L.ntasks) {
+      EncIss I;
+      enc_issue(W, A, L, kp, kt, safe, I);
+      enc_put(g.base, I);
+      kp += WAVE * ENC_B;
+      kt += WAVE * ENC_T;
+    }
+    k0 += ENC_SW;
+    if (k0 >= H.cnt) break;
+    wave_sync();
+    const EncE E = enc_entry(A, H, k0);
+    L = enc_layout(W, H, k0, E, g.gshift);
+    if (L.rs) put_u32(g.base + g.data_end + 4 * (L.rs - 1), L.st);
+    kp = 0;
+    kt = 0;
+  }
+  if (l == 0) {
+    put_u32(g.base + H.size - 4, g.nrest);
+    g.base[H.size] = 0;
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ u128 u4_to_u128(uint4 v) {
+  return ((u128)(((uint64_t)v.w << 32) | v.z) << 64) | (((uint64_t)v.y << 32) | v.x);
+}
+__device__ __forceinline__ uint4 u128_to_u4(u128 x) {
+  return make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
+}
+
+// block message in the stage -> output bytes and masked CRC, any size: lane l
+// takes the chunks c = 63 - l + 64 i, first to last; only a lane's first
+// chunk can reach below message position 4
+__device__ __forceinline__ void enc_store_loop(const CrcLds* T, const EncH& H, const EncG& g, uint8_t* stage_end,
+                                               uint8_t* dst) {
+  const uint32_t n = g.n;
+  uint32_t acc = 0;
+  const int64_t c_first = 63 - (int64_t)lane_id();
+  int64_t c = c_first < (int64_t)g.J16 ? c_first + 64 * (((int64_t)g.J16 - 1 - c_first) / 64) : -1;
+  if (c >= 0 && (int64_t)n - 16 * (c + 1) < 4) {
+    const int64_t p0 = (int64_t)n - 16 * (c + 1);
+    const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
+    if (p0 >= 0) {
+      __builtin_memcpy(dst + p0, &v, 16);
+    } else {
+      const uint8_t* vb = (const uint8_t*)&v;
+      for (int k = 0; k < 16; k++)
+        if (p0 + k >= 0) dst[p0 + k] = vb[k];
+    }
+    acc = crc_chunk(T, v, p0);
+    c -= 64;
+  }
+  for (; c >= 0; c -= 64) {
+    const uint32_t p0 = n - 16 * (uint32_t)(c + 1);
+    const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
+    __builtin_memcpy(dst + p0, &v, 16);
+    acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, v);
+  }
+  const uint32_t raw = crc_wave_join(T, acc);
+  if (lane_id() == 0) {
+    const uint32_t m = crc_mask(raw ^ 0xFFFFFFFFu);
+    __builtin_memcpy(dst + n, &m, 4);
+  }
+}
 
 __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   CrcLds* T = (CrcLds*)smem;
   load_crc_tables(T, A.g_crc, threadIdx.x, blockDim.x);
   __syncthreads();
-  const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
+  const uint64_t nb = *A.nblocks;
+  if (nb == 0) return;
+  // the wave index is the same in every lane: block handles are scalar loads
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), l = lane_id();
   const uint32_t waves = blockDim.x / WAVE;
   uint8_t* wbase = smem + sizeof(CrcLds) + (size_t)wv * A.wave_lds;
   EncWin* W = (EncWin*)wbase;
   uint8_t* stage_end = wbase + A.wave_lds;
-  const uint64_t nb = *A.nblocks;
   const uint64_t stride = (uint64_t)gridDim.x * waves;
-  // the next block's record and its first window of entry records are
-  // loaded while the current block is stored and checksummed
+  const uint64_t safe = (uint64_t)(uintptr_t)A.g_crc;
   uint64_t b = (uint64_t)blockIdx.x * waves + wv;
-  BlockRec Bn;
-  EncRec rn;
-  uint32_t stn = 0;
-  if (b < nb) {
-    Bn = A.blk[b];
-    if (l < min(Bn.cnt, ENC_SW)) {
-      rn = A.rec[Bn.s0 + l];
-      stn = A.ent_off[Bn.s0 + l];
-    }
+  if (b >= nb) return;
+  // prologue: block b staged, the next block's handle and first records
+  EncH H = enc_handle(A, b, nb), Hn = enc_handle(A, b + stride, nb);
+  {
+    const EncG g = enc_geom(H, stage_end);
+    const EncE E = enc_entry(A, H, 0);
+    const EncL L = enc_layout(W, H, 0, E, g.gshift);
+    EncIss I;
+    enc_issue(W, A, L, 0, 0, safe, I);
+    enc_commit(W, A, H, g, L, I, safe);
   }
+  EncE En = enc_entry(A, Hn, 0);
   for (; b < nb; b += stride) {
-    const BlockRec B = Bn;
-    const EncRec r0 = rn;
-    const uint32_t st0 = stn;
-    const uint32_t R = B.R, cnt = B.cnt, size = B.size;
-    const uint64_t s0 = B.s0;
-    const uint32_t nrest = (cnt + R - 1) / R;
-    const uint32_t data_end = size - 4 * nrest - 4;
-    const uint32_t n = size + 1;
-    uint8_t* dst = A.out + B.dst;
-    const uint32_t* blk_off = A.ent_off + s0;
-    const uint32_t J16 = (n + 15) / 16;
-    uint8_t* base = stage_end - n;         // message byte p at base[p]
-    const uint32_t gshift = 16 * J16 - n;  // chunk grid: positions 16 m - gshift
-    // --- entries, a window at a time: one lane per entry lays out its
-    // entry, then all lanes write the header, key delta and value-edge bytes
-    // (byte tasks) and copy the whole aligned chunks of the values
-    for (uint32_t k0 = 0; k0 < cnt; k0 += ENC_SW) {
-      const uint32_t nw = min(cnt - k0, ENC_SW);
-      uint32_t tasks = 0, pieces = 0;
-      if (l < nw) {
-        const uint32_t i = k0 + l;
-        const EncRec r = k0 ? A.rec[s0 + i] : r0;
-        const uint32_t st = k0 ? blk_off[i] : st0;
-        const uint32_t shared = (i % R == 0) ? 0u : r.shared;
-        const uint32_t ns = r.ulen + 8 - shared;
-        uint32_t la, lb, lc;
-        const uint64_t va = pack_varint(shared, &la), vb = pack_varint(ns, &lb), vc = pack_varint(r.vlen, &lc);
-        const u128 H = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
-        const uint32_t hl = la + lb + lc;
-        const uint32_t vs = st + hl + ns, en = vs + r.vlen;
-        // a: first grid position >= vs; z: last grid position <= en (it can
-        // lie before the message start, hence signed)
-        const uint32_t a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
-        const int64_t z = (int64_t)en - (int64_t)((en + gshift) & 15u);
-        uint32_t h_end = en, t_beg = en;
-        if ((int64_t)a + 16 <= z) {
-          pieces = (uint32_t)((z - (int64_t)a) / 16);
-          h_end = a;
-          t_beg = (uint32_t)z;
-        }
-        W->vp[l] = r.vp;
-        W->tag[l] = r.tag;
-        W->h0[l] = (uint64_t)H;
-        W->h1[l] = (uint64_t)(H >> 64);
-        W->st[l] = st;
-        W->hl[l] = hl;
-        W->ns[l] = ns;
-        W->sh[l] = shared;
-        W->ul[l] = r.ulen;
-        W->e[l] = r.e;
-        W->vs[l] = vs;
-        W->a[l] = a;
-        W->hn[l] = h_end - vs;
-        W->tb[l] = t_beg;
-        tasks = hl + ns + (h_end - vs) + (en - t_beg);
-        if (i % R == 0) {  // restart slot of this entry
-          uint8_t* d = base + data_end + 4 * (i / R);
-          d[0] = (uint8_t)st;
-          d[1] = (uint8_t)(st >> 8);
-          d[2] = (uint8_t)(st >> 16);
-          d[3] = (uint8_t)(st >> 24);
-        }
-      }
-      const uint32_t ti = wave_incl_scan(tasks), pi = wave_incl_scan(pieces);
-      if (l < nw) {
-        W->pb[l] = ti - tasks;
-        W->pc[l] = pi - pieces;
-      }
-      const uint32_t ntasks = __shfl(ti, WAVE - 1, WAVE), npieces = __shfl(pi, WAVE - 1, WAVE);
-      if (l == 0) {
-        W->pb[nw] = ntasks;
-        W->pc[nw] = npieces;
-      }
-      wave_sync();
-      // whole aligned chunks of the values, the first ENC_B per lane in flight
-      // with the byte tasks below
-      uint4 v[ENC_B];
-#pragma unroll
-      for (uint32_t t = 0; t < ENC_B; t++) {
-        const uint32_t k = l + WAVE * t;
-        if (k >= npieces) continue;
-        uint32_t lo = 0, hi = nw;  // pc[lo] <= k < pc[hi]
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (W->pc[mid] <= k) lo = mid;
-          else hi = mid;
-        }
-        const uint32_t pos = W->a[lo] + 16 * (k - W->pc[lo]);
-        v[t] = ldg16(W->vp[lo] + (pos - W->vs[lo]));
-      }
-      // byte tasks, ENC_T per lane at a time: the sources of a batch are
-      // worked out first so that its global loads are in flight together
-      for (uint32_t kb = 0; kb < ntasks; kb += WAVE * ENC_T) {
-        uint32_t byte[ENC_T], d[ENC_T];
-        uint64_t src[ENC_T];
-#pragma unroll
-        for (uint32_t t = 0; t < ENC_T; t++) {
-          const uint32_t k = kb + l + WAVE * t;
-          src[t] = 0;
-          byte[t] = 0;
-          d[t] = ~0u;
-          if (k >= ntasks) continue;
-          uint32_t lo = 0, hi = nw;  // pb[lo] <= k < pb[hi]
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (W->pb[mid] <= k) lo = mid;
-            else hi = mid;
-          }
-          uint32_t o = k - W->pb[lo];
-          const uint32_t hl = W->hl[lo], ns = W->ns[lo];
-          if (o < hl) {
-            byte[t] = (uint32_t)((o < 8 ? W->h0[lo] >> (8 * o) : W->h1[lo] >> (8 * (o - 8))) & 0xFFu);
-            d[t] = W->st[lo] + o;
-          } else if (o < hl + ns) {
-            const uint32_t q = W->sh[lo] + (o - hl), ul = W->ul[lo];
-            if (q < ul) src[t] = (uint64_t)(uintptr_t)A.tu.heap + (uint64_t)W->e[lo] * A.kw8 * 8 + q;
-            else byte[t] = (uint32_t)(W->tag[lo] >> (8 * (q - ul))) & 0xFFu;
-            d[t] = W->st[lo] + o;
-          } else {
-            o -= hl + ns;
-            const uint32_t hn = W->hn[lo], vs = W->vs[lo];
-            const uint32_t off = (o < hn) ? o : (W->tb[lo] - vs) + (o - hn);
-            src[t] = W->vp[lo] + off;
-            d[t] = vs + off;
-          }
-        }
-#pragma unroll
-        for (uint32_t t = 0; t < ENC_T; t++)
-          if (src[t]) byte[t] = ldg_u8(src[t]);
-#pragma unroll
-        for (uint32_t t = 0; t < ENC_T; t++)
-          if (d[t] != ~0u) base[d[t]] = (uint8_t)byte[t];
-      }
-#pragma unroll
-      for (uint32_t t = 0; t < ENC_B; t++) {
-        const uint32_t k = l + WAVE * t;
-        if (k >= npieces) continue;
-        uint32_t lo = 0, hi = nw;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (W->pc[mid] <= k) lo = mid;
-          else hi = mid;
-        }
-        *(uint4*)(base + W->a[lo] + 16 * (k - W->pc[lo])) = v[t];
-      }
-      // remaining whole chunks of long values, ENC_B per lane at a time
-      for (uint32_t kb = WAVE * ENC_B; kb < npieces; kb += WAVE * ENC_B) {
-        uint32_t pos[ENC_B];
-#pragma unroll
-        for (uint32_t t = 0; t < ENC_B; t++) {
-          const uint32_t k = kb + l + WAVE * t;
-          pos[t] = ~0u;
-          if (k >= npieces) continue;
-          uint32_t lo = 0, hi = nw;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (W->pc[mid] <= k) lo = mid;
-            else hi = mid;
-          }
-          pos[t] = W->a[lo] + 16 * (k - W->pc[lo]);
-          v[t] = ldg16(W->vp[lo] + (pos[t] - W->vs[lo]));
-        }
-#pragma unroll
-        for (uint32_t t = 0; t < ENC_B; t++)
-          if (pos[t] != ~0u) *(uint4*)(base + pos[t]) = v[t];
-      }
-      wave_sync();
+    const EncH Hnn = enc_handle(A, b + 2 * stride, nb);
+    const EncG g = enc_geom(H, stage_end);
+    uint8_t* dst = A.out + H.dst;
+    const bool piped = g.J16 <= 64 * ENC_QS && g.n >= 16;
+    // the next block: first window laid out, its first batch in flight
+    // (the window is free: this block is wholly in the stage)
+    const EncG gn = enc_geom(Hn, stage_end);
+    EncL Ln;
+    EncIss In;
+    if (Hn.valid) {
+      Ln = enc_layout(W, Hn, 0, En, gn.gshift);
+      enc_issue(W, A, Ln, 0, 0, safe, In);
     }
-    // --- restart count, type byte
-    if (l == 0) {
-      uint8_t* d = base + size - 4;
-      d[0] = (uint8_t)nrest;
-      d[1] = (uint8_t)(nrest >> 8);
-      d[2] = (uint8_t)(nrest >> 16);
-      d[3] = (uint8_t)(nrest >> 24);
-      d[4] = 0;
+    if (piped) {
+      // this block's chunks into registers, then stored and checksummed;
+      // every lane issues ENC_QS chunk stores.  A first chunk that starts
+      // before the message is stored as message bytes [0, 16) (the bytes past
+      // it are the next chunk's)
+      const int64_t c_first = 63 - (int64_t)l;
+      const int64_t ct = c_first < (int64_t)g.J16 ? c_first + 64 * (((int64_t)g.J16 - 1 - c_first) / 64) : -1;
+      const int64_t pt = (int64_t)g.n - 16 * (ct + 1);
+      uint4 s[ENC_QS];
+#pragma unroll
+      for (uint32_t q = 0; q < ENC_QS; q++) {
+        const int64_t c = ct - 64 * (int64_t)q;
+        s[q] = c >= 0 ? *(const uint4*)(stage_end - 16 * (c + 1)) : make_uint4(0, 0, 0, 0);
+      }
+      if (ct >= 1 && pt < 0) {
+        const uint4 nx = *(const uint4*)(stage_end - 16 * ct);  // chunk ct - 1
+        const uint32_t sh = (uint32_t)(-pt);
+        s[0] = u128_to_u4((u4_to_u128(s[0]) >> (8 * sh)) | (u4_to_u128(nx) << (8 * (16 - sh))));
+      }
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)(g.n + 4), 0x00020000);
+      uint32_t acc = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < ENC_QS; q++) {
+        const int64_t c = ct - 64 * (int64_t)q;
+        const int64_t p0 = (int64_t)g.n - 16 * (c + 1);
+        const u32x4 dv = {s[q].x, s[q].y, s[q].z, s[q].w};
+        __builtin_amdgcn_raw_buffer_store_b128(dv, rs, c >= 0 ? (uint32_t)(p0 > 0 ? p0 : 0) : ENC_OOB, 0, 0);
+        if (c >= 0) {
+          if (q == 0)
+            acc = p0 < 4 ? crc_chunk(T, p0 < 0 ? u128_to_u4(u4_to_u128(s[0]) << (8 * (uint32_t)-p0)) : s[0], p0)
+                         : crc_chunk_plain(T, s[0]);
+          else
+            acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, s[q]);
+        }
+      }
+      const uint32_t raw = crc_wave_join(T, acc);
+      __builtin_amdgcn_raw_buffer_store_b32(crc_mask(raw ^ 0xFFFFFFFFu), rs, l == 0 ? g.n : ENC_OOB, 0, 0);
+    } else {
+      enc_store_loop(T, H, g, stage_end, dst);
     }
     wave_sync();
-    // next block's records (in flight during the store and checksum)
-    if (b + stride < nb) {
-      Bn = A.blk[b + stride];
-      if (l < min(Bn.cnt, ENC_SW)) {
-        rn = A.rec[Bn.s0 + l];
-        stn = A.ent_off[Bn.s0 + l];
-      }
-    }
-    // --- store and checksum: lane l takes the chunks c = 63 - l + 64 i,
-    // first to last; only a lane's first chunk can reach below message
-    // position 4
-    uint32_t acc = 0;
-    const int64_t c_first = 63 - (int64_t)l;
-    int64_t c = c_first < (int64_t)J16 ? c_first + 64 * (((int64_t)J16 - 1 - c_first) / 64) : -1;
-    if (c >= 0 && (int64_t)n - 16 * (c + 1) < 4) {
-      const int64_t p0 = (int64_t)n - 16 * (c + 1);
-      const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
-      if (p0 >= 0) {
-        __builtin_memcpy(dst + p0, &v, 16);
-      } else {
-        const uint8_t* vb = (const uint8_t*)&v;
-        for (int k = 0; k < 16; k++)
-          if (p0 + k >= 0) dst[p0 + k] = vb[k];
-      }
-      acc = crc_chunk(T, v, p0);
-      c -= 64;
-    }
-    for (; c >= 0; c -= 64) {
-      const uint32_t p0 = n - 16 * (uint32_t)(c + 1);
-      const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
-      __builtin_memcpy(dst + p0, &v, 16);
-      acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, v);
-    }
-    const uint32_t raw = crc_wave_join(T, acc);
-    if (l == 0) {
-      const uint32_t m = crc_mask(raw ^ 0xFFFFFFFFu);
-      __builtin_memcpy(dst + n, &m, 4);
-    }
-    wave_sync();
+    // records of the block after next, then the next block completed in the
+    // stage once its first batch has arrived
+    const EncE Enn = enc_entry(A, Hnn, 0);
+    if (Hn.valid) enc_commit(W, A, Hn, gn, Ln, In, safe);
+    H = Hn;
+    Hn = Hnn;
+    En = Enn;
   }
 }
 
