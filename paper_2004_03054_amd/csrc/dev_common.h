@@ -386,26 +386,6 @@ __device__ __host__ inline uint32_t gf2_xpow8n(uint64_t n) {
   return result;
 }
 
-// Raw CRC of a whole message of n bytes by one workgroup of 16 waves: wave w
-// folds segment w (segments of L bytes, L a multiple of 16, aligned to the
-// message end; leading segments may start before the message and contribute
-// only their bytes inside it), and the segments are joined by multiplication
-// with x^(8 L) mod P.  Every thread must call; the result is valid in thread 0.
-__device__ __forceinline__ uint32_t wg16_raw_crc(const CrcLds* T, const uint8_t* msg, uint64_t n, uint32_t* part) {
-  const uint64_t L = (((n + 15) / 16) + 15) / 16 * 16;
-  const uint32_t w = threadIdx.x / WAVE;
-  const int64_t s0 = (int64_t)n - (int64_t)(16 - w) * (int64_t)L;
-  const uint32_t raw = (s0 + (int64_t)L > 0) ? wave_raw_crc(T, msg, s0, L) : 0u;
-  if (lane_id() == 0) part[w] = raw;
-  __syncthreads();
-  uint32_t acc = 0;
-  if (threadIdx.x == 0) {
-    const uint32_t K = gf2_xpow8n(L);
-    for (int q = 0; q < 16; q++) acc = gf2_mulmod(acc, K) ^ part[q];
-  }
-  return acc;
-}
-
 // cooperative load of the global CRC tables (the head of the image) into LDS
 template <typename L = CrcLds>
 __device__ __forceinline__ void load_crc_tables(L* dst, const uint32_t* src, int tid, int nthreads) {

@@ -8,7 +8,8 @@
 //   k_footer     one thread per input: footer magic, index handle
 //   k_blk_nr     one thread per block: restart count
 //   k_crc_wave   one wave per block: masked CRC32C and block type
-//   k_crc_big    one workgroup per (long) block: 16 waves on 16 segments
+//   k_crc_multi  index blocks: 16 KiB segments over the grid, joined by the
+//                last workgroup of each block
 //   k_imap       one thread per restart interval: its block (binary search)
 //   k_walk       one thread per restart interval: walks the interval's
 //                entries (count pass, then emit pass after a prefix sum)
@@ -18,6 +19,7 @@
 //                inside a table; records how adjacent tables compare
 #include "dev_common.h"
 #include "kernels.h"
+#include "crc_multi.h"
 
 namespace luda {
 
@@ -230,25 +232,27 @@ __global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const 
   if (lane_id() == 0 && bytes) atomicAdd(bytes_total, (unsigned long long)bytes);
 }
 
-// one workgroup of 16 waves per block: wave w folds segment w (segments of
-// equal length, aligned to the message end), then the segments are joined
-// by multiplication with x^(8 len) mod P
-__global__ void __launch_bounds__(1024) k_crc_big(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok,
-                                                  unsigned long long* err) {
-  __shared__ CrcLds T;
-  __shared__ uint32_t part[16];
-  const uint64_t nb = *ws.n_dev;
-  const uint32_t b = blockIdx.x;
-  if (b >= nb) return;
-  if (ws.skip[b]) {
-    if (threadIdx.x == 0) ok[b] = 0;
-    return;
+// index blocks of the inputs, checked against their trailers
+struct IndexMsgs {
+  WalkSet ws;
+  Inputs in;
+  uint8_t* ok;
+  unsigned long long* err;
+  __device__ uint32_t count() const { return (uint32_t)*ws.n_dev; }
+  __device__ void span(uint32_t m, const uint8_t** p, uint64_t* n) const {
+    *p = (const uint8_t*)ws.ptr[m];
+    *n = ws.skip[m] ? 0 : (uint64_t)ws.size[m] + 1;
   }
-  load_crc_tables(&T, g_crc, threadIdx.x, blockDim.x);
-  __syncthreads();
-  const uint8_t* c = (const uint8_t*)ws.ptr[b];
-  const uint32_t raw = wg16_raw_crc(&T, c, (uint64_t)ws.size[b] + 1, part);
-  if (threadIdx.x == 0) finish_crc(ws, in, b, raw, ok, err);
+  __device__ void finish(uint32_t m, uint32_t raw) const { finish_crc(ws, in, m, raw, ok, err); }
+  __device__ void empty(uint32_t m) const { ok[m] = 0; }
+};
+
+template __global__ void k_crc_multi<IndexMsgs>(IndexMsgs, const uint32_t*, uint32_t*, uint32_t*);
+
+void launch_crc_index(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
+                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_crc_multi<IndexMsgs>, dim3(grid), dim3(1024), 0, st, IndexMsgs{ws, in, ok, err}, g_crc, part,
+                     ticket);
 }
 
 // interval -> block map: the block of interval i is the last b with

@@ -19,10 +19,11 @@
 //   k_index_write  one thread per data block: its index entry and restart slot
 //   k_meta         one thread per file: filter tail, metaindex, trailers' type
 //                  bytes, footer
-//   k_crc_ranges   one workgroup of 16 waves per (file, filter | metaindex |
-//                  index block)
+//   k_crc_multi    checksums of each file's filter, metaindex and index
+//                  blocks, segments of them spread over the grid
 #include "dev_common.h"
 #include "kernels.h"
+#include "crc_multi.h"
 
 namespace luda {
 
@@ -870,32 +871,36 @@ __global__ void k_meta(OutFiles of, const uint64_t* win_off, const uint64_t* nfi
   for (int k = 0; k < 8; k++) ft[40 + k] = (uint8_t)(TABLE_MAGIC >> (8 * k));
 }
 
-// CRC of filter (kind 0), metaindex (1) and index (2) blocks of each file:
-// one workgroup of 16 waves per block
-__global__ void __launch_bounds__(1024) k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out,
-                                                     const uint32_t* g_crc) {
-  __shared__ CrcLds T;
-  __shared__ uint32_t part[16];
-  const uint64_t f = blockIdx.x / 3;
-  const uint32_t kind = blockIdx.x % 3;
-  if (f >= cap || f >= *nfiles) return;
-  load_crc_tables(&T, g_crc, threadIdx.x, blockDim.x);
-  __syncthreads();
-  uint64_t off, size;
-  if (kind == 0) {
-    off = of.filter_off[f];
-    size = of.filter_size[f];
-  } else if (kind == 1) {
-    off = of.meta_off[f];
-    size = of.meta_size[f];
-  } else {
-    off = of.index_off[f];
-    size = of.index_size[f];
+// filter (kind 0), metaindex (1) and index (2) block of each file: the
+// masked CRC goes into the block's trailer
+struct FileMsgs {
+  OutFiles of;
+  const uint64_t* nfiles;
+  uint64_t cap;
+  uint8_t* out;
+  __device__ uint32_t count() const { return 3 * (uint32_t)min(cap, *nfiles); }
+  __device__ uint8_t* msg(uint32_t m, uint64_t* n) const {
+    const uint32_t f = m / 3, kind = m % 3;
+    const uint64_t off = kind == 0 ? of.filter_off[f] : kind == 1 ? of.meta_off[f] : of.index_off[f];
+    const uint64_t size = kind == 0 ? of.filter_size[f] : kind == 1 ? of.meta_size[f] : of.index_size[f];
+    *n = size + 1;
+    return out + of.out[f] + off;
   }
-  uint8_t* msg = out + of.out[f] + off;
-  const uint64_t n = size + 1;
-  const uint32_t raw = wg16_raw_crc(&T, msg, n, part);
-  if (threadIdx.x == 0) put_fixed32(msg + n, crc_mask(raw ^ 0xFFFFFFFFu));
+  __device__ void span(uint32_t m, const uint8_t** p, uint64_t* n) const { *p = msg(m, n); }
+  __device__ void finish(uint32_t m, uint32_t raw) const {
+    uint64_t n;
+    uint8_t* p = msg(m, &n);
+    put_fixed32(p + n, crc_mask(raw ^ 0xFFFFFFFFu));
+  }
+  __device__ void empty(uint32_t) const {}
+};
+
+template __global__ void k_crc_multi<FileMsgs>(FileMsgs, const uint32_t*, uint32_t*, uint32_t*);
+
+void launch_crc_files(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
+                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_crc_multi<FileMsgs>, dim3(grid), dim3(1024), 0, st, FileMsgs{of, nfiles, cap, out}, g_crc,
+                     part, ticket);
 }
 
 }  // namespace luda

@@ -73,7 +73,9 @@ __global__ void k_footer(Inputs in, WalkSet idx, unsigned long long* err);
 __global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long long* err);
 __global__ void k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
                            unsigned long long* bytes_total);
-__global__ void k_crc_big(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err);
+// checksums of the inputs' index blocks against their trailers
+void launch_crc_index(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
+                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
 __global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev, uint32_t* iblk);
 template <int KIND, int MODE>
 __global__ void k_walk(WalkArgs A);
@@ -260,6 +262,9 @@ __global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen)
 __global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,
                          const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv);
 __global__ void k_check_sorted(Tuples tu, uint32_t kw8, uint64_t n, uint32_t* bad);
-__global__ void k_crc_ranges(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc);
+// checksums of every file's filter, metaindex and index blocks (trailers
+// written); part and ticket as for k_crc_multi
+void launch_crc_files(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
+                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
 
 }  // namespace luda

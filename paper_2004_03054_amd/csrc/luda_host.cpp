@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -40,7 +41,9 @@ struct CrcTables {
   uint32_t t4[4][256];
   uint32_t sh[NSH][4][256];
   uint32_t u0[2048], u1[2048], u2[1024];  // 11-bit fields of a word
+  uint32_t segk[8];                        // x^(8 CRC_SEG_BYTES 2^k) mod P, k = 0..6 (and a pad)
 };
+static_assert(offsetof(CrcTables, segk) == 53248, "the kernels find the segment constants after the 11-bit tables");
 // LDS bytes of the slicing and shift tables (the head of the image), what
 // the encoder stages next to its blocks
 constexpr size_t CRC_LDS_BYTES = sizeof(uint32_t) * 4 * 256 * (1 + NSH);
@@ -62,6 +65,25 @@ uint32_t apply_shift(const uint32_t sh[4][256], uint32_t c) {
   return sh[0][c & 0xFF] ^ sh[1][(c >> 8) & 0xFF] ^ sh[2][(c >> 16) & 0xFF] ^ sh[3][c >> 24];
 }
 
+// GF(2) products mod P in the reflected representation, for the segment join constants and the self check
+uint32_t h_mulmod(uint32_t a, uint32_t b) {
+  uint32_t p = 0;
+  for (int i = 0; i < 32; i++) {
+    if (a & (0x80000000u >> i)) p ^= b;
+    b = (b & 1u) ? (b >> 1) ^ POLY : (b >> 1);
+  }
+  return p;
+}
+uint32_t h_xpow8n(uint64_t n) {
+  uint32_t result = 0x80000000u, sq = 0x00800000u;
+  while (n) {
+    if (n & 1) result = h_mulmod(result, sq);
+    sq = h_mulmod(sq, sq);
+    n >>= 1;
+  }
+  return result;
+}
+
 void build_crc_tables(CrcTables* T) {
   uint32_t t0[256];
   byte_table(t0);
@@ -79,25 +101,7 @@ void build_crc_tables(CrcTables* T) {
     T->u1[i] = word(i << 11);
   }
   for (uint32_t i = 0; i < 1024; i++) T->u2[i] = word(i << 22);
-}
-
-// GF(2) products mod P in the reflected representation, for the self check
-uint32_t h_mulmod(uint32_t a, uint32_t b) {
-  uint32_t p = 0;
-  for (int i = 0; i < 32; i++) {
-    if (a & (0x80000000u >> i)) p ^= b;
-    b = (b & 1u) ? (b >> 1) ^ POLY : (b >> 1);
-  }
-  return p;
-}
-uint32_t h_xpow8n(uint64_t n) {
-  uint32_t result = 0x80000000u, sq = 0x00800000u;
-  while (n) {
-    if (n & 1) result = h_mulmod(result, sq);
-    sq = h_mulmod(sq, sq);
-    n >>= 1;
-  }
-  return result;
+  for (int k = 0; k < 8; k++) T->segk[k] = k < 7 ? h_xpow8n((uint64_t)CRC_SEG_BYTES << k) : 0;
 }
 
 struct DBuf {
@@ -171,6 +175,22 @@ T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
     b.cap = want;
   }
   return (T*)b.p;
+}
+
+// counters that the kernels leave at zero: zero-filled when (re)allocated
+void fill_u32(luda_ctx* c, void* p, uint32_t v, uint64_t n);
+uint32_t* ticket_buf(luda_ctx* c, const std::string& name, uint64_t n) {
+  const DBuf before = c->bufs[name];
+  uint32_t* p = dbuf<uint32_t>(c, name, n);
+  const DBuf& now = c->bufs[name];
+  if (now.p != before.p || now.cap != before.cap) fill_u32(c, p, 0, now.cap / 4);
+  return p;
+}
+
+// grid of the multi-workgroup checksum over messages of at most `bytes`
+// bytes in total (segments of CRC_SEG_BYTES, one per message at least)
+uint32_t crc_multi_grid(const luda_ctx* c, uint64_t bytes, uint64_t msgs) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bytes / CRC_SEG_BYTES + msgs, 2ull * c->n_cu));
 }
 
 inline uint32_t blocks_for(uint64_t n, uint32_t t = 256) {
@@ -729,7 +749,10 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   {
     KTimer kt(c, "k_crc_tables");
-    hipLaunchKernelGGL(k_crc_ranges, dim3((uint32_t)(3 * NF)), dim3(1024), 0, st, of, job_f0 + J, NF, out, c->d_crc);
+    const uint64_t segs = O.total_bytes / CRC_SEG_BYTES + 3 * NF + 1;
+    uint32_t* part = dbuf<uint32_t>(c, "of_crc_part", segs);
+    uint32_t* ticket = ticket_buf(c, "of_crc_ticket", 3 * NF);
+    launch_crc_files(of, job_f0 + J, NF, out, c->d_crc, part, ticket, crc_multi_grid(c, O.total_bytes, 3 * NF), st);
     LAUNCH_CHECK();
     kt.stop();
   }
@@ -855,8 +878,13 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_blk_nr, dim3(blocks_for(NG)), dim3(256), 0, st, ix, in, IX.nr, err);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_crc_big, dim3(NG), dim3(1024), 0, st, ix, in, c->d_crc, IX.ok, err);
-    LAUNCH_CHECK();
+    {
+      const uint64_t segs = total_in / CRC_SEG_BYTES + NG + 1;
+      uint32_t* part = dbuf<uint32_t>(c, "ix_crc_part", segs);
+      uint32_t* ticket = ticket_buf(c, "ix_crc_ticket", NG);
+      launch_crc_index(ix, in, c->d_crc, IX.ok, err, part, ticket, crc_multi_grid(c, total_in, NG), st);
+      LAUNCH_CHECK();
+    }
 
     uint64_t* scan_g = dbuf<uint64_t>(c, "scan_tmp_g", NG / 2048 + 8);
     launch_scan<uint32_t, uint64_t>(IX.nr, NG, nullptr, IX.ibase, scan_g, st);

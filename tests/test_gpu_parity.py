@@ -74,6 +74,20 @@ def test_tiny_variants(vi):
         run_both(tiny_job(100 + seed, **kw), f"variant{vi}-{seed}")
 
 
+def test_long_index_blocks():
+    """Index blocks of about 3 MB (over 64 checksum segments of 16 KiB, so the
+    segment join folds several segments per lane), in the inputs and in the
+    outputs."""
+    job = tiny_job(7, n_inputs=2, entries=150000, key_alphabet=20, key_len=(6, 10), val_len=(0, 6), block_size=40,
+                   restart_interval=4, target_file_size=4 << 20, mode="leveled", max_versions=2)
+    run_both(job, "long-index")
+    ins = oracle.build_input_tables(job)
+    bad = bytearray(ins[1])
+    bad[len(bad) - 48 - 5 - 1000000] ^= 0x01  # a byte inside the second input's index block
+    res, ref = run_both(job, "long-index-corrupt", inputs=[ins[0], bytes(bad)])
+    assert ref.status != 0
+
+
 def test_empty_and_all_dropped():
     res = ctx().compact([], dict(block_size=4096, restart_interval=16, bloom_bits_per_key=10, bottommost=1,
                                  target_file_size=1 << 20))
