@@ -4,14 +4,11 @@
 // table bytes straight into the output block (the paper's lazy value
 // movement, Sec. III-D, without the intermediate pair buffer).
 //
-//   k_encode       one wave per output data block: assembles the block in an
-//                  LDS stage (value interiors as aligned 16-byte copies,
-//                  headers, keys, value edges and the tail as bytes), then
-//                  stores it in 16-byte chunks aligned to the block end and
-//                  folds each chunk into the block's CRC in registers
-//   k_encode_gen   the same bytes for blocks too large for the stage: every
-//                  64-byte unit is generated in registers from the entry
-//                  records
+//   k_gaps         one thread per gap chunk of a block (a 16-byte chunk not
+//                  wholly inside one value): assembles it into the gap buffer
+//   k_encode       one wave per output data block: every 16-byte chunk of
+//                  the block is one load (from a value, or from the gap
+//                  buffer), stored and folded into the block's CRC
 //   k_key_hash     one thread per surviving key: its XXH64
 //   k_filter_small one thread per small filter window: bits in a private LDS
 //                  slot
@@ -103,482 +100,243 @@ __device__ inline Ov overlap(int64_t p0, int64_t a, int64_t b) {
   return r;
 }
 
-// One 16-byte chunk of block message bytes [p0, p0 + 16) (positions < 0 give
-// zeros) assembled from segments: each overlapping entry's header, key delta
-// and value, then restart offsets, the restart count and the type byte (0).
-// i is the window entry holding position max(p0, 0) when that lies in the
-// entry area.
-__device__ uint4 enc_chunk_slow(const EncLds* L, uint32_t nw, uint32_t i, int64_t p0, uint32_t data_end,
-                                uint32_t size, uint32_t nrest, uint32_t R, const uint32_t* blk_off,
-                                const uint64_t* heap, uint32_t kw8) {
+// Message bytes [p0, p0 + 16) of block B (positions outside [0, n) give
+// zeros), assembled from the overlapping parts: each entry's header, key
+// delta and value, then restart offsets, the restart count and the type
+// byte (0).  No entry before i0 reaches p0.
+__device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, int64_t p0, uint32_t i0) {
+  const uint32_t R = B.R, cnt = B.cnt, size = B.size;
+  const uint32_t nrest = (cnt + R - 1) / R;
+  const uint32_t data_end = size - 4 * nrest - 4;
+  const uint32_t* off = A.ent_off + B.s0;
   u128 acc = 0;
-  const int64_t pend = p0 + 16;
-  for (; i < nw; i++) {
-    const int64_t st = L->st[i];
-    if (st >= pend || st >= (int64_t)data_end) break;
-    const int64_t en = L->st[i + 1], vs = L->vs[i];
-    const uint32_t sh = L->sh[i], ul = L->ul[i];
-    const uint32_t ns = ul + 8 - sh;
-    const int64_t ks = vs - ns;
-    const Ov h = overlap(p0, st, ks);
-    if (h.n) {
+  const int64_t pend = p0 + 16, q0 = p0 < 0 ? 0 : p0;
+  if (q0 < (int64_t)data_end) {
+    for (uint32_t i = i0; i < cnt; i++) {
+      const int64_t st = off[i];
+      if (st >= pend) break;
+      const EncRec r = A.rec[B.s0 + i];
+      const uint32_t sh = (i % R == 0) ? 0u : r.shared;
+      const uint32_t ns = r.ulen + 8 - sh;
       uint32_t la, lb, lc;
-      const uint64_t va = pack_varint(sh, &la), vb = pack_varint(ns, &lb), vc = pack_varint((uint32_t)(en - vs), &lc);
-      const u128 H = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
-      acc |= shl_bytes(keep_bytes(shr_bytes(H, h.o), h.n), h.d);
+      const uint64_t va = pack_varint(sh, &la), vb = pack_varint(ns, &lb), vc = pack_varint(r.vlen, &lc);
+      const int64_t ks = st + la + lb + lc, vs = ks + ns, en = vs + r.vlen;
+      const Ov h = overlap(p0, st, ks);
+      if (h.n) {
+        const u128 H = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
+        acc |= shl_bytes(keep_bytes(shr_bytes(H, h.o), h.n), h.d);
+      }
+      const Ov k = overlap(p0, ks, vs);
+      if (k.n) acc |= shl_bytes(ikey_span(A.tu.heap + (uint64_t)r.e * A.kw8, A.kw8, r.ulen, r.tag, sh + k.o, k.n), k.d);
+      const Ov v = overlap(p0, vs, en);
+      if (v.n) acc |= shl_bytes(load_span((const uint8_t*)r.vp + v.o, v.n), v.d);
     }
-    const Ov k = overlap(p0, ks, vs);
-    if (k.n) acc |= shl_bytes(ikey_span(heap + (uint64_t)L->e[i] * kw8, kw8, ul, L->tag[i], sh + k.o, k.n), k.d);
-    const Ov v = overlap(p0, vs, en);
-    if (v.n) acc |= shl_bytes(load_span((const uint8_t*)L->vp[i] + v.o, v.n), v.d);
   }
   if (pend > (int64_t)data_end) {
-    const int64_t rs = data_end;
-    const int64_t from = max(p0, rs);
-    const uint32_t r0 = (uint32_t)((from - rs) >> 2);
-    for (uint32_t r = r0; r < nrest; r++) {
-      const int64_t a = rs + 4ll * r;
+    const int64_t from = q0 > (int64_t)data_end ? q0 : (int64_t)data_end;
+    for (uint32_t r = (uint32_t)((from - data_end) >> 2); r < nrest; r++) {
+      const int64_t a = (int64_t)data_end + 4ll * r;
       if (a >= pend) break;
       const Ov o = overlap(p0, a, a + 4);
-      if (o.n) acc |= shl_bytes(keep_bytes((u128)(blk_off[(uint64_t)r * R] >> (8 * o.o)), o.n), o.d);
+      if (o.n) acc |= shl_bytes(keep_bytes((u128)(off[(uint64_t)r * R] >> (8 * o.o)), o.n), o.d);
     }
     const int64_t a = (int64_t)size - 4;
     const Ov o = overlap(p0, a, a + 4);
     if (o.n) acc |= shl_bytes(keep_bytes((u128)(nrest >> (8 * o.o)), o.n), o.d);
   }
-  uint4 v;
-  v.x = (uint32_t)acc;
-  v.y = (uint32_t)(acc >> 32);
-  v.z = (uint32_t)(acc >> 64);
-  v.w = (uint32_t)(acc >> 96);
-  return v;
+  return make_uint4((uint32_t)acc, (uint32_t)(acc >> 32), (uint32_t)(acc >> 64), (uint32_t)(acc >> 96));
 }
 
-// One wave per output data block.  The block's message (contents || type
-// byte) is produced as 16-byte chunks aligned to its end; lane l produces the
-// chunks c = 63 - l + 64 i (c counted from the end) in increasing position,
-// stores each and folds it into its CRC register (Horner with a shift by
-// 1024 bytes), and the wave joins the 64 registers at the end.  Entry
-// metadata is staged in LDS ENC_W entries at a time; a window after the first
-// starts 8 entries before the previous one ended, so a chunk assigned to a
-// window (by its first byte) never reaches past the window's entries (an
-// entry is at least 4 bytes).
-constexpr uint32_t ENC_B = 4;  // whole value chunks per lane in flight together
-constexpr uint32_t ENC_T = 4;  // byte tasks per lane in flight together
+// ---------------------------------------------------------------------------
+// Gap chunks.  A block message is cut into 16-byte chunks aligned to its end
+// (chunk m covers positions [16 m - gshift, 16 m - gshift + 16), gshift =
+// 16 J16 - n).  The chunks lying wholly inside one value (its interior) are
+// copied from the input by the encoder; every other chunk (headers, key
+// deltas, value edges, the restart array and the block tail) is a gap chunk,
+// assembled here once into the gap buffer.  Slot 0 of a block holds its
+// message bytes [0, 16) instead (what the encoder stores for a first chunk
+// that starts before the message); slots 1.. hold the gap chunks in order.
+// One thread per slot.
 
-constexpr uint32_t ENC_OVERLAP = 16;  // entries shared by consecutive windows (>= 64 bytes)
-constexpr uint32_t GEN_UNIT = 64;     // bytes a lane folds per step in k_encode_gen
+// Threads go to blocks in groups of GAP_GROUP: thread j of a block's group
+// takes its slots j, j + GAP_GROUP, ...
+constexpr uint32_t GAP_GROUP = 16;
 
-__global__ void __launch_bounds__(512) k_encode_gen(EncodeArgs A) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  CrcLds* T = (CrcLds*)smem;
-  load_crc_tables(T, A.g_crc, threadIdx.x, blockDim.x);
-  __syncthreads();
-  const uint32_t wv = threadIdx.x / WAVE, l = lane_id();
-  const uint32_t waves = blockDim.x / WAVE;
-  EncLds* L = (EncLds*)(smem + sizeof(CrcLds)) + wv;
-  // a lane folds 64-byte units (four chunks in sequence); units are joined
-  // by multiplications with x^(8 m) mod P for m = 4096 (between a lane's
-  // units) and 64 * 2^k (lanes)
-  uint32_t kj[7];
-#pragma unroll
-  for (int k = 0; k < 7; k++) kj[k] = gf2_xpow8n((uint64_t)GEN_UNIT << k);
+__global__ void __launch_bounds__(256) k_gaps(EncodeArgs A) {
   const uint64_t nb = *A.nblocks;
-  for (uint64_t b = (uint64_t)blockIdx.x * waves + wv; b < nb; b += (uint64_t)gridDim.x * waves) {
+  const uint64_t groups = (uint64_t)gridDim.x * blockDim.x / GAP_GROUP;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t b = tid / GAP_GROUP; b < nb; b += groups) {
     const BlockRec B = A.blk[b];
-    const uint32_t R = B.R, cnt = B.cnt, size = B.size;
-    const uint64_t s0 = B.s0;
-    const uint32_t nrest = (cnt + R - 1) / R;
-    const uint32_t data_end = size - 4 * nrest - 4;
-    const int64_t n = (int64_t)size + 1;
-    uint8_t* dst = A.out + B.dst;
-    const uint32_t* blk_off = A.ent_off + s0;
-    const int64_t JU = (n + GEN_UNIT - 1) / GEN_UNIT;
-    const int64_t u_first = 63 - (int64_t)l;
-    int64_t uu = u_first < JU ? u_first + 64 * ((JU - 1 - u_first) / 64) : -1;
-    uint32_t acc = 0;
-    uint32_t k0 = 0;
-    for (;;) {
-      const uint32_t k1 = min(cnt, k0 + ENC_W);
-      const uint32_t nw = k1 - k0;
-      const bool last = (k1 == cnt);
-      if (l < nw) {
-        const uint32_t i = k0 + l;
-        const EncRec r = A.rec[s0 + i];
-        const uint32_t shared = (i % R == 0) ? 0u : r.shared;
-        const uint32_t st = blk_off[i];
-        const uint32_t ns = r.ulen + 8 - shared;
-        L->st[l] = st;
-        L->vs[l] = st + vlen32(shared) + vlen32(ns) + vlen32(r.vlen) + ns;
-        L->e[l] = r.e;
-        L->sh[l] = shared;
-        L->ul[l] = r.ulen;
-        L->vp[l] = r.vp;
-        L->tag[l] = r.tag;
+    const uint64_t g0 = A.gap_base[b], ns = A.gap_base[b + 1] - g0;
+    const uint32_t n = B.size + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
+    const EntL* E = A.entl + B.s0;
+    for (uint64_t g = tid % GAP_GROUP; g < ns; g += GAP_GROUP) {
+      int64_t p0 = 0;
+      uint32_t lo = 0;
+      if (g > 0) {
+        // gap chunk g - 1: after the interior of the last entry with fewer
+        // gap chunks before its interior (ia - cum) than g
+        const uint64_t gq = g - 1;
+        uint64_t m = gq;
+        if ((uint64_t)(E[0].ia - E[0].cum) <= gq) {
+          uint32_t hi = B.cnt;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((uint64_t)(E[mid].ia - E[mid].cum) <= gq) lo = mid;
+            else hi = mid;
+          }
+          m = gq + E[lo].cum + E[lo].pieces;
+        }
+        p0 = 16 * (int64_t)m - (int64_t)gshift;
       }
-      if (l == 0) L->st[nw] = last ? data_end : blk_off[k1];
-      wave_sync();
-      // units assigned to this window by their first byte; a unit never
-      // reaches past the window's entries (the next window starts
-      // ENC_OVERLAP entries, at least 64 bytes, earlier)
-      const int64_t hi = last ? n : (int64_t)L->st[nw - ENC_OVERLAP];
-      uint32_t cur = 0;
-      while (uu >= 0) {
-        const int64_t p = n - (int64_t)GEN_UNIT * (uu + 1);
-        if ((p < 0 ? 0 : p) >= hi) break;
-        uint4 v[4];
-        uint32_t slow = 0;
-#pragma unroll
-        for (uint32_t q = 0; q < 4; q++) {
-          const int64_t p0 = p + 16 * q;
-          v[q] = make_uint4(0, 0, 0, 0);
-          if (p0 + 16 <= 0) continue;
-          const int64_t P = p0 < 0 ? 0 : p0;
-          // entry holding P: the last with st <= P (from the lane's cursor)
-          uint32_t lo_i = cur, hi_i = nw;
-          while (hi_i - lo_i > 1) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            if ((int64_t)L->st[mid] <= P) lo_i = mid;
-            else hi_i = mid;
-          }
-          cur = lo_i;
-          const int64_t vs = L->vs[cur];
-          if (p0 >= vs && p0 + 16 <= (int64_t)L->st[cur + 1]) v[q] = ldg16(L->vp[cur] + (uint64_t)(p0 - vs));
-          else slow |= 1u << q;
-        }
-        // chunks that cross a segment boundary, one at a time
-        while (slow) {
-          const uint32_t q = __builtin_ctz(slow);
-          slow &= slow - 1;
-          const int64_t p0 = p + 16 * q;
-          const int64_t P = p0 < 0 ? 0 : p0;
-          uint32_t lo_i = 0, hi_i = nw;
-          while (hi_i - lo_i > 1) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            if ((int64_t)L->st[mid] <= P) lo_i = mid;
-            else hi_i = mid;
-          }
-          const uint4 r = enc_chunk_slow(L, nw, lo_i, p0, data_end, (uint32_t)size, nrest, R, blk_off, A.tu.heap, A.kw8);
-#pragma unroll
-          for (uint32_t u = 0; u < 4; u++)
-            if (u == q) v[u] = r;
-        }
-#pragma unroll
-        for (uint32_t q = 0; q < 4; q++) {
-          const int64_t p0 = p + 16 * q;
-          if (p0 >= 0) {
-            __builtin_memcpy(dst + p0, &v[q], 16);
-          } else if (p0 + 16 > 0) {
-            const uint8_t* vb = (const uint8_t*)&v[q];
-            for (int k = 0; k < 16; k++)
-              if (p0 + k >= 0) dst[p0 + k] = vb[k];
-          }
-        }
-        uint32_t ur = 0;
-#pragma unroll
-        for (uint32_t q = 0; q < 4; q++) ur = crc_chunk_from(T, ur, v[q], p + 16 * q);
-        acc = gf2_mulmod(acc, kj[6]) ^ ur;
-        uu -= 64;
-      }
-      wave_sync();
-      if (last) break;
-      k0 = k1 - ENC_OVERLAP;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-      uint32_t other = __shfl_down(acc, 1u << k, WAVE);
-      if (l + (1u << k) >= WAVE) other = 0;
-      acc = gf2_mulmod(acc, kj[k]) ^ other;
-    }
-    if (l == 0) {
-      const uint32_t m = crc_mask(acc ^ 0xFFFFFFFFu);
-      __builtin_memcpy(dst + n, &m, 4);
+      A.gapbuf[g0 + g] = enc_bytes(A, B, p0, lo);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Staged encoder.  Per wave: [EncWin entry window | stage].  The block
-// message (contents || type byte) sits at the end of the stage, which is
-// 16-byte aligned, so the chunk grid of the CRC (16-byte chunks aligned to the
-// message end) is the aligned grid of the stage.
+// Encoder: one wave per output data block.  Lane l takes the chunks
+// c = 63 - l + 64 i (counted from the end of the message, first to last):
+// an interior chunk is read from its value, a gap chunk from the gap buffer;
+// each is stored into the output and folded into the lane's CRC register
+// (Horner, a shift by 1024 bytes between a lane's chunks), and the lanes are
+// joined at the end.  The chunk sources come from the block's entry layout
+// (lane i holds entry i when the block has at most 64 entries; a binary
+// search over it by shuffles finds a chunk's entry).
 //
-// Blocks are software-pipelined: while block X is stored and checksummed
-// from registers, the loads that fill block X+1 (its first window of value
-// chunks and bytes) are in flight, its entry records were loaded one block
-// ahead and its handle two blocks ahead.  Every global load and store of the
-// common path is issued by every lane (a lane with nothing to load reads a
-// fixed valid address; stores go through a buffer descriptor of the block,
-// and a lane with nothing to store uses an offset past its end, which the
-// hardware drops), so each wait is for exactly the loads it needs.
+// Blocks are software-pipelined: while block X is stored and checksummed,
+// the chunk loads of block X+1 are in flight, its layout was loaded one block
+// ahead and its handle two blocks ahead.  Every load and store of the common
+// path is issued by every lane (a lane with nothing to load reads a fixed
+// valid address; stores go through a buffer descriptor of the block, and a
+// lane with nothing to store uses an offset past its end, which the hardware
+// drops), so each wait is for exactly the loads it needs.
 
-constexpr uint32_t ENC_QS = 5;           // chunks per lane held in registers: blocks up to 5 KiB pipelined
+constexpr uint32_t ENC_QS = 5;             // chunks per lane in registers: blocks up to 5 KiB pipelined
 constexpr uint32_t ENC_OOB = 0x80000000u;  // a buffer offset past any block
 
 struct EncH {  // one block, the same in every lane
-  uint64_t dst, s0;
-  uint32_t cnt, size, R;
-  bool valid;
+  uint64_t dst, s0, gap;
+  uint32_t cnt, n, J16, gshift;
+  bool valid, piped;
 };
 
 __device__ __forceinline__ EncH enc_handle(const EncodeArgs& A, uint64_t b, uint64_t nb) {
-  const BlockRec r = A.blk[b < nb ? b : nb - 1];  // nb > 0
+  const uint64_t bb = b < nb ? b : nb - 1;  // nb > 0
+  const BlockRec r = A.blk[bb];
   EncH h;
   h.dst = r.dst;
   h.s0 = r.s0;
+  h.gap = A.gap_base[bb];
   h.cnt = r.cnt;
-  h.size = r.size;
-  h.R = r.R;
+  h.n = r.size + 1;
+  h.J16 = (h.n + 15) / 16;
+  h.gshift = 16 * h.J16 - h.n;
   h.valid = b < nb;
+  h.piped = h.J16 <= 64 * ENC_QS && h.cnt <= WAVE && h.n >= 16;
   return h;
 }
 
-struct EncE {  // this lane's entry of a window
-  EncRec r;
-  uint32_t st;
-};
-
-// entry k0 + l of block H (lanes past the block's end read its last entry)
-__device__ __forceinline__ EncE enc_entry(const EncodeArgs& A, const EncH& H, uint32_t k0) {
-  const uint32_t i = min(k0 + lane_id(), H.cnt - 1);  // cnt >= 1
-  EncE e;
-  e.r = A.rec[H.s0 + i];
-  e.st = A.ent_off[H.s0 + i];
-  return e;
+// this lane's entry of the block (lanes past its end repeat the last one)
+__device__ __forceinline__ EntL enc_entl(const EncodeArgs& A, const EncH& H) {
+  return A.entl[H.s0 + min(lane_id(), H.cnt - 1)];  // cnt >= 1
 }
 
-struct EncL {
-  uint32_t nw, ntasks, npieces;
-  uint32_t rs;  // restart slot of this lane's entry: its index + 1, or 0
-  uint32_t st;
-};
-
-// lays out entries k0 .. k0 + nw - 1 (lane l: entry k0 + l) into the window
-__device__ __forceinline__ EncL enc_layout(EncWin* W, const EncH& H, uint32_t k0, const EncE& E, uint32_t gshift) {
-  const uint32_t l = lane_id();
-  EncL L;
-  L.nw = min(H.cnt - k0, ENC_SW);
-  L.rs = 0;
-  L.st = E.st;
-  uint32_t tasks = 0, pieces = 0;
-  if (l < L.nw) {
-    const uint32_t i = k0 + l;
-    const EncRec& r = E.r;
-    const uint32_t st = E.st;
-    const uint32_t shared = (i % H.R == 0) ? 0u : r.shared;
-    const uint32_t ns = r.ulen + 8 - shared;
-    uint32_t la, lb, lc;
-    const uint64_t va = pack_varint(shared, &la), vb = pack_varint(ns, &lb), vc = pack_varint(r.vlen, &lc);
-    const u128 Hd = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
-    const uint32_t hl = la + lb + lc;
-    const uint32_t vs = st + hl + ns, en = vs + r.vlen;
-    // a: first grid position >= vs; z: last grid position <= en (it can lie
-    // before the message start, hence signed)
-    const uint32_t a = vs + ((16u - ((vs + gshift) & 15u)) & 15u);
-    const int64_t z = (int64_t)en - (int64_t)((en + gshift) & 15u);
-    uint32_t h_end = en, t_beg = en;
-    if ((int64_t)a + 16 <= z) {
-      pieces = (uint32_t)((z - (int64_t)a) / 16);
-      h_end = a;
-      t_beg = (uint32_t)z;
-    }
-    W->vp[l] = r.vp;
-    W->tag[l] = r.tag;
-    W->h0[l] = (uint64_t)Hd;
-    W->h1[l] = (uint64_t)(Hd >> 64);
-    W->st[l] = st;
-    W->hl[l] = hl;
-    W->ns[l] = ns;
-    W->sh[l] = shared;
-    W->ul[l] = r.ulen;
-    W->e[l] = r.e;
-    W->vs[l] = vs;
-    W->a[l] = a;
-    W->hn[l] = h_end - vs;
-    W->tb[l] = t_beg;
-    tasks = hl + ns + (h_end - vs) + (en - t_beg);
-    if (i % H.R == 0) L.rs = i / H.R + 1;
+// the source address of chunk m of block H, E being this lane's entry of it
+// (the block has at most 64 entries)
+__device__ __forceinline__ uint64_t enc_src(const EncodeArgs& A, const EncH& H, const EntL& E, uint32_t m) {
+  // the last entry whose interior starts at or before m (entry 0 if none):
+  // the same steps in every lane, so that every shuffle reads active lanes
+  uint32_t lo = 0;
+  for (uint32_t step = H.cnt > 1 ? 1u << (31 - __builtin_clz(H.cnt - 1)) : 0u; step; step >>= 1) {
+    const uint32_t k = min(lo + step, H.cnt - 1);
+    if ((uint32_t)__shfl((int)E.ia, (int)k, WAVE) <= m && lo + step < H.cnt) lo += step;
   }
-  const uint32_t ti = wave_incl_scan(tasks), pi = wave_incl_scan(pieces);
-  if (l < L.nw) {
-    W->pb[l] = ti - tasks;
-    W->pc[l] = pi - pieces;
-  }
-  L.ntasks = __shfl(ti, WAVE - 1, WAVE);
-  L.npieces = __shfl(pi, WAVE - 1, WAVE);
-  if (l == 0) {
-    W->pb[L.nw] = L.ntasks;
-    W->pc[L.nw] = L.npieces;
-  }
-  wave_sync();
-  return L;
+  const uint32_t ia = __shfl((int)E.ia, (int)lo, WAVE), pieces = __shfl((int)E.pieces, (int)lo, WAVE);
+  const uint32_t cum = __shfl((int)E.cum, (int)lo, WAVE);
+  const uint64_t vsrc = ((uint64_t)(uint32_t)__shfl((int)(E.vsrc >> 32), (int)lo, WAVE) << 32) |
+                        (uint32_t)__shfl((int)(uint32_t)E.vsrc, (int)lo, WAVE);
+  if (ia <= m && m < ia + pieces) return vsrc + 16ull * m;
+  const uint32_t g = ia <= m ? m - cum - pieces : m;  // gap chunks before m
+  return (uint64_t)(uintptr_t)(A.gapbuf + H.gap + 1 + g);
 }
 
-// one batch of a window's stage writes, loaded into registers: whole aligned
-// value chunks kp0 + l + 64 t and byte tasks kt0 + l + 64 t
-struct EncIss {
-  uint4 v[ENC_B];
-  uint32_t pos[ENC_B];  // stage position of the chunk, ~0: none
-  uint32_t bl[ENC_T];   // loaded byte
-  uint32_t bd[ENC_T];   // stage position of the byte | its value << 20 (0x100: the loaded one); ~0: none
-};
-constexpr uint32_t ENC_LOADED = 0x100u << 20;
-
-__device__ __forceinline__ uint32_t win_find(const uint32_t* off, uint32_t nw, uint32_t k) {
-  uint32_t lo = 0, hi = nw;  // off[lo] <= k < off[hi]
+// the same for any block: binary search over the global layout
+__device__ __forceinline__ uint64_t enc_src_any(const EncodeArgs& A, const EncH& H, uint32_t m) {
+  const EntL* E = A.entl + H.s0;
+  uint32_t lo = 0, hi = H.cnt;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= k) lo = mid;
+    if (E[mid].ia <= m) lo = mid;
     else hi = mid;
   }
-  return lo;
+  const EntL e = E[lo];
+  if (e.ia <= m && m < e.ia + e.pieces) return e.vsrc + 16ull * m;
+  const uint32_t g = e.ia <= m ? m - e.cum - e.pieces : m;
+  return (uint64_t)(uintptr_t)(A.gapbuf + H.gap + 1 + g);
 }
 
-__device__ __forceinline__ void enc_issue(const EncWin* W, const EncodeArgs& A, const EncL& L, uint32_t kp0,
-                                          uint32_t kt0, uint64_t safe, EncIss& I) {
-  const uint32_t l = lane_id();
-#pragma unroll
-  for (uint32_t t = 0; t < ENC_B; t++) {
-    const uint32_t k = kp0 + l + WAVE * t;
-    uint64_t src = safe;
-    I.pos[t] = ~0u;
-    if (k < L.npieces) {
-      const uint32_t lo = win_find(W->pc, L.nw, k);
-      I.pos[t] = W->a[lo] + 16 * (k - W->pc[lo]);
-      src = W->vp[lo] + (I.pos[t] - W->vs[lo]);
-    }
-    I.v[t] = ldg16(src);
-  }
-#pragma unroll
-  for (uint32_t t = 0; t < ENC_T; t++) {
-    const uint32_t k = kt0 + l + WAVE * t;
-    uint64_t src = safe;
-    I.bd[t] = ~0u;
-    if (k < L.ntasks) {
-      const uint32_t lo = win_find(W->pb, L.nw, k);
-      uint32_t o = k - W->pb[lo];
-      const uint32_t hl = W->hl[lo], ns = W->ns[lo];
-      if (o < hl) {
-        const uint32_t v = (uint32_t)((o < 8 ? W->h0[lo] >> (8 * o) : W->h1[lo] >> (8 * (o - 8))) & 0xFFu);
-        I.bd[t] = (W->st[lo] + o) | (v << 20);
-      } else if (o < hl + ns) {
-        const uint32_t q = W->sh[lo] + (o - hl), ul = W->ul[lo];
-        uint32_t v = ENC_LOADED;
-        if (q < ul) src = (uint64_t)(uintptr_t)A.tu.heap + (uint64_t)W->e[lo] * A.kw8 * 8 + q;
-        else v = ((uint32_t)(W->tag[lo] >> (8 * (q - ul))) & 0xFFu) << 20;
-        I.bd[t] = (W->st[lo] + o) | v;
-      } else {
-        o -= hl + ns;
-        const uint32_t hn = W->hn[lo], vs = W->vs[lo];
-        const uint32_t off = (o < hn) ? o : (W->tb[lo] - vs) + (o - hn);
-        src = W->vp[lo] + off;
-        I.bd[t] = (vs + off) | ENC_LOADED;
-      }
-    }
-    I.bl[t] = ldg_u8(src);
-  }
+__device__ __forceinline__ int64_t enc_top(const EncH& H) {
+  const int64_t c0 = 63 - (int64_t)lane_id();
+  return c0 < (int64_t)H.J16 ? c0 + 64 * (((int64_t)H.J16 - 1 - c0) / 64) : -1;
 }
 
-__device__ __forceinline__ void enc_put(uint8_t* base, const EncIss& I) {
-#pragma unroll
-  for (uint32_t t = 0; t < ENC_T; t++)
-    if (I.bd[t] != ~0u) base[I.bd[t] & 0xFFFFFu] = (uint8_t)(I.bd[t] >> 20 == 0x100u ? I.bl[t] : I.bd[t] >> 20);
-#pragma unroll
-  for (uint32_t t = 0; t < ENC_B; t++)
-    if (I.pos[t] != ~0u) *(uint4*)(base + I.pos[t]) = I.v[t];
-}
-
-__device__ __forceinline__ void put_u32(uint8_t* d, uint32_t v) {
-  d[0] = (uint8_t)v;
-  d[1] = (uint8_t)(v >> 8);
-  d[2] = (uint8_t)(v >> 16);
-  d[3] = (uint8_t)(v >> 24);
-}
-
-struct EncG {  // the stage geometry of a block
-  uint32_t n, J16, gshift, nrest, data_end;
-  uint8_t* base;  // message byte p at base[p]
+// chunk loads of a pipelined block: ENC_QS chunks and the head slot
+struct EncV {
+  uint4 v[ENC_QS];
+  uint4 head;
 };
 
-__device__ __forceinline__ EncG enc_geom(const EncH& H, uint8_t* stage_end) {
-  EncG g;
-  g.n = H.size + 1;
-  g.J16 = (g.n + 15) / 16;
-  g.gshift = 16 * g.J16 - g.n;
-  g.nrest = (H.cnt + H.R - 1) / H.R;
-  g.data_end = H.size - 4 * g.nrest - 4;
-  g.base = stage_end - g.n;
-  return g;
-}
-
-// writes the rest of block H into the stage once its first batch I (of the
-// first window, laid out as L) has arrived: the first batch, the remaining
-// batches and windows, the restart array, restart count and type byte
-__device__ __forceinline__ void enc_commit(EncWin* W, const EncodeArgs& A, const EncH& H, const EncG& g,
-                                           const EncL& L0, const EncIss& I0, uint64_t safe) {
-  const uint32_t l = lane_id();
-  enc_put(g.base, I0);
-  if (L0.rs) put_u32(g.base + g.data_end + 4 * (L0.rs - 1), L0.st);
-  EncL L = L0;
-  uint32_t kp = WAVE * ENC_B, kt = WAVE * ENC_T;
-  for (uint32_t k0 = 0;;) {
-    while (kp < L.npieces || kt < L.ntasks) {
-      EncIss I;
-      enc_issue(W, A, L, kp, kt, safe, I);
-      enc_put(g.base, I);
-      kp += WAVE * ENC_B;
-      kt += WAVE * ENC_T;
-    }
-    k0 += ENC_SW;
-    if (k0 >= H.cnt) break;
-    wave_sync();
-    const EncE E = enc_entry(A, H, k0);
-    L = enc_layout(W, H, k0, E, g.gshift);
-    if (L.rs) put_u32(g.base + g.data_end + 4 * (L.rs - 1), L.st);
-    kp = 0;
-    kt = 0;
+__device__ __forceinline__ void enc_load(const EncodeArgs& A, const EncH& H, const EntL& E, uint64_t safe, EncV& V) {
+  const int64_t ct = enc_top(H);
+#pragma unroll
+  for (uint32_t q = 0; q < ENC_QS; q++) {
+    const int64_t c = ct - 64 * (int64_t)q;
+    const uint64_t src = enc_src(A, H, E, (uint32_t)((int64_t)H.J16 - 1 - (c >= 0 ? c : 0)));
+    V.v[q] = ldg16(c >= 0 && H.valid ? src : safe);
   }
-  if (l == 0) {
-    put_u32(g.base + H.size - 4, g.nrest);
-    g.base[H.size] = 0;
-  }
-  wave_sync();
+  V.head = ldg16(H.valid ? (uint64_t)(uintptr_t)(A.gapbuf + H.gap) : safe);
 }
 
-__device__ __forceinline__ u128 u4_to_u128(uint4 v) {
-  return ((u128)(((uint64_t)v.w << 32) | v.z) << 64) | (((uint64_t)v.y << 32) | v.x);
-}
-__device__ __forceinline__ uint4 u128_to_u4(u128 x) {
-  return make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
-}
-
-// block message in the stage -> output bytes and masked CRC, any size: lane l
-// takes the chunks c = 63 - l + 64 i, first to last; only a lane's first
-// chunk can reach below message position 4
-__device__ __forceinline__ void enc_store_loop(const CrcLds* T, const EncH& H, const EncG& g, uint8_t* stage_end,
-                                               uint8_t* dst) {
-  const uint32_t n = g.n;
+// stores and checksums a pipelined block from registers
+__device__ __forceinline__ void enc_store(const CrcLds* T, const EncodeArgs& A, const EncH& H, const EncV& V) {
+  const int64_t ct = enc_top(H);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(A.out + H.dst, (short)0, (int)(H.n + 4), 0x00020000);
   uint32_t acc = 0;
-  const int64_t c_first = 63 - (int64_t)lane_id();
-  int64_t c = c_first < (int64_t)g.J16 ? c_first + 64 * (((int64_t)g.J16 - 1 - c_first) / 64) : -1;
-  if (c >= 0 && (int64_t)n - 16 * (c + 1) < 4) {
+#pragma unroll
+  for (uint32_t q = 0; q < ENC_QS; q++) {
+    const int64_t c = ct - 64 * (int64_t)q;
+    const int64_t p0 = (int64_t)H.n - 16 * (c + 1);
+    const uint4 o = (q == 0 && p0 < 0) ? V.head : V.v[q];
+    const u32x4 dv = {o.x, o.y, o.z, o.w};
+    __builtin_amdgcn_raw_buffer_store_b128(dv, rs, c >= 0 ? (uint32_t)(p0 > 0 ? p0 : 0) : ENC_OOB, 0, 0);
+    if (c >= 0) {
+      if (q == 0) acc = p0 < 4 ? crc_chunk(T, V.v[0], p0) : crc_chunk_plain(T, V.v[0]);
+      else acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, V.v[q]);
+    }
+  }
+  const uint32_t raw = crc_wave_join(T, acc);
+  __builtin_amdgcn_raw_buffer_store_b32(crc_mask(raw ^ 0xFFFFFFFFu), rs, lane_id() == 0 ? H.n : ENC_OOB, 0, 0);
+}
+
+// any block, one chunk at a time
+__device__ void enc_block_any(const CrcLds* T, const EncodeArgs& A, const EncH& H) {
+  uint8_t* dst = A.out + H.dst;
+  const uint32_t n = H.n;
+  uint32_t acc = 0;
+  for (int64_t c = enc_top(H); c >= 0; c -= 64) {
     const int64_t p0 = (int64_t)n - 16 * (c + 1);
-    const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
+    const uint4 v = ldg16(enc_src_any(A, H, (uint32_t)((int64_t)H.J16 - 1 - c)));
     if (p0 >= 0) {
       __builtin_memcpy(dst + p0, &v, 16);
+      acc = crc_shift(T->sh[6], acc) ^ (p0 < 4 ? crc_chunk(T, v, p0) : crc_chunk_plain(T, v));
     } else {
       const uint8_t* vb = (const uint8_t*)&v;
       for (int k = 0; k < 16; k++)
         if (p0 + k >= 0) dst[p0 + k] = vb[k];
+      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
     }
-    acc = crc_chunk(T, v, p0);
-    c -= 64;
-  }
-  for (; c >= 0; c -= 64) {
-    const uint32_t p0 = n - 16 * (uint32_t)(c + 1);
-    const uint4 v = *(const uint4*)(stage_end - 16 * (c + 1));
-    __builtin_memcpy(dst + p0, &v, 16);
-    acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, v);
   }
   const uint32_t raw = crc_wave_join(T, acc);
   if (lane_id() == 0) {
@@ -588,95 +346,36 @@ __device__ __forceinline__ void enc_store_loop(const CrcLds* T, const EncH& H, c
 }
 
 __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  CrcLds* T = (CrcLds*)smem;
-  load_crc_tables(T, A.g_crc, threadIdx.x, blockDim.x);
+  __shared__ CrcLds T;
+  load_crc_tables(&T, A.g_crc, threadIdx.x, blockDim.x);
   __syncthreads();
   const uint64_t nb = *A.nblocks;
   if (nb == 0) return;
   // the wave index is the same in every lane: block handles are scalar loads
-  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), l = lane_id();
-  const uint32_t waves = blockDim.x / WAVE;
-  uint8_t* wbase = smem + sizeof(CrcLds) + (size_t)wv * A.wave_lds;
-  EncWin* W = (EncWin*)wbase;
-  uint8_t* stage_end = wbase + A.wave_lds;
-  const uint64_t stride = (uint64_t)gridDim.x * waves;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const uint64_t stride = (uint64_t)gridDim.x * (blockDim.x / WAVE);
   const uint64_t safe = (uint64_t)(uintptr_t)A.g_crc;
-  uint64_t b = (uint64_t)blockIdx.x * waves + wv;
+  uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
   if (b >= nb) return;
-  // prologue: block b staged, the next block's handle and first records
-  EncH H = enc_handle(A, b, nb), Hn = enc_handle(A, b + stride, nb);
-  {
-    const EncG g = enc_geom(H, stage_end);
-    const EncE E = enc_entry(A, H, 0);
-    const EncL L = enc_layout(W, H, 0, E, g.gshift);
-    EncIss I;
-    enc_issue(W, A, L, 0, 0, safe, I);
-    enc_commit(W, A, H, g, L, I, safe);
+  EncH H0 = enc_handle(A, b, nb), H1 = enc_handle(A, b + stride, nb), H2 = enc_handle(A, b + 2 * stride, nb);
+  EntL E1 = enc_entl(A, H1);
+  EncV V0;
+  if (H0.piped) {
+    const EntL E0 = enc_entl(A, H0);
+    enc_load(A, H0, E0, safe, V0);
   }
-  EncE En = enc_entry(A, Hn, 0);
   for (; b < nb; b += stride) {
-    const EncH Hnn = enc_handle(A, b + 2 * stride, nb);
-    const EncG g = enc_geom(H, stage_end);
-    uint8_t* dst = A.out + H.dst;
-    const bool piped = g.J16 <= 64 * ENC_QS && g.n >= 16;
-    // the next block: first window laid out, its first batch in flight
-    // (the window is free: this block is wholly in the stage)
-    const EncG gn = enc_geom(Hn, stage_end);
-    EncL Ln;
-    EncIss In;
-    if (Hn.valid) {
-      Ln = enc_layout(W, Hn, 0, En, gn.gshift);
-      enc_issue(W, A, Ln, 0, 0, safe, In);
-    }
-    if (piped) {
-      // this block's chunks into registers, then stored and checksummed;
-      // every lane issues ENC_QS chunk stores.  A first chunk that starts
-      // before the message is stored as message bytes [0, 16) (the bytes past
-      // it are the next chunk's)
-      const int64_t c_first = 63 - (int64_t)l;
-      const int64_t ct = c_first < (int64_t)g.J16 ? c_first + 64 * (((int64_t)g.J16 - 1 - c_first) / 64) : -1;
-      const int64_t pt = (int64_t)g.n - 16 * (ct + 1);
-      uint4 s[ENC_QS];
-#pragma unroll
-      for (uint32_t q = 0; q < ENC_QS; q++) {
-        const int64_t c = ct - 64 * (int64_t)q;
-        s[q] = c >= 0 ? *(const uint4*)(stage_end - 16 * (c + 1)) : make_uint4(0, 0, 0, 0);
-      }
-      if (ct >= 1 && pt < 0) {
-        const uint4 nx = *(const uint4*)(stage_end - 16 * ct);  // chunk ct - 1
-        const uint32_t sh = (uint32_t)(-pt);
-        s[0] = u128_to_u4((u4_to_u128(s[0]) >> (8 * sh)) | (u4_to_u128(nx) << (8 * (16 - sh))));
-      }
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)(g.n + 4), 0x00020000);
-      uint32_t acc = 0;
-#pragma unroll
-      for (uint32_t q = 0; q < ENC_QS; q++) {
-        const int64_t c = ct - 64 * (int64_t)q;
-        const int64_t p0 = (int64_t)g.n - 16 * (c + 1);
-        const u32x4 dv = {s[q].x, s[q].y, s[q].z, s[q].w};
-        __builtin_amdgcn_raw_buffer_store_b128(dv, rs, c >= 0 ? (uint32_t)(p0 > 0 ? p0 : 0) : ENC_OOB, 0, 0);
-        if (c >= 0) {
-          if (q == 0)
-            acc = p0 < 4 ? crc_chunk(T, p0 < 0 ? u128_to_u4(u4_to_u128(s[0]) << (8 * (uint32_t)-p0)) : s[0], p0)
-                         : crc_chunk_plain(T, s[0]);
-          else
-            acc = crc_shift(T->sh[6], acc) ^ crc_chunk_plain(T, s[q]);
-        }
-      }
-      const uint32_t raw = crc_wave_join(T, acc);
-      __builtin_amdgcn_raw_buffer_store_b32(crc_mask(raw ^ 0xFFFFFFFFu), rs, l == 0 ? g.n : ENC_OOB, 0, 0);
-    } else {
-      enc_store_loop(T, H, g, stage_end, dst);
-    }
-    wave_sync();
-    // records of the block after next, then the next block completed in the
-    // stage once its first batch has arrived
-    const EncE Enn = enc_entry(A, Hnn, 0);
-    if (Hn.valid) enc_commit(W, A, Hn, gn, Ln, In, safe);
-    H = Hn;
-    Hn = Hnn;
-    En = Enn;
+    const EncH H3 = enc_handle(A, b + 3 * stride, nb);
+    EncV V1;
+    if (H1.piped) enc_load(A, H1, E1, safe, V1);
+    const EntL E2 = enc_entl(A, H2);
+    if (H0.piped) enc_store(&T, A, H0, V0);
+    else enc_block_any(&T, A, H0);
+    H0 = H1;
+    H1 = H2;
+    H2 = H3;
+    E1 = E2;
+    V0 = V1;
   }
 }
 

@@ -381,11 +381,13 @@ __global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out) {
 
 __global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s, const JobDesc* jobs,
                              const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n,
-                             uint64_t cap, OutBlocks ob, uint32_t* ent_off) {
+                             const EncRec* rec, uint64_t cap, OutBlocks ob, uint32_t* ent_off, EntL* entl,
+                             uint32_t* gapcnt) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= cap) return;
   if (b >= job_ob0[J]) {
     ob.full[b] = 0;
+    gapcnt[b] = 0;
     return;
   }
   const uint32_t j = job_of(job_ob0, J, b);
@@ -408,6 +410,32 @@ __global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* 
   ob.size[b] = content;
   ob.full[b] = content + 5;
   ob.job[b] = j;
+  // value interiors in the chunk grid of the block message (contents and
+  // type byte): the whole chunks between the first grid position at or
+  // after the value start and the last one at or before its end
+  const uint32_t n = (uint32_t)content + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
+  uint32_t cum = 0;
+  for (uint32_t t = first; t < end; t++) {
+    const uint64_t s = sbase + t;
+    const EncRec rc = rec[s];
+    const uint32_t i = t - first;
+    const uint32_t sh = (i % R == 0) ? 0u : rc.shared;
+    const uint32_t ns = rc.ulen + 8 - sh;
+    const uint32_t vs = ent_off[s] + varint_len(sh) + varint_len(ns) + varint_len(rc.vlen) + ns;
+    const uint32_t en = vs + rc.vlen;
+    const uint32_t ia = (vs + gshift + 15) / 16;  // first grid position >= vs is 16 ia - gshift
+    const uint32_t iz = (en + gshift) / 16;       // last grid position <= en is 16 iz - gshift
+    const uint32_t pieces = iz > ia ? iz - ia : 0;
+    EntL L;
+    L.vsrc = rc.vp - (uint64_t)vs - (uint64_t)gshift;
+    L.ia = ia;
+    L.pieces = pieces;
+    L.cum = cum;
+    L.pad = 0;
+    entl[s] = L;
+    cum += pieces;
+  }
+  gapcnt[b] = J16 - cum + 1;  // and the head slot
 }
 
 // per output file: block range, data bytes, filter window count

@@ -124,9 +124,11 @@ void launch_seg_mark(const SegChunk* ch, const uint32_t* nch_dev, uint32_t grid,
 __global__ void k_make_segjobs(const uint64_t* base_excl, const uint32_t* counts, uint32_t J, SegJob* sj,
                                SegChunk* ch, uint32_t* nch_out);
 __global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out);
+struct EntL;
 __global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s, const JobDesc* jobs,
-                             const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n, uint64_t cap,
-                             OutBlocks ob, uint32_t* ent_off);
+                             const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n,
+                             const EncRec* rec, uint64_t cap, OutBlocks ob, uint32_t* ent_off, EntL* entl,
+                             uint32_t* gapcnt);
 __global__ void k_file_pre(const uint64_t* job_f0, uint32_t J, const uint64_t* job_ob0, const uint32_t* file_first,
                            const uint64_t* ob_excl, uint64_t cap, OutFiles of);
 __global__ void k_block_post(const uint64_t* nfiles_total, OutFiles of, const uint64_t* ob_excl,
@@ -147,6 +149,17 @@ struct EncRec {
   uint32_t shared;  // key bytes shared with the previous survivor of its job
   uint32_t ulen;
   uint32_t vlen;
+};
+// per survivor, written by k_block_meta: the whole 16-byte chunks of its
+// value in its block's chunk grid (chunks aligned to the end of the block
+// message; chunk m covers message positions [16 m - gshift, 16 m - gshift +
+// 16) with gshift = 16 ceil(n / 16) - n for a message of n bytes)
+struct EntL {
+  uint64_t vsrc;    // chunk m of the value interior is at vsrc + 16 m
+  uint32_t ia;      // first chunk of the interior (also set when it is empty)
+  uint32_t pieces;  // chunks of the interior
+  uint32_t cum;     // interior chunks of the earlier entries of the block
+  uint32_t pad;
 };
 // per output block, written by k_block_dst for the encoder
 struct BlockRec {
@@ -175,43 +188,12 @@ struct EncodeArgs {
   const EncRec* rec;
   const BlockRec* blk;
   uint32_t kw8;
-  uint32_t wave_lds;        // staged encoder: LDS bytes per wave (multiple of 16)
+  const EntL* entl;         // each survivor's value interior in its block's chunk grid
+  const uint64_t* gap_base; // first gap buffer slot of each block (and the total)
+  uint4* gapbuf;            // gap chunks (16 bytes each)
 };
-// entries of one output block held in LDS at a time (per wave)
-constexpr uint32_t ENC_W = 64;
-struct EncLds {
-  uint64_t vp[ENC_W];       // value address
-  uint64_t tag[ENC_W];
-  uint32_t st[ENC_W + 1];   // entry start (block offset); st[n] = end of the last
-  uint32_t vs[ENC_W];       // value start (block offset)
-  uint32_t e[ENC_W];        // decoded entry (key slot)
-  uint32_t sh[ENC_W];       // key bytes shared with the previous entry
-  uint32_t ul[ENC_W];       // user key length
-  uint32_t pad[3];
-};
-// the staged encoder's entry window (per wave)
-constexpr uint32_t ENC_SW = 32;
-struct EncWin {
-  uint64_t vp[ENC_SW];    // value address
-  uint64_t tag[ENC_SW];
-  uint64_t h0[ENC_SW];    // header bytes 0..7 (varints shared, non_shared, value_len)
-  uint64_t h1[ENC_SW];    // header bytes 8..14
-  uint32_t st[ENC_SW];    // entry start (block offset)
-  uint32_t hl[ENC_SW];    // header bytes
-  uint32_t ns[ENC_SW];    // key delta bytes
-  uint32_t sh[ENC_SW];    // key bytes shared with the previous entry
-  uint32_t ul[ENC_SW];    // user key length
-  uint32_t e[ENC_SW];     // decoded entry (key slot)
-  uint32_t vs[ENC_SW];    // value start (block offset)
-  uint32_t a[ENC_SW];     // first whole aligned chunk of the value
-  uint32_t hn[ENC_SW];    // value bytes before it
-  uint32_t tb[ENC_SW];    // first value byte after the last whole chunk
-  uint32_t pb[ENC_SW + 1];  // byte tasks: offsets (header, key delta, value edges)
-  uint32_t pc[ENC_SW + 1];  // whole-chunk copies: offsets
-  uint32_t pad[2];
-};
+__global__ void k_gaps(EncodeArgs A);
 __global__ void k_encode(EncodeArgs A);
-__global__ void k_encode_gen(EncodeArgs A);
 struct FilterArgs {
   const JobDesc* jobs;
   OutBlocks ob;

@@ -520,8 +520,10 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   ob.off = dbuf<uint64_t>(c, "ob_off", OB);
   ob.ie_size = dbuf<uint32_t>(c, "ob_ie", OB);
   uint32_t* ent_off = dbuf<uint32_t>(c, "ent_off", S);
+  EntL* entl = dbuf<EntL>(c, "ent_layout", S);
+  uint32_t* gapcnt = dbuf<uint32_t>(c, "gap_cnt", OB);
   hipLaunchKernelGGL(k_block_meta, dim3(blocks_for(OB)), dim3(256), 0, st, job_ob0, J, d_sj, P.d_jobs, seg_first,
-                     sz_r, sz_n, OB, ob, ent_off);
+                     sz_r, sz_n, erec, OB, ob, ent_off, entl, gapcnt);
   LAUNCH_CHECK();
   uint64_t* ob_excl = dbuf<uint64_t>(c, "ob_excl", OB + 1);
   uint64_t* scan_tmp = dbuf<uint64_t>(c, "scan_tmp64", OB / 2048 + 8);
@@ -598,6 +600,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     NF = *b;
     NW = *w;
     max_bsize = x[0];
+    c->counters.emplace_back("max_block_bytes", (double)max_bsize);
   }
 
   uint32_t* win_keys = dbuf<uint32_t>(c, "win_keys", NW);
@@ -675,28 +678,30 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.rec = erec;
     A.blk = brec;
     A.kw8 = P.kw8;
-    // staged encoder when a block message (plus the entry window) fits in
-    // LDS for at least two waves; otherwise the register generator
-    const size_t win = (sizeof(EncWin) + 15) & ~size_t(15);
-    const size_t per_wave = win + ((size_t(max_bsize) + 1 + 15) & ~size_t(15)) + 16;
-    const size_t budget = c->lds_limit - 2048 - CRC_LDS_BYTES;
-    const size_t sw = std::min<size_t>(c->tp.encode_waves, budget / per_wave);
-    const bool staged = sw >= 2 && per_wave < (1u << 31);
-    const int waves = staged ? (int)sw : 8;
-    const void* fn = staged ? (const void*)k_encode : (const void*)k_encode_gen;
-    A.wave_lds = staged ? (uint32_t)per_wave : 0;
-    const size_t lds = CRC_LDS_BYTES + (staged ? per_wave : sizeof(EncLds)) * waves;
+    A.entl = entl;
+    // gap chunks: every block's chunk slots (J16 + 1 at most), then the
+    // chunks that are not value interiors assembled once
+    uint64_t* gap_base = dbuf<uint64_t>(c, "gap_base", NBLK + 1);
+    uint64_t* scan_gap = dbuf<uint64_t>(c, "scan_tmp_gap", NBLK / 2048 + 8);
+    launch_scan<uint32_t, uint64_t>(gapcnt, NBLK, nullptr, gap_base, scan_gap, st);
+    LAUNCH_CHECK();
+    const uint64_t slots = dout / 16 + 2 * NBLK + 1;
+    A.gap_base = gap_base;
+    A.gapbuf = dbuf<uint4>(c, "gap_buf", slots);
+    KTimer kg(c, "k_gaps");
+    hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, NBLK * 16)), dim3(256), 0, st, A);  // 16 threads per block
+    LAUNCH_CHECK();
+    kg.stop();
+    const int waves = (int)c->tp.encode_waves;
     int occ = 0;
-    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, waves * 64, lds));
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, 0));
     occ = std::max(occ, 1);
     const uint64_t want = (NBLK + waves - 1) / waves;
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
     KTimer kt(c, "k_encode");
-    if (staged) hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), lds, st, A);
-    else hipLaunchKernelGGL(k_encode_gen, dim3(grid), dim3(waves * 64), lds, st, A);
+    hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), 0, st, A);
     LAUNCH_CHECK();
     kt.stop();
-    c->counters.emplace_back("encode_staged", staged ? 1.0 : 0.0);
     c->counters.emplace_back("encode_waves_per_group", (double)waves);
     c->counters.emplace_back("encode_groups", (double)grid);
     c->counters.emplace_back("encode_groups_per_cu", (double)occ);
@@ -1351,8 +1356,7 @@ int luda_ctx_create(int device, luda_ctx** out) {
     c->n_cu = prop.multiProcessorCount;
     c->lds_limit = prop.sharedMemPerBlock;
     // kernels whose dynamic LDS is sized at run time may use all of it
-    const void* dyn[] = {(const void*)k_encode, (const void*)k_encode_gen, (const void*)k_filter,
-                         (const void*)k_seg_compose};
+    const void* dyn[] = {(const void*)k_filter, (const void*)k_seg_compose};
     for (const void* f : dyn)
       HIPCK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_limit - 2048));
     static CrcTables T;
