@@ -103,8 +103,10 @@ __device__ inline Ov overlap(int64_t p0, int64_t a, int64_t b) {
 // Message bytes [p0, p0 + 16) of block B (positions outside [0, n) give
 // zeros), assembled from the overlapping parts: each entry's header, key
 // delta and value, then restart offsets, the restart count and the type
-// byte (0).  No entry before i0 reaches p0.
-__device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, int64_t p0, uint32_t i0) {
+// byte (0).  No entry before i0 reaches p0.  Ents gives entry i's start
+// (st(i)) and record (rec(i)).
+template <class Ents>
+__device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, const Ents& X, int64_t p0, uint32_t i0) {
   const uint32_t R = B.R, cnt = B.cnt, size = B.size;
   const uint32_t nrest = (cnt + R - 1) / R;
   const uint32_t data_end = size - 4 * nrest - 4;
@@ -113,9 +115,9 @@ __device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, int64_t p0, u
   const int64_t pend = p0 + 16, q0 = p0 < 0 ? 0 : p0;
   if (q0 < (int64_t)data_end) {
     for (uint32_t i = i0; i < cnt; i++) {
-      const int64_t st = off[i];
+      const int64_t st = X.st(i);
       if (st >= pend) break;
-      const EncRec r = A.rec[B.s0 + i];
+      const EncRec r = X.rec(i);
       const uint32_t sh = (i % R == 0) ? 0u : r.shared;
       const uint32_t ns = r.ulen + 8 - sh;
       uint32_t la, lb, lc;
@@ -158,39 +160,88 @@ __device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, int64_t p0, u
 // that starts before the message); slots 1.. hold the gap chunks in order.
 // One thread per slot.
 
-// Threads go to blocks in groups of GAP_GROUP: thread j of a block's group
-// takes its slots j, j + GAP_GROUP, ...
+// Threads go to blocks in groups of GAP_GROUP lanes of one wave: lane j of a
+// block's group takes its slots j, j + GAP_GROUP, ...  A block of at most
+// GAP_GROUP entries has its entries staged in LDS by the group first (one
+// round of loads), a larger one is read from global memory.
 constexpr uint32_t GAP_GROUP = 16;
 
+struct GapEnt {
+  EncRec r;
+  uint32_t st, ia, pieces, cum;
+};
+
+struct EntsGlobal {
+  const EncodeArgs* A;
+  uint64_t s0;
+  __device__ uint32_t st(uint32_t i) const { return A->ent_off[s0 + i]; }
+  __device__ EncRec rec(uint32_t i) const { return A->rec[s0 + i]; }
+  __device__ uint32_t gb(uint32_t i) const { return A->entl[s0 + i].ia - A->entl[s0 + i].cum; }
+  __device__ uint32_t after(uint32_t i) const { return A->entl[s0 + i].cum + A->entl[s0 + i].pieces; }
+};
+
+struct EntsLds {
+  const GapEnt* L;
+  __device__ uint32_t st(uint32_t i) const { return L[i].st; }
+  __device__ EncRec rec(uint32_t i) const { return L[i].r; }
+  __device__ uint32_t gb(uint32_t i) const { return L[i].ia - L[i].cum; }
+  __device__ uint32_t after(uint32_t i) const { return L[i].cum + L[i].pieces; }
+};
+
+// gap slot g of block B into the gap buffer
+template <class Ents>
+__device__ __forceinline__ void gap_slot(const EncodeArgs& A, const BlockRec& B, const Ents& X, uint64_t g0,
+                                         uint64_t g) {
+  const uint32_t n = B.size + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
+  int64_t p0 = 0;
+  uint32_t lo = 0;
+  if (g > 0) {
+    // gap chunk g - 1: after the interior of the last entry with fewer gap
+    // chunks before its interior (ia - cum) than g
+    const uint64_t gq = g - 1;
+    uint64_t m = gq;
+    if ((uint64_t)X.gb(0) <= gq) {
+      uint32_t hi = B.cnt;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)X.gb(mid) <= gq) lo = mid;
+        else hi = mid;
+      }
+      m = gq + X.after(lo);
+    }
+    p0 = 16 * (int64_t)m - (int64_t)gshift;
+  }
+  A.gapbuf[g0 + g] = enc_bytes(A, B, X, p0, lo);
+}
+
 __global__ void __launch_bounds__(256) k_gaps(EncodeArgs A) {
+  __shared__ GapEnt lds[256 / GAP_GROUP][GAP_GROUP];
   const uint64_t nb = *A.nblocks;
   const uint64_t groups = (uint64_t)gridDim.x * blockDim.x / GAP_GROUP;
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t j = threadIdx.x % GAP_GROUP;
+  GapEnt* L = lds[threadIdx.x / GAP_GROUP];
   for (uint64_t b = tid / GAP_GROUP; b < nb; b += groups) {
     const BlockRec B = A.blk[b];
     const uint64_t g0 = A.gap_base[b], ns = A.gap_base[b + 1] - g0;
-    const uint32_t n = B.size + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
-    const EntL* E = A.entl + B.s0;
-    for (uint64_t g = tid % GAP_GROUP; g < ns; g += GAP_GROUP) {
-      int64_t p0 = 0;
-      uint32_t lo = 0;
-      if (g > 0) {
-        // gap chunk g - 1: after the interior of the last entry with fewer
-        // gap chunks before its interior (ia - cum) than g
-        const uint64_t gq = g - 1;
-        uint64_t m = gq;
-        if ((uint64_t)(E[0].ia - E[0].cum) <= gq) {
-          uint32_t hi = B.cnt;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((uint64_t)(E[mid].ia - E[mid].cum) <= gq) lo = mid;
-            else hi = mid;
-          }
-          m = gq + E[lo].cum + E[lo].pieces;
-        }
-        p0 = 16 * (int64_t)m - (int64_t)gshift;
+    if (B.cnt <= GAP_GROUP) {
+      if (j < B.cnt) {
+        const EntL e = A.entl[B.s0 + j];
+        GapEnt x;
+        x.r = A.rec[B.s0 + j];
+        x.st = A.ent_off[B.s0 + j];
+        x.ia = e.ia;
+        x.pieces = e.pieces;
+        x.cum = e.cum;
+        L[j] = x;
       }
-      A.gapbuf[g0 + g] = enc_bytes(A, B, p0, lo);
+      wave_sync();
+      const EntsLds X{L};
+      for (uint64_t g = j; g < ns; g += GAP_GROUP) gap_slot(A, B, X, g0, g);
+      wave_sync();
+    } else {
+      const EntsGlobal X{&A, B.s0};
+      for (uint64_t g = j; g < ns; g += GAP_GROUP) gap_slot(A, B, X, g0, g);
     }
   }
 }
