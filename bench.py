@@ -64,6 +64,32 @@ def fingerprint(t) -> int:
     return int(((w ^ (w >> 29)) * (mult | 1)).sum().item()) ^ n
 
 
+# rocprofv3 byte counters of a kernel are valid only for the sources they
+# were taken on: profiles/ records them with a hash of those sources
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_plain_large_11x64MiB.md")
+TRAFFIC_SOURCES = ["k_encode.hip", "dev_common.h", "kernels.h", "luda_internal.h", "crc_multi.h"]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it is missing or the kernel's sources changed since."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic %s bytes_per_launch=(\d+) sources_sha256=([0-9a-f]+)$" % re.escape(kernel), text, re.M)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2004_03054_amd", "csrc")
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return float(m.group(1)) if h.hexdigest() == m.group(2) else None
+
+
 def kernel_times(ctx):
     """Device time of each timed kernel in the last call (launches of the same
     kernel, e.g. merge rounds, summed)."""
@@ -161,7 +187,7 @@ def main():
     dom = max(alg, key=lambda k: kavg.get(k, 0.0))
     achieved = alg[dom] / (kavg[dom] * 1e-3) / 1e9 if kavg.get(dom) else 0.0
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                 "alg_bytes_per_launch": alg[dom], "avg_ms": round(kavg[dom], 4)}
     other = {k: {"avg_ms": round(kavg.get(k, 0.0), 4),
                  "gbps": round(alg[k] / (kavg[k] * 1e-3) / 1e9, 1) if kavg.get(k) else None}

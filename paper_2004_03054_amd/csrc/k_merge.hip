@@ -81,9 +81,11 @@ __device__ inline uint32_t find_job(const uint64_t* starts, uint32_t J, uint64_t
   return lo;
 }
 
-__global__ void k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, const JobDesc* jobs,
-                              const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
-                              unsigned long long* shadowed, unsigned long long* tomb, const uint32_t* active) {
+__global__ void __launch_bounds__(1024) k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, const JobDesc* jobs,
+                                                     const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
+                                                     unsigned long long* shadowed, unsigned long long* tomb,
+                                                     const uint32_t* active) {
+  if ((uint64_t)blockIdx.x * blockDim.x >= n) return;  // the whole workgroup
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < n;
   uint32_t j = 0;
@@ -101,15 +103,28 @@ __global__ void k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, cons
       keep[p] = (first && !drop_del) ? 1u : 0u;
     }
   }
-  // counts: one atomic per wave when the whole wave is in one job
-  const uint32_t j0 = __shfl(j, 0, WAVE);
-  const bool uniform = wave_ballot(live && j != j0) == 0;
-  if (uniform) {
+  // counts: one global atomic per workgroup when the whole workgroup is in
+  // one job (atomics on one address serialise), per thread otherwise
+  __shared__ unsigned long long s_sh, s_td;
+  if (threadIdx.x == 0) {
+    s_sh = 0;
+    s_td = 0;
+  }
+  const uint64_t p0 = (uint64_t)blockIdx.x * blockDim.x;
+  const uint64_t plast = min(p0 + blockDim.x, n) - 1;  // p0 < n: grid sized to n
+  const uint32_t ja = find_job(job_e0, J, p0), jb = find_job(job_e0, J, plast);
+  __syncthreads();
+  if (ja == jb) {
     const uint32_t ns = (uint32_t)__popcll(wave_ballot(shadow));
     const uint32_t nd = (uint32_t)__popcll(wave_ballot(drop_del));
     if (lane_id() == 0) {
-      if (ns) atomicAdd(&shadowed[j0], (unsigned long long)ns);
-      if (nd) atomicAdd(&tomb[j0], (unsigned long long)nd);
+      if (ns) atomicAdd(&s_sh, (unsigned long long)ns);
+      if (nd) atomicAdd(&s_td, (unsigned long long)nd);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (s_sh) atomicAdd(&shadowed[ja], s_sh);
+      if (s_td) atomicAdd(&tomb[ja], s_td);
     }
   } else {
     if (shadow) atomicAdd(&shadowed[j], 1ull);

@@ -98,7 +98,7 @@ __global__ void k_scatter(const uint32_t* ord, const uint32_t* keep, const uint3
 // bounds it): out[0..n) and out[n] = total.  scratch holds cap/2048 + 2.
 // Input values of type TI are summed as T.  Up to SCAN_ONE_MAX elements one
 // workgroup does it in one launch.
-constexpr uint64_t SCAN_ONE_MAX = 16384;
+constexpr uint64_t SCAN_ONE_MAX = 4096;
 template <typename TI, typename T>
 void launch_scan(const TI* in, uint64_t cap, const uint64_t* n_dev, T* out, T* scratch, hipStream_t st);
 constexpr uint32_t MERGE_ITEMS_PER_THREAD = 8;

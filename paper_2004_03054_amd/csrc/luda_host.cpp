@@ -1180,7 +1180,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   uint32_t* surv = dbuf<uint32_t>(c, "surv", N);
   uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", J + 1);
   if (N) {
-    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N)), dim3(256), 0, st, ord, tu, kw8, d_jobs, job_e0d, J, N, keep,
+    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N, 1024)), dim3(1024), 0, st, ord, tu, kw8, d_jobs, job_e0d, J, N, keep,
                        shadowed, tomb, d_active);
     LAUNCH_CHECK();
   }
