@@ -284,6 +284,7 @@ __global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev
 template <int KIND, int MODE>
 __global__ void __launch_bounds__(256) k_walk(WalkArgs A) {
   const uint64_t ni = *A.ni_dev;
+  uint32_t maxk_all = 0;  // longest key this thread saw (count pass over data blocks)
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t b = A.iblk[i];
     const uint32_t k = (uint32_t)(i - A.ibase[b]);
@@ -384,7 +385,11 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs A) {
       }
     }
     if (MODE == 0) A.icnt[i] = cnt;
-    if (KIND == 1 && MODE == 0 && maxk) atomicMax(A.maxklen, maxk);
+    maxk_all = max(maxk_all, maxk);
+  }
+  if (KIND == 1 && MODE == 0) {
+    maxk_all = wave_max(maxk_all);
+    if (lane_id() == 0 && maxk_all) atomicMax(A.maxklen, maxk_all);
   }
 }
 
