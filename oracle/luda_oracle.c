@@ -596,8 +596,10 @@ static int pack_view(const view_t *in, const ref_options *opt, ref_result *res) 
 
 static int check_options(const ref_options *opt) {
   if (!opt || opt->block_size < 1 || opt->restart_interval < 1 || opt->bloom_bits_per_key < 1 ||
-      opt->target_file_size < 1)
+      opt->target_file_size < 1 || opt->reserved != 0 || (opt->n_snapshots && !opt->snapshots))
     return REF_INVALID_ARG;
+  for (uint32_t i = 0; i < opt->n_snapshots; i++)
+    if (opt->snapshots[i] >> 56 || (i && opt->snapshots[i] <= opt->snapshots[i - 1])) return REF_INVALID_ARG;
   return REF_OK;
 }
 
@@ -924,9 +926,27 @@ int ref_decode_table(const uint8_t *sst, uint64_t size, uint32_t input_index, re
 /* Phase 2 "(Delete and) Sort" (Sec. II-A): merge and sort all restored
  * entries in key order and drop stale ones.  Order: user key ascending, tag
  * descending, then (input index, position) ascending, which is the decoded
- * index since inputs are decoded in order.  The first entry of each user key
- * is its newest version; every later one is shadowed.  A surviving deletion
- * is dropped only when the output is the bottom level. */
+ * index since inputs are decoded in order.
+ *
+ * Which versions are stale (the paper names the rule, Sec. II-A, without
+ * snapshots; live snapshots are the reading written out here).  A reader at
+ * snapshot s sees, for each user key, its newest version with sequence <= s;
+ * a reader of the current state sees the newest version.  A version is kept
+ * iff some such reader sees it: the newest version of its key, and every
+ * version v for which a snapshot s lies in [seq(v), seq(newer)), newer being
+ * the next newer version of the key.  Every other version is shadowed.  At
+ * the bottom level a kept deletion is dropped too when no kept value of its
+ * key is older than it (no reader can then tell it from absence).  With no
+ * snapshots this is: the newest version survives, and a surviving deletion
+ * is dropped at the bottom level. */
+
+/* snapshots below sequence q: two versions are seen by the same readers iff
+ * this count is equal for both */
+static uint32_t stripe_of(const ref_options *opt, uint64_t q) {
+  uint32_t k = 0;
+  while (k < opt->n_snapshots && opt->snapshots[k] < q) k++;
+  return k;
+}
 
 typedef struct {
   const dec_t *d;
@@ -985,25 +1005,46 @@ int ref_compact(const uint8_t *const *inputs, const uint64_t *sizes, uint32_t n_
   sort_ctx sc = {&d};
   qsort_r(order, n, sizeof(uint64_t), cmp_decoded, &sc);
 
+  /* one user key at a time: versions [g0, g1) of order, newest first */
   uint64_t m = 0, shadowed = 0, tomb = 0;
-  for (uint64_t j = 0; j < n; j++) {
-    uint64_t a = order[j];
-    int first = 1;
-    if (j > 0) {
-      uint64_t b = order[j - 1];
-      first = cmp_user(d.keys.p + d.koff.p[a], d.koff.p[a + 1] - d.koff.p[a],
-                       d.keys.p + d.koff.p[b], d.koff.p[b + 1] - d.koff.p[b]) != 0;
-    }
-    if (!first) {
-      shadowed++;
-      continue;
-    }
-    if (opt->bottommost && (d.tags.p[a] & 0xFF) == 0) {
-      tomb++;
-      continue;
-    }
-    surv[m++] = a;
+  uint8_t *keep = (uint8_t *)malloc(n + 1);
+  if (!keep) {
+    free(order), free(surv), free(r);
+    dec_free(&d);
+    err->status = REF_NOMEM;
+    return REF_NOMEM;
   }
+  for (uint64_t g0 = 0, g1; g0 < n; g0 = g1) {
+    const uint64_t a0 = order[g0];
+    for (g1 = g0 + 1; g1 < n; g1++) {
+      const uint64_t b = order[g1];
+      if (cmp_user(d.keys.p + d.koff.p[a0], d.koff.p[a0 + 1] - d.koff.p[a0], d.keys.p + d.koff.p[b],
+                   d.koff.p[b + 1] - d.koff.p[b]) != 0)
+        break;
+    }
+    for (uint64_t j = g0; j < g1; j++) {
+      const uint64_t seq = d.tags.p[order[j]] >> 8;
+      keep[j] = j == g0 || stripe_of(opt, seq) != stripe_of(opt, d.tags.p[order[j - 1]] >> 8);
+      if (!keep[j]) shadowed++;
+    }
+    if (opt->bottommost) {
+      int older_value = 0; /* a kept value older than the version at hand */
+      for (uint64_t j = g1; j-- > g0;) {
+        if (!keep[j]) continue;
+        if ((d.tags.p[order[j]] & 0xFF) == 0) {
+          if (!older_value) {
+            keep[j] = 0;
+            tomb++;
+          }
+        } else {
+          older_value = 1;
+        }
+      }
+    }
+    for (uint64_t j = g0; j < g1; j++)
+      if (keep[j]) surv[m++] = order[j];
+  }
+  free(keep);
 
   view_t v;
   v.n = m;

@@ -46,8 +46,11 @@ typedef struct {
   uint32_t block_size;         /* data block target bytes */
   uint32_t restart_interval;   /* entries between restart points (>= 1) */
   uint32_t bloom_bits_per_key; /* Bloom filter bits per key (>= 1) */
-  uint32_t bottommost;         /* 1: drop deletions that survive dedup */
+  uint32_t bottommost;         /* 1: drop deletions that no kept value lies under */
   uint64_t target_file_size;   /* output file cut threshold (>= 1) */
+  const uint64_t *snapshots;   /* live snapshot sequence numbers, strictly ascending, < 2^56 */
+  uint32_t n_snapshots;        /* 0: no snapshots */
+  uint32_t reserved;           /* 0 */
 } ref_options;
 
 typedef struct {

@@ -32,7 +32,8 @@ def build(force: bool = True) -> str:
 class _Options(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("restart_interval", C.c_uint32),
                 ("bloom_bits_per_key", C.c_uint32), ("bottommost", C.c_uint32),
-                ("target_file_size", C.c_uint64)]
+                ("target_file_size", C.c_uint64), ("snapshots", C.POINTER(C.c_uint64)),
+                ("n_snapshots", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _Error(C.Structure):
@@ -176,8 +177,15 @@ def bloom_may_match(filt: bytes, key: bytes) -> bool:
 
 
 def _opts(o: dict) -> _Options:
-    return _Options(int(o["block_size"]), int(o["restart_interval"]), int(o["bloom_bits_per_key"]),
-                    int(o["bottommost"]), int(o["target_file_size"]))
+    """Options for the C oracle; o["snapshots"] (optional) lists the live
+    snapshot sequence numbers in ascending order."""
+    snaps = [int(x) for x in o.get("snapshots", ())]
+    arr = (C.c_uint64 * max(1, len(snaps)))(*snaps)
+    r = _Options(int(o["block_size"]), int(o["restart_interval"]), int(o["bloom_bits_per_key"]),
+                 int(o["bottommost"]), int(o["target_file_size"]), C.cast(arr, C.POINTER(C.c_uint64)),
+                 len(snaps), 0)
+    r._keep = arr  # the array lives as long as the options
+    return r
 
 
 @dataclass
