@@ -23,9 +23,17 @@
  *     (entry bytes + 4 * restart points + 4) >= block_size;
  *   - a table is finished right after the block that makes its data bytes
  *     (blocks + 5-byte trailers) >= target_file_size.
- * Drop rule (no snapshots): the newest version of each user key survives
- * (largest tag; equal tags: the earlier input, then the earlier position);
- * a surviving deletion is dropped only when `bottommost` is set.
+ * Drop rule (the stale versions of paper Sec. II-A; live snapshots are a
+ * reading of it).  Versions of a user key are ordered newest first (largest
+ * tag; equal tags: the earlier input, then the earlier position).  A reader
+ * at snapshot s sees the newest version with sequence number <= s, a reader
+ * of the current state the newest version.  A version survives iff some
+ * such reader sees it: the newest version, and each version v with a
+ * snapshot in [seq(v), seq(next newer version)).  When `bottommost` is set,
+ * a surviving deletion is dropped too unless a surviving value of its key is
+ * older than it.  With no snapshots: the newest version of each user key
+ * survives, and a surviving deletion is dropped only when `bottommost` is
+ * set.
  *
  * Threading: a context is used by one thread at a time.  Errors are returned
  * as status codes; no exception crosses this interface.
@@ -68,7 +76,13 @@ typedef struct {
   uint32_t bloom_bits_per_key; /* Bloom filter bits per key (> 0), e.g. 10 */
   uint32_t bottommost;         /* 1: the output level is the last level */
   uint64_t target_file_size;   /* output table cut threshold in bytes (> 0) */
+  const uint64_t *snapshots;   /* live snapshot sequence numbers, strictly ascending, each < 2^56, in host
+                                  memory (for every entry point); copied during the call (by
+                                  luda_server_submit: before it returns); NULL when n_snapshots is 0 */
+  uint32_t n_snapshots;        /* at most LUDA_MAX_SNAPSHOTS; 0: no snapshots */
+  uint32_t reserved;           /* must be 0 */
 } luda_options;
+#define LUDA_MAX_SNAPSHOTS 65536
 
 /* The first corruption in reading order: inputs in order; inside an input the
  * footer, the index block, then data blocks in index order; inside a block

@@ -27,7 +27,8 @@ class LudaBuf(C.Structure):
 class LudaOptions(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("restart_interval", C.c_uint32),
                 ("bloom_bits_per_key", C.c_uint32), ("bottommost", C.c_uint32),
-                ("target_file_size", C.c_uint64)]
+                ("target_file_size", C.c_uint64), ("snapshots", C.POINTER(C.c_uint64)),
+                ("n_snapshots", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class LudaError(C.Structure):
@@ -129,8 +130,15 @@ def lib():
 
 
 def options(d: dict) -> LudaOptions:
-    return LudaOptions(int(d["block_size"]), int(d["restart_interval"]), int(d["bloom_bits_per_key"]),
-                       int(d["bottommost"]), int(d["target_file_size"]))
+    """C options from a dict; d["snapshots"] (optional) lists live snapshot
+    sequence numbers in ascending order."""
+    snaps = [int(x) for x in d.get("snapshots", ())]
+    arr = (C.c_uint64 * max(1, len(snaps)))(*snaps)
+    o = LudaOptions(int(d["block_size"]), int(d["restart_interval"]), int(d["bloom_bits_per_key"]),
+                    int(d["bottommost"]), int(d["target_file_size"]),
+                    C.cast(arr, C.POINTER(C.c_uint64)) if snaps else None, len(snaps), 0)
+    o._keep = arr  # the array lives as long as the options
+    return o
 
 
 @dataclass
@@ -298,7 +306,9 @@ class Context:
             keep.append(bufs)
             cjobs[j].inputs = C.cast(bufs, C.POINTER(LudaBuf))
             cjobs[j].n_inputs = len(inputs)
-            cjobs[j].options = options(opts)
+            o = options(opts)
+            keep.append(o)  # its snapshot array must outlive the call
+            cjobs[j].options = o
         res = (LudaResult * max(1, J))()
         rc = lib().luda_compact_batch(self._h, cjobs, J, 1 if device_inputs else 0, res)
         out = [_take(self._h, res[j], device=device_inputs, materialize=materialize) for j in range(J)]
@@ -321,7 +331,9 @@ class Context:
             keep.append(bufs)
             cjobs[j].inputs = C.cast(bufs, C.POINTER(LudaBuf))
             cjobs[j].n_inputs = len(inputs)
-            cjobs[j].options = options(opts)
+            o = options(opts)
+            keep.append(o)  # its snapshot array must outlive the call
+            cjobs[j].options = o
         return cjobs, keep
 
     def params(self) -> dict:
@@ -400,7 +412,8 @@ class Server:
         job = LudaJob()
         job.inputs = C.cast(bufs, C.POINTER(LudaBuf))
         job.n_inputs = len(inputs)
-        job.options = options(opts)
+        o = options(opts)  # its snapshot array is copied by the submit
+        job.options = o
         t = C.c_uint64()
         rc = lib().luda_server_submit(self._h, C.byref(job), C.byref(t))
         if rc != 0:

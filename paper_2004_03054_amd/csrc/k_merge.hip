@@ -81,10 +81,28 @@ __device__ inline uint32_t find_job(const uint64_t* starts, uint32_t J, uint64_t
   return lo;
 }
 
+// live snapshots below sequence number q (lower bound in an ascending list):
+// two versions are seen by the same snapshot readers iff it is equal for both
+__device__ inline uint32_t snap_stripe(const uint64_t* s, uint32_t n, uint64_t q) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s[mid] < q) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Drop rule, per sorted position p (versions of a user key are adjacent,
+// newest first).  A version is kept iff a reader sees it: it is the newest
+// of its key, or a live snapshot lies between it and the next newer version
+// (different stripes).  At the bottom level a kept deletion is dropped too
+// unless a kept value of its key is older.  With no snapshots: the newest
+// version is kept, and a kept deletion is dropped at the bottom level.
 __global__ void __launch_bounds__(1024) k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, const JobDesc* jobs,
-                                                     const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
-                                                     unsigned long long* shadowed, unsigned long long* tomb,
-                                                     const uint32_t* active) {
+                                                     const uint64_t* snaps, const uint64_t* job_e0, uint32_t J,
+                                                     uint64_t n, uint32_t* keep, unsigned long long* shadowed,
+                                                     unsigned long long* tomb, const uint32_t* active) {
   if ((uint64_t)blockIdx.x * blockDim.x >= n) return;  // the whole workgroup
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < n;
@@ -96,11 +114,35 @@ __global__ void __launch_bounds__(1024) k_dedup_flags(const uint32_t* ord, Tuple
       keep[p] = 0;
     } else {
       const uint32_t e = ord[p];
+      const JobDesc jd = jobs[j];
       const bool first = (p == job_e0[j]) || !same_user_key(tu, kw8, ord[p - 1], e);
       const bool del = (tu.tag[e] & 0xFF) == 0;
-      drop_del = first && jobs[j].bottommost && del;
-      shadow = !first;
-      keep[p] = (first && !drop_del) ? 1u : 0u;
+      bool kept = first;
+      if (jd.n_snap) {
+        const uint64_t* S = snaps + jd.snap_first;
+        const uint32_t se = snap_stripe(S, jd.n_snap, tu.tag[e] >> 8);
+        kept = first || se != snap_stripe(S, jd.n_snap, tu.tag[ord[p - 1]] >> 8);
+        if (kept && del && jd.bottommost) {
+          // the older versions of the key, newest first: is one a kept value?
+          bool older_value = false;
+          uint32_t sprev = se;
+          for (uint64_t q = p + 1; q < job_e0[j + 1]; q++) {
+            const uint32_t f = ord[q];
+            if (!same_user_key(tu, kw8, ord[q - 1], f)) break;
+            const uint32_t sq = snap_stripe(S, jd.n_snap, tu.tag[f] >> 8);
+            if (sq != sprev && (tu.tag[f] & 0xFF) != 0) {
+              older_value = true;
+              break;
+            }
+            sprev = sq;
+          }
+          drop_del = !older_value;
+        }
+      } else {
+        drop_del = first && jd.bottommost && del;
+      }
+      shadow = !kept;
+      keep[p] = (kept && !drop_del) ? 1u : 0u;
     }
   }
   // counts: one global atomic per workgroup when the whole workgroup is in

@@ -90,7 +90,7 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, uint64_t
 __global__ void k_merge(const MergeTask* tasks, uint32_t ntasks, const uint32_t* src, uint32_t* dst, Tuples tu,
                         uint32_t kw8, uint64_t total);
 __global__ void k_dedup_flags(const uint32_t* ord, Tuples tu, uint32_t kw8, const JobDesc* jobs,
-                              const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
+                              const uint64_t* snaps, const uint64_t* job_e0, uint32_t J, uint64_t n, uint32_t* keep,
                               unsigned long long* shadowed, unsigned long long* tomb, const uint32_t* active);
 __global__ void k_scatter(const uint32_t* ord, const uint32_t* keep, const uint32_t* pos, uint64_t n,
                           uint32_t* surv);

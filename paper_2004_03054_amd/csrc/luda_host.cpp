@@ -372,8 +372,11 @@ luda_error decode_err(uint64_t key, const std::vector<uint64_t>& in_size, uint32
 
 int check_opt(const luda_options* o) {
   if (!o || o->block_size == 0 || o->restart_interval == 0 || o->bloom_bits_per_key == 0 ||
-      o->target_file_size == 0)
+      o->target_file_size == 0 || o->reserved != 0 || o->n_snapshots > LUDA_MAX_SNAPSHOTS ||
+      (o->n_snapshots && !o->snapshots))
     return LUDA_INVALID_ARG;
+  for (uint32_t i = 0; i < o->n_snapshots; i++)
+    if ((o->snapshots[i] >> 56) || (i && o->snapshots[i] <= o->snapshots[i - 1])) return LUDA_INVALID_ARG;
   return LUDA_OK;
 }
 
@@ -796,14 +799,18 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   std::vector<JobDesc> jd(J);
   std::vector<uint64_t> in_ptr, in_size, job_in_first(J + 1);
   std::vector<uint32_t> in_job, in_local;
+  std::vector<uint64_t> snaps;  // every job's live snapshots, back to back
   uint64_t G = 0, total_in = 0;
   for (uint32_t j = 0; j < J; j++) {
+    if (snaps.size() + jobs[j].options.n_snapshots > 0xFFFFFFF0ull)
+      throw Fail{LUDA_UNSUPPORTED, "too many snapshots in one call"};
     hj[j].in_first = (uint32_t)G;
     hj[j].n_in = jobs[j].n_inputs;
     job_in_first[j] = G;
     const luda_options& o = jobs[j].options;
     jd[j] = JobDesc{o.block_size, o.restart_interval, o.bloom_bits_per_key, o.bottommost ? 1u : 0u,
-                    o.target_file_size, (uint32_t)G, jobs[j].n_inputs};
+                    o.target_file_size, (uint32_t)G, jobs[j].n_inputs, (uint32_t)snaps.size(), o.n_snapshots};
+    snaps.insert(snaps.end(), o.snapshots, o.snapshots + o.n_snapshots);
     for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
       in_size.push_back(jobs[j].inputs[i].size);
       in_job.push_back(j);
@@ -833,6 +840,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   }
   mark(c, "h2d");
   JobDesc* d_jobs = dbuf<JobDesc>(c, "jobs", J);
+  uint64_t* d_snaps = dbuf<uint64_t>(c, "snapshots", snaps.size());
+  if (!snaps.empty()) up(c, d_snaps, snaps.data(), snaps.size() * 8);
   Inputs in;
   in.n = NG;
   uint64_t* d_in_ptr = dbuf<uint64_t>(c, "in_ptr", NG);
@@ -1180,8 +1189,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   uint32_t* surv = dbuf<uint32_t>(c, "surv", N);
   uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", J + 1);
   if (N) {
-    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N, 1024)), dim3(1024), 0, st, ord, tu, kw8, d_jobs, job_e0d, J, N, keep,
-                       shadowed, tomb, d_active);
+    hipLaunchKernelGGL(k_dedup_flags, dim3(blocks_for(N, 1024)), dim3(1024), 0, st, ord, tu, kw8, d_jobs, d_snaps,
+                       job_e0d, J, N, keep, shadowed, tomb, d_active);
     LAUNCH_CHECK();
   }
   launch_scan<uint32_t, uint32_t>(keep, N, nullptr, kpos, scan32, st);

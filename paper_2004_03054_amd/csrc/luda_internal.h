@@ -37,6 +37,8 @@ struct JobDesc {
   uint64_t target_file_size;
   uint32_t in_first;  // first global input
   uint32_t n_in;
+  uint32_t snap_first;  // the job's live snapshots: [snap_first, snap_first + n_snap) of the call's list
+  uint32_t n_snap;
 };
 
 struct Inputs {

@@ -25,6 +25,7 @@ using Clock = std::chrono::steady_clock;
 
 struct ServedJob {
   std::vector<luda_buf> inputs;
+  std::vector<uint64_t> snapshots;  // the job's copy of its snapshot list
   luda_options opt{};
   uint64_t est = 0;  // admitted bytes
   Clock::time_point t_submit, t_done;
@@ -140,6 +141,11 @@ int luda_server_submit(luda_server* s, const luda_job* job, uint64_t* ticket) {
     bytes += job->inputs[i].size;
   }
   j->opt = job->options;
+  if (j->opt.n_snapshots) {
+    if (!j->opt.snapshots || j->opt.n_snapshots > LUDA_MAX_SNAPSHOTS) return LUDA_INVALID_ARG;
+    j->snapshots.assign(j->opt.snapshots, j->opt.snapshots + j->opt.n_snapshots);
+    j->opt.snapshots = j->snapshots.data();
+  }
   j->est = std::max<uint64_t>(2 * bytes, 1);
   j->t_submit = Clock::now();
   {
