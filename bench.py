@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: bytes copied per launch (MiB)")
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "copy"], default="plain",
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "copy", "coopsort"], default="plain",
                     help="plain: one large compaction (default); batch: many uneven jobs, "
                          "one batched pass vs one call per job; serve: Poisson arrivals through the "
                          "request loop vs plain per-job launches")
@@ -131,6 +131,8 @@ def main():
         return serve_main(args)
     if args.mode == "copy":
         return copy_main(args)
+    if args.mode == "coopsort":
+        return coopsort_main(args)
     import numpy as np
     import torch
     from paper_2004_03054_amd import Context
@@ -357,6 +359,54 @@ def batch_main(args):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def coopsort_main(args):
+    """The paper's cooperative sort against the device merge, on the plain
+    large compaction: the same resident tables compacted with the merge step
+    on the device, then with the entries' keys copied to the host, sorted on
+    host threads and the order copied back.  Reports both step times and the
+    merge stage (HIP events around it), and checks the outputs are the same
+    bytes (device fingerprints)."""
+    os.environ["LUDA_STAGE_TIMES"] = "1"
+    import numpy as np
+    import torch
+    from paper_2004_03054_amd import Context
+    from workload import config1
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    job = config1(scale=args.scale)
+    ctx = Context(0)
+    tables = device_tables(ctx, job)
+    in_bytes = sum(int(t.numel()) for t in tables)
+    opts = job.options()
+    out = {}
+    prints = {}
+    for name, host in (("device_merge", False), ("host_sort", True)):
+        ctx.set_host_sort(host)
+        for _ in range(args.warmup):
+            r = ctx.compact_dev(tables, opts, materialize=False)
+            assert r.status == 0, (r.name, ctx.last_error())
+        steps, merge = [], []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.compact_dev(tables, opts, materialize=False)
+            torch.cuda.synchronize()
+            steps.append((time.perf_counter() - t0) * 1e3)
+            st = dict(ctx.stage_times())
+            merge.append(st.get("merge", float("nan")))
+        r = ctx.compact_dev(tables, opts, materialize=fingerprint)
+        prints[name] = [f for f in r.files]
+        out[name] = {"ms_per_step": round(float(np.median(steps)), 3),
+                     "merge_stage_ms": round(float(np.median(merge)), 3),
+                     "gbps": round(in_bytes / (np.median(steps) * 1e-3) / 1e9, 1)}
+        log(f"[bench] {name}: {out[name]}")
+    ctx.set_host_sort(False)
+    print(json.dumps({"mode": "coopsort", "workload": job.name, "input_bytes": in_bytes,
+                      "entries_in": int(sum(r.n for r in job.runs)), "host_threads": min(16, os.cpu_count() or 1),
+                      "device_merge": out["device_merge"], "host_sort": out["host_sort"],
+                      "outputs_identical": prints["device_merge"] == prints["host_sort"]}), flush=True)
 
 
 def copy_main(args):

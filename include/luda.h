@@ -204,6 +204,15 @@ int luda_set_params(luda_ctx *ctx, const luda_params *p);
 int luda_autotune(luda_ctx *ctx, const luda_job *jobs, uint32_t n_jobs, int device_inputs, uint32_t rounds,
                   luda_params *best, double *best_ms);
 
+/* Cooperative sort (paper Sec. III-D: the decoded tuples go to the CPU,
+ * are sorted there and come back): with on != 0, the merge step of this
+ * context's calls copies every entry's key, tag and key length to host
+ * memory, sorts them on up to 16 host threads and uploads the order; the
+ * outputs are the same bytes as with the device merge (on == 0, the
+ * default).  For measuring the paper's design choice against the device
+ * merge. */
+int luda_set_host_sort(luda_ctx *ctx, int on);
+
 /* Host-side self check of the CRC32C shift tables (no device needed). */
 int luda_selftest_crc(void);
 

@@ -123,6 +123,8 @@ def lib():
     L.luda_server_poll.restype = C.c_int
     L.luda_server_stats.argtypes = [C.c_void_p] + [C.POINTER(C.c_uint64)] * 4
     L.luda_server_stats.restype = C.c_int
+    L.luda_set_host_sort.argtypes = [C.c_void_p, C.c_int]
+    L.luda_set_host_sort.restype = C.c_int
     L.luda_server_destroy.argtypes = [C.c_void_p]
     L.luda_server_destroy.restype = None
     _lib = L
@@ -335,6 +337,13 @@ class Context:
             keep.append(o)  # its snapshot array must outlive the call
             cjobs[j].options = o
         return cjobs, keep
+
+    def set_host_sort(self, on: bool):
+        """Cooperative sort: order the entries on the host instead of merging
+        them on the device (same output bytes)."""
+        rc = lib().luda_set_host_sort(self._h, 1 if on else 0)
+        if rc != 0:
+            raise ValueError(f"luda_set_host_sort: {STATUS.get(rc, rc)}")
 
     def params(self) -> dict:
         p = LudaParams()

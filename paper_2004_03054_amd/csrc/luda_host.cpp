@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "luda.h"
@@ -130,6 +131,7 @@ struct luda_ctx {
   UpSegs up_pending{};
   // stage timing (LUDA_STAGE_TIMES) and hot-kernel timing (always)
   bool timing = false;
+  bool host_sort = false;  // cooperative sort: order the entries on the host (luda_set_host_sort)
   std::vector<std::pair<std::string, hipEvent_t>> marks;
   std::vector<hipEvent_t> event_pool;
   size_t event_used = 0;
@@ -789,6 +791,56 @@ struct WalkPlan {
   uint64_t NI = 0;  // intervals
 };
 
+// The paper's cooperative sort (Sec. III-D): the decoded entries' keys go to
+// the host, are sorted there, and the order comes back.  Same order as the
+// device merge: user key bytes ascending (a shorter key first), tag
+// descending, then decode position (input, then position) ascending.  Jobs
+// that already failed keep their decode order.
+void host_sort_order(luda_ctx* c, const Tuples& tu, uint32_t kw8, uint64_t N, uint32_t J,
+                     const std::vector<HostJob>& hj, const std::vector<uint64_t>& job_e0, uint32_t* d_ord) {
+  hipStream_t st = c->stream;
+  std::vector<uint64_t> heap(N * kw8), tag(N);
+  std::vector<uint32_t> ulen(N), ord(N);
+  HIPCK(hipMemcpyAsync(heap.data(), tu.heap, N * kw8 * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(tag.data(), tu.tag, N * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(ulen.data(), tu.ulen, N * 4, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  const uint8_t* kb = (const uint8_t*)heap.data();
+  const uint64_t slot = (uint64_t)kw8 * 8;
+  auto less = [&](uint32_t a, uint32_t b) {
+    const uint32_t la = std::min<uint64_t>(ulen[a], slot), lb = std::min<uint64_t>(ulen[b], slot);
+    const int cm = memcmp(kb + a * slot, kb + b * slot, std::min(la, lb));
+    if (cm) return cm < 0;
+    if (la != lb) return la < lb;
+    if (tag[a] != tag[b]) return tag[a] > tag[b];
+    return a < b;
+  };
+  for (uint64_t i = 0; i < N; i++) ord[i] = (uint32_t)i;
+  const unsigned T = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  for (uint32_t j = 0; j < J; j++) {
+    if (hj[j].failed) continue;
+    uint32_t* a0 = ord.data() + job_e0[j];
+    const uint64_t n = job_e0[j + 1] - job_e0[j];
+    if (n < 2) continue;
+    // T sorted pieces, then pairwise merges
+    std::vector<uint64_t> cut(T + 1);
+    for (unsigned t = 0; t <= T; t++) cut[t] = n * t / T;
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; t++) th.emplace_back([&, t] { std::sort(a0 + cut[t], a0 + cut[t + 1], less); });
+    for (auto& x : th) x.join();
+    for (unsigned w = 1; w < T; w *= 2) {
+      th.clear();
+      for (unsigned t = 0; t + w < T; t += 2 * w)
+        th.emplace_back([&, t, w] {
+          std::inplace_merge(a0 + cut[t], a0 + cut[t + w], a0 + cut[std::min(T, t + 2 * w)], less);
+        });
+      for (auto& x : th) x.join();
+    }
+  }
+  HIPCK(hipMemcpyAsync(d_ord, ord.data(), N * 4, hipMemcpyHostToDevice, st));
+  HIPCK(hipStreamSynchronize(st));  // ord is freed on return
+}
+
 void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, luda_result* results) {
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
@@ -1123,7 +1175,10 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   }
   uint32_t* ordA = dbuf<uint32_t>(c, "ordA", N);
   uint32_t* ordB = dbuf<uint32_t>(c, "ordB", N);
-  if (N) {
+  if (c->host_sort && N) {
+    host_sort_order(c, tu, kw8, N, J, hj, job_e0, ordA);
+    need_merge = false;
+  } else if (N) {
     hipLaunchKernelGGL(k_iota, dim3(blocks_for(N)), dim3(256), 0, st, ordA, N);
     LAUNCH_CHECK();
   }
@@ -1583,6 +1638,12 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
 static bool params_ok(const luda_params* p) {
   return p && (p->crc_waves == 4 || p->crc_waves == 8 || p->crc_waves == 16) && p->encode_waves >= 2 &&
          p->encode_waves <= 16 && p->stride_blocks >= 1 && p->stride_blocks <= 64;
+}
+
+int luda_set_host_sort(luda_ctx* c, int on) {
+  if (!c) return LUDA_INVALID_ARG;
+  c->host_sort = on != 0;
+  return LUDA_OK;
 }
 
 int luda_get_params(luda_ctx* c, luda_params* p) {

@@ -159,3 +159,24 @@ def test_launch_params_do_not_change_bytes():
         assert_same_files(res.files, ref.files, "autotuned")
     finally:
         c.set_params(**saved)
+
+
+def test_host_sort_gives_the_same_bytes():
+    """The cooperative sort (entries ordered on the host) gives the oracle's
+    bytes, alone and in a batch."""
+    c = ctx()
+    c.set_host_sort(True)
+    try:
+        for seed in range(4):
+            run_both(tiny_job(seed, mode=("l0", "leveled")[seed % 2], bottommost=seed % 2), f"hostsort-tiny-{seed}")
+        run_both(config0(), "hostsort-config0")
+        run_both(config1(scale=1 / 64), "hostsort-config1x1/64")
+        jobs = [tiny_job(20 + s, bottommost=s % 2) for s in range(5)] + [config3_job(3, scale=1 / 64)]
+        ins = [oracle.build_input_tables(j) for j in jobs]
+        out = c.compact_batch([(i, j.options()) for i, j in zip(ins, jobs)], device_inputs=False)
+        for k, (j, i, r) in enumerate(zip(jobs, ins, out)):
+            ref = oracle.compact(i, j.options())
+            assert r.status == 0, (k, r.name)
+            assert_same_files(r.files, ref.files, f"hostsort batch job {k}")
+    finally:
+        c.set_host_sort(False)
