@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve mode: seconds of arrivals")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve mode: HBM budget")
+    ap.add_argument("--resident", action="store_true",
+                    help="serve mode: outputs stay in HBM and half the requests read an earlier request's outputs")
     ap.add_argument("--jobs", type=int, default=256, help="batch mode: number of jobs")
     ap.add_argument("--oracle-jobs", type=int, default=2, help="batch mode: jobs checked against the oracle")
     args = ap.parse_args()
@@ -427,21 +429,33 @@ def copy_main(args):
                       "gbps_read_plus_write": round(2 * n / dt / 1e9, 1)}), flush=True)
 
 
-def run_trace(srv, arrivals, picks, tables, opts, tbytes):
+def run_trace(srv, arrivals, picks, tables, opts, tbytes, sub=None):
     """Submit each request at its arrival time; collect in order.  Returns
-    per-request (latency ms, input bytes, output digest) and the span."""
+    per-request (latency ms, input bytes, output digest) and the span.  With
+    sub, request k whose sub[k] is an earlier request k2 takes k2's output
+    tables (left in HBM by the server) in place of its first lower input; it
+    waits for k2 if k2 is not done yet."""
     import threading
     tickets = [None] * len(arrivals)
     ready = threading.Semaphore(0)
     out = [None] * len(arrivals)
+    files = [None] * len(arrivals)
+    done = [threading.Event() for _ in arrivals]
 
     def collect():
         for k in range(len(arrivals)):
             ready.acquire()
             r, lat = srv.poll(tickets[k])
             assert r.status == 0, (k, r.name)
-            out[k] = (lat, tbytes[picks[k]], hashlib.sha256(b"".join(r.files)).hexdigest(), time.perf_counter())
+            if r.files and not isinstance(r.files[0], (bytes, bytearray)):
+                dig = hashlib.sha256(repr([fingerprint(t) for t in r.files]).encode()).hexdigest()
+                files[k] = r.files  # device tensors, inputs of later requests
+            else:
+                dig = hashlib.sha256(b"".join(r.files)).hexdigest()
+            out[k] = (lat, inb[k], dig, time.perf_counter())
+            done[k].set()
 
+    inb = [0] * len(arrivals)
     th = threading.Thread(target=collect)
     th.start()
     t0 = time.perf_counter()
@@ -449,7 +463,12 @@ def run_trace(srv, arrivals, picks, tables, opts, tbytes):
         d = at - (time.perf_counter() - t0)
         if d > 0:
             time.sleep(d)
-        tickets[k] = srv.submit(tables[j], opts[j])
+        ins = tables[j]
+        if sub is not None and sub[k] is not None:
+            done[sub[k]].wait()
+            ins = [ins[0]] + list(files[sub[k]]) + list(ins[2:])
+        inb[k] = sum(int(t.numel()) for t in ins)
+        tickets[k] = srv.submit(ins, opts[j])
         ready.release()
     th.join()
     span = max(o[3] for o in out) - t0
@@ -460,7 +479,8 @@ def serve_main(args):
     """Poisson arrivals of jobs drawn from the batch workload's job mixture,
     through the request loop (admission under an HBM budget, batched passes
     on two workers) and through plain per-job launches (one job at a time),
-    on the same trace.  Latency = completion (outputs in host memory) minus
+    on the same trace.  Latency = completion (outputs in host memory; in HBM
+    with --resident) minus
     arrival."""
     import numpy as np
     import torch
@@ -482,13 +502,22 @@ def serve_main(args):
     arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n)).tolist()
     picks = rng.integers(0, args.jobs, n).tolist()
     budget = int(args.budget_gib * 2**30)
+    sub = None
+    if args.resident:
+        # with probability 1/2 a request's first lower input is replaced by the
+        # output tables of a request that arrived at least 1 s earlier
+        sub = []
+        for k, at in enumerate(arrivals):
+            early = [q for q in range(k) if arrivals[q] <= at - 1.0]
+            sub.append(int(rng.choice(early)) if early and rng.random() < 0.5 else None)
+        log(f"[bench] {sum(x is not None for x in sub)} of {n} requests read earlier outputs kept in HBM")
     results = {}
     for name, kw in (("served", dict(max_batch_jobs=0, workers=2)), ("plain", dict(max_batch_jobs=1, workers=1))):
-        srv = Server(0, hbm_budget=budget, host_outputs=True, **kw)
+        srv = Server(0, hbm_budget=budget, host_outputs=not args.resident, **kw)
         # warm the workers' buffers on the largest job
         big = int(np.argmax(tbytes))
         srv.poll(srv.submit(tables[big], opts[big]))
-        out, span = run_trace(srv, arrivals, picks, tables, opts, tbytes)
+        out, span = run_trace(srv, arrivals, picks, tables, opts, tbytes, sub)
         st = srv.stats()
         srv.close()
         lat = np.array([o[0] for o in out])
@@ -518,7 +547,8 @@ def serve_main(args):
         "config": {"workload": f"served-poisson{args.rate:g}-pool{args.jobs}" +
                    ("" if args.scale == 1.0 else f"-scale{args.scale:g}"),
                    "rate_per_s": args.rate, "duration_s": args.duration, "hbm_budget_gib": args.budget_gib,
-                   "outputs": "host"},
+                   "outputs": "hbm" if args.resident else "host",
+                   "resident_inputs": bool(args.resident)},
         "served": results["served"],
         "plain_per_job": results["plain"],
         "outputs_identical": bool(same),
