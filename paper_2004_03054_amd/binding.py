@@ -66,7 +66,8 @@ EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compa
            "luda_compact_batch", "luda_build_tables_dev", "luda_result_free", "luda_status_str",
            "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters",
            "luda_server_create", "luda_server_submit", "luda_server_poll", "luda_server_stats",
-           "luda_server_destroy", "luda_get_params", "luda_set_params", "luda_autotune"]
+           "luda_server_destroy", "luda_get_params", "luda_set_params", "luda_autotune", "luda_set_host_sort",
+           "luda_pin_reserve"]
 
 _lib = None
 
@@ -125,6 +126,8 @@ def lib():
     L.luda_server_stats.restype = C.c_int
     L.luda_set_host_sort.argtypes = [C.c_void_p, C.c_int]
     L.luda_set_host_sort.restype = C.c_int
+    L.luda_pin_reserve.argtypes = [C.c_uint64]
+    L.luda_pin_reserve.restype = C.c_uint64
     L.luda_server_destroy.argtypes = [C.c_void_p]
     L.luda_server_destroy.restype = None
     _lib = L
@@ -277,13 +280,14 @@ class Context:
     def last_error(self) -> str:
         return lib().luda_last_error(self._h).decode()
 
-    def compact(self, inputs: Sequence, opts: dict) -> Result:
-        """Host tables in, host tables out."""
+    def compact(self, inputs: Sequence, opts: dict, materialize: bool = True) -> Result:
+        """Host tables in, host tables out.  With materialize=False the
+        output tables are released unread (sizes only)."""
         bufs, _keep = _bufs(inputs)
         o = options(opts)
         r = LudaResult()
         lib().luda_compact(self._h, bufs, len(inputs), C.byref(o), C.byref(r))
-        return _take(self._h, r, device=False)
+        return _take(self._h, r, device=False, materialize=materialize)
 
     def compact_dev(self, inputs: Sequence, opts: dict, materialize: bool = True) -> Result:
         """Device (torch uint8 cuda tensors) tables in, device tensors out.
@@ -399,6 +403,12 @@ class Context:
 
 def selftest_crc() -> int:
     return lib().luda_selftest_crc()
+
+
+def pin_reserve(nbytes: int) -> int:
+    """Pin host memory ahead of time for results in host memory (see
+    luda_pin_reserve); returns the pinned pool's size in bytes."""
+    return int(lib().luda_pin_reserve(int(nbytes)))
 
 
 class Server:

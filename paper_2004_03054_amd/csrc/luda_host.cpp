@@ -10,12 +10,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -388,13 +390,148 @@ int check_opt(const luda_options* o) {
 struct DevBlock {
   void* p = nullptr;
   size_t cap = 0;
-  int refs = 0;
+  std::atomic<int> refs{0};  // results of one pass may be freed from several threads
+  DevBlock(void* p_, size_t cap_, int refs_) : p(p_), cap(cap_), refs(refs_) {}
 };
+
+// Pinned host memory for results in host memory (device-to-host copies at
+// full link speed, no page faults on first touch).  Pinning pages is slow
+// (it costs about as much as the copy), so pinned memory is allocated in
+// segments of PIN_SEG bytes that live until the process ends, up to PIN_CAP
+// bytes in all; a result takes a range of one segment (first fit, freed
+// ranges merge with their neighbours).  A result larger than a segment gets
+// a segment of its own, unpinned again once it is free.  With PIN_CAP in use
+// (results held by the caller), results go to ordinary memory.
+constexpr size_t PIN_SEG = size_t(1) << 30;
+constexpr size_t PIN_CAP = size_t(32) << 30;
+constexpr size_t PIN_ALIGN = 4096;
+
+struct PinSeg {
+  uint8_t* p = nullptr;
+  size_t cap = 0;
+  std::map<size_t, size_t> free;  // offset -> length of the free ranges
+};
+
+struct HostBlock {
+  void* p = nullptr;
+  size_t cap = 0;
+  int refs = 0;
+  PinSeg* seg = nullptr;  // null: ordinary memory
+};
+
+std::mutex pin_mu;
+std::vector<PinSeg*> pin_segs;
+size_t pin_total = 0;
+
+// first fit among the free ranges of the segments (pin_mu held)
+HostBlock* pin_take(size_t n) {
+  for (PinSeg* g : pin_segs)
+    for (auto it = g->free.begin(); it != g->free.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, len = it->second;
+      g->free.erase(it);
+      if (len > n) g->free.emplace(off + n, len - n);
+      return new HostBlock{g->p + off, n, 0, g};
+    }
+  return nullptr;
+}
+
+// a new segment of cap bytes, already counted in pin_total; pinning runs
+// outside the lock, so that other threads keep taking ranges meanwhile
+PinSeg* pin_grow(size_t cap) {
+  void* p = nullptr;
+  if (hipHostMalloc(&p, cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(pin_mu);
+    pin_total -= cap;
+    return nullptr;
+  }
+  return new PinSeg{(uint8_t*)p, cap, {}};
+}
+
+HostBlock* pin_get(size_t n) {
+  n = std::max(PIN_ALIGN, (n + PIN_ALIGN - 1) & ~(PIN_ALIGN - 1));
+  const size_t cap = std::max(PIN_SEG, (n + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1));
+  bool grow = false;
+  {
+    std::lock_guard<std::mutex> lk(pin_mu);
+    if (HostBlock* h = pin_take(n)) return h;
+    if (pin_total + cap <= PIN_CAP) {
+      pin_total += cap;
+      grow = true;
+    }
+  }
+  if (PinSeg* g = grow ? pin_grow(cap) : nullptr) {
+    std::lock_guard<std::mutex> lk(pin_mu);
+    if (cap > n) g->free.emplace(n, cap - n);
+    pin_segs.push_back(g);
+    return new HostBlock{g->p, n, 0, g};
+  }
+  void* p = malloc(n);
+  return p ? new HostBlock{p, n, 0, nullptr} : nullptr;
+}
+
+// grow the pool by whole segments until it holds `bytes` (at most PIN_CAP)
+size_t pin_reserve(size_t bytes) {
+  bytes = std::min(bytes, PIN_CAP);
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> lk(pin_mu);
+      if (pin_total >= bytes || pin_total + PIN_SEG > PIN_CAP) return pin_total;
+      pin_total += PIN_SEG;
+    }
+    PinSeg* g = pin_grow(PIN_SEG);
+    std::lock_guard<std::mutex> lk(pin_mu);
+    if (!g) return pin_total;
+    g->free.emplace(0, PIN_SEG);
+    pin_segs.push_back(g);
+  }
+}
+
+void pin_put(HostBlock* h) {
+  PinSeg* g = h->seg;
+  if (!g) {
+    free(h->p);
+    delete h;
+    return;
+  }
+  std::lock_guard<std::mutex> lk(pin_mu);
+  size_t off = (size_t)((uint8_t*)h->p - g->p), len = h->cap;
+  delete h;
+  auto nx = g->free.lower_bound(off);
+  if (nx != g->free.end() && nx->first == off + len) {  // merge with the next range
+    len += nx->second;
+    nx = g->free.erase(nx);
+  }
+  if (nx != g->free.begin()) {  // and with the previous one
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == off) {
+      off = pv->first;
+      len += pv->second;
+      g->free.erase(pv);
+    }
+  }
+  if (g->cap > PIN_SEG && len == g->cap) {  // an outsize segment, free again
+    (void)hipHostFree(g->p);
+    pin_total -= g->cap;
+    pin_segs.erase(std::find(pin_segs.begin(), pin_segs.end(), g));
+    delete g;
+    return;
+  }
+  g->free.emplace(off, len);
+}
 
 struct ResultInternal {
   DevBlock* dev = nullptr;
-  bool host_data = false;
+  HostBlock* host = nullptr;  // host results: the pinned block they point into
 };
+
+void release_host(ResultInternal* ri) {
+  if (!ri || !ri->host) return;
+  HostBlock* h = ri->host;
+  ri->host = nullptr;
+  if (--h->refs == 0) pin_put(h);
+}
 
 void release_dev(luda_ctx* c, ResultInternal* ri) {
   if (!ri || !ri->dev) return;
@@ -1282,11 +1419,29 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
 
   // --- results
   const bool dev_out = dev_inputs;
-  uint8_t* host_all = nullptr;
-  if (!dev_out && O.total_bytes) {
-    host_all = (uint8_t*)malloc(O.total_bytes);
-    if (!host_all) throw Fail{LUDA_NOMEM, "host output allocation failed"};
-    HIPCK(hipMemcpyAsync(host_all, O.d_out, O.total_bytes, hipMemcpyDeviceToHost, st));
+  // host outputs: each job's tables into a pinned block of its own
+  std::vector<HostBlock*> hblk(J, nullptr);
+  if (!dev_out) {
+    auto drop = [&] {
+      (void)hipStreamSynchronize(st);  // copies already queued end first
+      for (HostBlock*& h : hblk)
+        if (h) pin_put(h), h = nullptr;
+    };
+    for (uint32_t j = 0; j < J; j++) {
+      if (hj[j].failed) continue;
+      const uint64_t b0 = O.file_out[O.job_f0[j]], b1 = O.file_out[O.job_f0[j + 1]];
+      if (b1 == b0) continue;
+      hblk[j] = pin_get(b1 - b0);
+      if (!hblk[j]) {
+        drop();
+        throw Fail{LUDA_NOMEM, "host result allocation failed"};
+      }
+      const hipError_t e = hipMemcpyAsync(hblk[j]->p, O.d_out + b0, b1 - b0, hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) {
+        drop();
+        HIPCK(e);
+      }
+    }
   }
   mark(c, "d2h");
   sync(c);
@@ -1295,7 +1450,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   DevBlock* dblk = nullptr;
   if (dev_out && O.total_bytes) {
     DBuf& b = c->bufs["out_tables"];
-    dblk = new DevBlock{b.p, b.cap, 0};
+    dblk = new DevBlock(b.p, b.cap, 0);
     b = DBuf{};
   }
   for (uint32_t j = 0; j < J; j++) {
@@ -1331,14 +1486,15 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
         ri->dev = dblk;
         dblk->refs++;
       } else {
-        r.data = (uint8_t*)malloc(r.data_size);
-        if (!r.data) throw Fail{LUDA_NOMEM, "host result allocation failed"};
-        memcpy(r.data, host_all + base, r.data_size);
-        ri->host_data = true;
+        r.data = (uint8_t*)hblk[j]->p;
+        ri->host = hblk[j];
+        hblk[j]->refs = 1;
+        hblk[j] = nullptr;
       }
     }
   }
-  free(host_all);
+  for (HostBlock* h : hblk)  // no result kept it
+    if (h) pin_put(h);
   if (dblk && dblk->refs == 0) {  // no result kept it
     c->bufs["out_tables"] = DBuf{dblk->p, dblk->cap};
     delete dblk;
@@ -1348,20 +1504,38 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
 
 }  // namespace
 
-int luda::result_to_host(luda_ctx* c, luda_result* r) {
-  ResultInternal* ri = (ResultInternal*)r->internal;
-  if (!ri || !ri->dev || !r->data_size) return LUDA_OK;
-  uint8_t* h = (uint8_t*)malloc(r->data_size);
-  if (!h) return LUDA_NOMEM;
-  if (hipMemcpyAsync(h, r->data, r->data_size, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    free(h);
-    return LUDA_DEVICE;
+int luda::result_to_host(luda_ctx* c, luda_result* r) { return results_to_host(c, r, 1); }
+
+// One pinned block per result; the copies are queued together and waited
+// for once.
+int luda::results_to_host(luda_ctx* c, luda_result* res, uint32_t n) {
+  std::vector<HostBlock*> hb(n, nullptr);
+  int rc = LUDA_OK;
+  bool any = false;
+  for (uint32_t k = 0; k < n && rc == LUDA_OK; k++) {
+    ResultInternal* ri = (ResultInternal*)res[k].internal;
+    if (!ri || !ri->dev || !res[k].data_size) continue;
+    hb[k] = pin_get(res[k].data_size);
+    if (!hb[k])
+      rc = LUDA_NOMEM;
+    else if (hipMemcpyAsync(hb[k]->p, res[k].data, res[k].data_size, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      rc = LUDA_DEVICE;
+    any = true;
   }
-  release_dev(c, ri);
-  ri->host_data = true;
-  r->data = h;
-  return LUDA_OK;
+  if (any && hipStreamSynchronize(c->stream) != hipSuccess && rc == LUDA_OK) rc = LUDA_DEVICE;
+  for (uint32_t k = 0; k < n; k++) {
+    if (!hb[k]) continue;
+    if (rc != LUDA_OK) {
+      pin_put(hb[k]);
+      continue;
+    }
+    ResultInternal* ri = (ResultInternal*)res[k].internal;
+    release_dev(c, ri);
+    hb[k]->refs = 1;
+    ri->host = hb[k];
+    res[k].data = (uint8_t*)hb[k]->p;
+  }
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1525,7 +1699,7 @@ int luda_compact_dev(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda
 void luda_result_free(luda_ctx* c, luda_result* r) {
   if (!r) return;
   ResultInternal* ri = (ResultInternal*)r->internal;
-  if (ri && ri->host_data) free(r->data);
+  release_host(ri);
   release_dev(c, ri);
   delete ri;
   free(r->files);
@@ -1614,7 +1788,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     out->internal = ri;
     if (nf) {
       DBuf& b = c->bufs["out_tables"];
-      ri->dev = new DevBlock{b.p, b.cap, 1};
+      ri->dev = new DevBlock(b.p, b.cap, 1);
       b = DBuf{};
       out->files = (luda_file*)calloc(nf, sizeof(luda_file));
       for (uint64_t f = 0; f < nf; f++) {
@@ -1645,6 +1819,8 @@ int luda_set_host_sort(luda_ctx* c, int on) {
   c->host_sort = on != 0;
   return LUDA_OK;
 }
+
+uint64_t luda_pin_reserve(uint64_t bytes) { return pin_reserve(bytes); }
 
 int luda_get_params(luda_ctx* c, luda_params* p) {
   if (!c || !p) return LUDA_INVALID_ARG;

@@ -10,4 +10,8 @@ namespace luda {
 // host outputs already.  Returns LUDA_OK, LUDA_NOMEM or LUDA_DEVICE.
 int result_to_host(luda_ctx* c, luda_result* r);
 
+// The same for the n results of one call: results that share one device
+// buffer (one batched pass) come back in one copy into one host block.
+int results_to_host(luda_ctx* c, luda_result* res, uint32_t n);
+
 }  // namespace luda

@@ -41,12 +41,13 @@ struct luda_server {
   std::vector<luda_ctx*> ctxs;
   std::vector<std::thread> threads;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_turn;
   std::deque<uint64_t> pending;
   std::unordered_map<uint64_t, std::unique_ptr<ServedJob>> jobs;
   uint64_t next_ticket = 1;
   uint64_t admitted = 0, peak = 0;
   uint64_t n_done = 0, n_batches = 0, max_batch = 0;
+  uint64_t take_seq = 0, copy_turn = 0;  // host outputs: batches copy out in the order taken
   bool stop = false;
 };
 
@@ -63,7 +64,7 @@ void worker(luda_server* s, luda_ctx* ctx) {
   (void)hipSetDevice(s->device);
   for (;;) {
     std::vector<ServedJob*> batch;
-    uint64_t est = 0;
+    uint64_t est = 0, seq = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] { return s->stop || can_take(s); });
@@ -77,6 +78,11 @@ void worker(luda_server* s, luda_ctx* ctx) {
         s->pending.pop_front();
       }
       s->peak = std::max(s->peak, s->admitted);
+      if (!batch.empty()) {
+        seq = s->take_seq++;
+        s->n_batches++;
+        s->max_batch = std::max<uint64_t>(s->max_batch, batch.size());
+      }
     }
     if (batch.empty()) continue;
     std::vector<luda_job> cj(batch.size());
@@ -87,23 +93,35 @@ void worker(luda_server* s, luda_ctx* ctx) {
       cj[k].options = batch[k]->opt;
     }
     luda_compact_batch(ctx, cj.data(), (uint32_t)cj.size(), 1, res.data());
-    if (s->cfg.host_outputs)
-      for (auto& r : res) luda::result_to_host(ctx, &r);
-    const Clock::time_point now = Clock::now();
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      for (size_t k = 0; k < batch.size(); k++) {
+    // Each job completes when its own outputs are where the caller reads
+    // them: with host outputs, the jobs of a batch complete one by one as
+    // their copies end, not all at the end of the last copy.  The copies of
+    // one batch at a time use the host link, batches in the order they were
+    // taken (first come, first served), while other workers' passes compute.
+    if (s->cfg.host_outputs) {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_turn.wait(lk, [&] { return s->copy_turn == seq; });
+    }
+    for (size_t k = 0; k < batch.size(); k++) {
+      if (s->cfg.host_outputs) luda::result_to_host(ctx, &res[k]);
+      const Clock::time_point now = Clock::now();
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
         batch[k]->res = res[k];
         batch[k]->done = true;
         batch[k]->t_done = now;
+        s->n_done++;
       }
+      if (s->cfg.host_outputs) s->cv_done.notify_all();
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->cfg.host_outputs) s->copy_turn++;
       s->admitted -= est;
-      s->n_done += batch.size();
-      s->n_batches++;
-      s->max_batch = std::max<uint64_t>(s->max_batch, batch.size());
     }
     s->cv_done.notify_all();
     s->cv_work.notify_all();
+    s->cv_turn.notify_all();
   }
 }
 
@@ -126,6 +144,10 @@ int luda_server_create(int device, const luda_server_cfg* cfg, luda_server** out
       return rc;
     }
     s->ctxs.push_back(c);
+  }
+  if (cfg->host_outputs) {
+    (void)hipSetDevice(device);
+    luda_pin_reserve(cfg->hbm_budget / 2);  // admitted jobs' outputs fit in it
   }
   for (luda_ctx* c : s->ctxs) s->threads.emplace_back(worker, s, c);
   *out = s;

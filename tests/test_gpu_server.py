@@ -53,3 +53,12 @@ def test_served_mix_matches_oracle(budget_mib, workers, max_batch):
         assert_same_files(r.files, ref.files, f"served job {k}")
         alone = ctx().compact(i, j.options())
         assert alone.files == r.files, f"served job {k}: alone vs mix"
+
+
+def test_pin_reserve_grows_by_segments():
+    from paper_2004_03054_amd import pin_reserve
+    before = pin_reserve(0)
+    after = pin_reserve(before + (1 << 30))
+    say(f"[gpu] pinned pool {before >> 20} -> {after >> 20} MiB")
+    assert after >= before + (1 << 30) and after % (1 << 30) == 0
+    assert pin_reserve(0) == after  # kept until the process ends
