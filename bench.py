@@ -135,6 +135,9 @@ def main():
                     help="serve mode: most jobs in one pass of the request loop (0: no limit); default 1 with "
                          "outputs copied to host memory (the host link bounds the rate, and a larger pass only "
                          "delays its first copy), 16 with outputs kept in HBM")
+    ap.add_argument("--keep-s", type=float, default=3.0,
+                    help="serve --resident: outputs of requests that arrived up to this many seconds earlier "
+                         "stay in HBM as inputs of later requests")
     ap.add_argument("--resident", action="store_true",
                     help="serve mode: outputs stay in HBM and half the requests read an earlier request's outputs")
     ap.add_argument("--jobs", type=int, default=256, help="batch mode: number of jobs")
@@ -448,12 +451,14 @@ def copy_main(args):
                       "gbps_read_plus_write": round(2 * n / dt / 1e9, 1)}), flush=True)
 
 
-def run_trace(srv, arrivals, picks, tables, opts, tbytes, sub=None):
+def run_trace(srv, arrivals, picks, tables, opts, tbytes, sub=None, keep_s=3.0):
     """Submit each request at its arrival time; collect in order.  Returns
-    per-request (latency ms, input bytes, output digest) and the span.  With
+    per-request (latency ms from the arrival time, input bytes, output
+    digest) and the span.  With
     sub, request k whose sub[k] is an earlier request k2 takes k2's output
     tables (left in HBM by the server) in place of its first lower input; it
-    waits for k2 if k2 is not done yet."""
+    waits for k2 if k2 is not done yet.  Outputs of requests that arrived more
+    than keep_s seconds before the current one are dropped."""
     import threading
     tickets = [None] * len(arrivals)
     ready = threading.Semaphore(0)
@@ -461,46 +466,68 @@ def run_trace(srv, arrivals, picks, tables, opts, tbytes, sub=None):
     files = [None] * len(arrivals)
     done = [threading.Event() for _ in arrivals]
 
+    failed = []
+
     def collect():
+        try:
+            collect_all()
+        except BaseException as e:  # noqa: BLE001 - handed to the submitting thread
+            failed.append(e)
+            for ev in done:
+                ev.set()
+            for _ in range(len(arrivals)):
+                ready.release()
+
+    def collect_all():
         for k in range(len(arrivals)):
             ready.acquire()
-            # host outputs: every 32nd request's bytes are fingerprinted (the
-            # binding's copy of every result into Python objects would not
-            # keep up with the GPU); the others are released unread
-            r, lat = srv.poll(tickets[k], materialize=sub is not None or k % 32 == 0)
-            assert r.status == 0, (k, r.name)
-            if r.files and r.files[0] is None:
-                dig = repr(r.file_sizes)
-            elif r.files and not isinstance(r.files[0], (bytes, bytearray)):
-                dig = repr([fingerprint(t) for t in r.files])
-                files[k] = r.files  # device tensors, inputs of later requests
-            else:
-                dig = repr([host_fingerprint(f) for f in r.files])
-            out[k] = (lat, inb[k], dig, time.perf_counter())
+            # every 32nd request's outputs are fingerprinted, in place before
+            # the library frees them (fingerprinting every result in Python
+            # would not keep up with the GPU, and its pauses would delay the
+            # submitting thread); the others are compared by file sizes
+            sample = k % 32 == 0
+            if sub is None:  # host outputs
+                r, lat = srv.poll(tickets[k], materialize=host_fingerprint if sample else False)
+                assert r.status == 0, (k, r.name)
+                dig = repr(r.files) if sample else repr(r.file_sizes)
+            else:  # device outputs, kept as inputs of later requests
+                r, lat = srv.poll(tickets[k])
+                assert r.status == 0, (k, r.name)
+                files[k] = r.files
+                dig = repr([fingerprint(t) for t in r.files]) if sample else repr(r.file_sizes)
+            out[k] = (lat + lag[k], inb[k], dig, time.perf_counter())
             done[k].set()
             if (k + 1) % 250 == 0:
                 log(f"[bench] {k + 1} of {len(arrivals)} requests done")
 
     inb = [0] * len(arrivals)
-    th = threading.Thread(target=collect)
+    lag = [0.0] * len(arrivals)
+    th = threading.Thread(target=collect, daemon=True)
     th.start()
     t0 = time.perf_counter()
     for k, (at, j) in enumerate(zip(arrivals, picks)):
+        if failed:
+            break
         d = at - (time.perf_counter() - t0)
         if d > 0:
             time.sleep(d)
         ins = tables[j]
         if sub is not None and sub[k] is not None:
             done[sub[k]].wait()
+            if failed:
+                break
             ins = [ins[0]] + list(files[sub[k]]) + list(ins[2:])
         if sub is not None:  # outputs no later request can read
             for q in range(k):
-                if arrivals[q] < at - 5.0 and done[q].is_set():
+                if arrivals[q] < at - keep_s and done[q].is_set():
                     files[q] = None
         inb[k] = sum(int(t.numel()) for t in ins)
+        lag[k] = max(0.0, time.perf_counter() - t0 - at) * 1e3  # submitted late by this thread
         tickets[k] = srv.submit(ins, opts[j])
         ready.release()
     th.join()
+    if failed:
+        raise RuntimeError("a served request failed") from failed[0]
     span = max(o[3] for o in out) - t0
     return out, span
 
@@ -539,10 +566,10 @@ def serve_main(args):
         if args.resident:
             # with probability 1/2 a request's first lower input is replaced by the
             # output tables of a request that arrived at least 1 s earlier
-            # (from the last 5 s of arrivals, so that older outputs can be freed)
+            # (from the last --keep-s seconds of arrivals, so that older outputs can be freed)
             sub = []
             for k, at in enumerate(arrivals):
-                early = [q for q in range(k) if at - 5.0 <= arrivals[q] <= at - 1.0]
+                early = [q for q in range(k) if at - args.keep_s <= arrivals[q] <= at - 1.0]
                 sub.append(int(rng.choice(early)) if early and rng.random() < 0.5 else None)
             log(f"[bench] {sum(x is not None for x in sub)} of {n} requests read earlier outputs kept in HBM")
         results = {}
@@ -552,7 +579,7 @@ def serve_main(args):
             # warm the workers' buffers on the largest job
             big = int(np.argmax(tbytes))
             srv.poll(srv.submit(tables[big], opts[big]))
-            out, span = run_trace(srv, arrivals, picks, tables, opts, tbytes, sub)
+            out, span = run_trace(srv, arrivals, picks, tables, opts, tbytes, sub, args.keep_s)
             st = srv.stats()
             srv.close()
             lat = np.array([o[0] for o in out])
@@ -587,7 +614,8 @@ def serve_main(args):
                        "rate_per_s": rate, "duration_s": args.duration, "hbm_budget_gib": args.budget_gib,
                        "max_batch_jobs": args.max_batch, "workers": args.workers,
                        "outputs": "hbm" if args.resident else "host",
-                       "resident_inputs": bool(args.resident)},
+                       "resident_inputs": bool(args.resident),
+                   **({"keep_s": args.keep_s} if args.resident else {})},
             "served": results["served"],
             "plain_per_job": results["plain"],
             "outputs_identical": bool(same),

@@ -162,6 +162,13 @@ int luda_build_tables_dev(luda_ctx *ctx, uint64_t n, const uint8_t *keys, const 
                           const uint64_t *tags, const uint8_t *vals, const uint64_t *voff,
                           const luda_options *opt, luda_result *out);
 
+/* Release a result's tables and file list.  Device outputs go back to the
+ * library's pool of output buffers on their device (reused by later calls
+ * on any context, up to 32 GiB per device; hipFree past that): device work
+ * the caller queued that reads them must have completed before this call
+ * (e.g. its stream synchronized).  Host outputs go back to the pinned pool
+ * (luda_pin_reserve).  ctx may be NULL; thread-safe for distinct results,
+ * also results of one batched pass. */
 void luda_result_free(luda_ctx *ctx, luda_result *r);
 
 const char *luda_status_str(int status);

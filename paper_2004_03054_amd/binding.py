@@ -195,14 +195,20 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
                  dropped_tombstones=r.dropped_tombstones, bytes_in=r.bytes_in, bytes_out=r.bytes_out,
                  ms_total=r.ms_total)
     if r.status == 0 and r.num_files and callable(materialize):
-        # apply a function to each device output table in place (no copy)
-        import torch  # device memory plumbing only
+        # apply a function to each output table in place, before the library
+        # frees it (no copy): a torch uint8 tensor over device outputs, a
+        # numpy uint8 array over host outputs
         for i in range(r.num_files):
             f = r.files[i]
             res.file_entries.append(f.num_entries)
             res.file_sizes.append(f.size)
-            t = (torch.as_tensor(_DevView(r.data + f.offset, f.size), device="cuda") if f.size and device
-                 else torch.empty(0, dtype=torch.uint8, device="cuda"))
+            if device:
+                import torch  # device memory plumbing only
+                t = (torch.as_tensor(_DevView(r.data + f.offset, f.size), device="cuda") if f.size
+                     else torch.empty(0, dtype=torch.uint8, device="cuda"))
+            else:
+                t = (np.ctypeslib.as_array((C.c_uint8 * f.size).from_address(r.data + f.offset)) if f.size
+                     else np.zeros(0, dtype=np.uint8))
             res.files.append(materialize(t))
     elif r.status == 0 and r.num_files and not materialize:
         res.files = [None] * r.num_files
@@ -221,6 +227,11 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
                     res.files.append(torch.empty(0, dtype=torch.uint8, device="cuda"))
             else:
                 res.files.append(C.string_at(r.data + f.offset, f.size))
+    if device and r.status == 0 and r.num_files and materialize:
+        # the copies (or the function's reads) were queued on torch's stream:
+        # they end before the buffer goes back to the library for reuse
+        import torch
+        torch.cuda.current_stream().synchronize()
     lib().luda_result_free(ctx, C.byref(r))
     return res
 
@@ -239,10 +250,13 @@ def _bufs(inputs) -> tuple:
 
 
 def _torch_sync():
-    """Device inputs written on torch's streams must be complete before the
-    library's own stream reads them."""
+    """Device inputs written on torch's current stream must be complete before
+    the library's own (non-blocking) streams read them.  Only that stream is
+    waited for: a device-wide synchronize would also wait for the passes the
+    library's other contexts and server workers have in flight.  Inputs
+    written on other torch streams are the caller's to order."""
     import torch
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
 
 
 def _dev_bufs(inputs) -> LudaBuf:

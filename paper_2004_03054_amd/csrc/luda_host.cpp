@@ -124,7 +124,6 @@ struct luda_ctx {
   size_t lds_limit = 64 * 1024;  // LDS per workgroup
   std::string last_error;
   std::map<std::string, DBuf> bufs;
-  DBuf spare_out;  // an output buffer returned by luda_result_free, for reuse
   // pinned host memory: readbacks (written by k_mail) and staged uploads
   uint8_t* mail = nullptr;
   size_t mail_cap = 0;
@@ -391,8 +390,48 @@ struct DevBlock {
   void* p = nullptr;
   size_t cap = 0;
   std::atomic<int> refs{0};  // results of one pass may be freed from several threads
-  DevBlock(void* p_, size_t cap_, int refs_) : p(p_), cap(cap_), refs(refs_) {}
+  int device = 0;
+  DevBlock(void* p_, size_t cap_, int refs_, int device_) : p(p_), cap(cap_), refs(refs_), device(device_) {}
 };
+
+// Output buffers handed to results come back, when the results are freed, to
+// a pool per device (up to DEV_POOL_CAP bytes each) from which later calls
+// take their output buffers.  hipMalloc and hipFree of buffers of hundreds of
+// MB cost milliseconds, and hipFree waits for the whole device, which would
+// stall the passes of other contexts and server workers.
+constexpr size_t DEV_POOL_CAP = size_t(32) << 30;
+std::mutex dev_pool_mu;
+std::map<int, std::multimap<size_t, void*>> dev_pool;  // device -> (capacity -> buffer)
+std::map<int, size_t> dev_pool_bytes;
+
+// the smallest pooled buffer of at least `bytes` and at most 2x that
+DBuf dev_pool_get(int device, size_t bytes) {
+  std::lock_guard<std::mutex> lk(dev_pool_mu);
+  auto& m = dev_pool[device];
+  auto it = m.lower_bound(bytes);
+  if (it == m.end() || it->first > 2 * bytes + (size_t(64) << 20)) return DBuf{};
+  DBuf b{it->second, it->first};
+  dev_pool_bytes[device] -= it->first;
+  m.erase(it);
+  return b;
+}
+
+void dev_pool_put(int device, DBuf b) {
+  if (!b.p) return;
+  {
+    std::lock_guard<std::mutex> lk(dev_pool_mu);
+    if (dev_pool_bytes[device] + b.cap <= DEV_POOL_CAP) {
+      dev_pool[device].emplace(b.cap, b.p);
+      dev_pool_bytes[device] += b.cap;
+      return;
+    }
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != device) (void)hipSetDevice(device);
+  (void)hipFree(b.p);
+  if (cur != device) (void)hipSetDevice(cur);
+}
 
 // Pinned host memory for results in host memory (device-to-host copies at
 // full link speed, no page faults on first touch).  Pinning pages is slow
@@ -538,24 +577,20 @@ void release_dev(luda_ctx* c, ResultInternal* ri) {
   DevBlock* d = ri->dev;
   ri->dev = nullptr;  // this result no longer holds the buffer, whoever frees it
   if (--d->refs > 0) return;
-  if (c && d->cap > c->spare_out.cap) {
-    if (c->spare_out.p) (void)hipFree(c->spare_out.p);
-    c->spare_out.p = d->p;
-    c->spare_out.cap = d->cap;
-  } else {
-    (void)hipFree(d->p);
-  }
+  (void)c;
+  dev_pool_put(d->device, DBuf{d->p, d->cap});
   delete d;
 }
 
-// the output buffer of this call, at least `bytes`; takes the spare buffer
-// when the current one is too small
+// the output buffer of this call, at least `bytes`: the context's own, else
+// one from the pool (the too small one goes back there), else a new one
 uint8_t* out_buffer(luda_ctx* c, size_t bytes) {
   DBuf& b = c->bufs["out_tables"];
-  if (b.cap < bytes && c->spare_out.cap >= bytes) {
-    if (b.p) HIPCK(hipFree(b.p));
-    b = c->spare_out;
-    c->spare_out = DBuf{};
+  if (b.cap < bytes) {
+    const size_t want = (bytes + 255) & ~size_t(255);
+    DBuf got = dev_pool_get(c->device, want);
+    dev_pool_put(c->device, b);
+    b = got;
   }
   return dbuf<uint8_t>(c, "out_tables", bytes);
 }
@@ -1450,7 +1485,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   DevBlock* dblk = nullptr;
   if (dev_out && O.total_bytes) {
     DBuf& b = c->bufs["out_tables"];
-    dblk = new DevBlock(b.p, b.cap, 0);
+    dblk = new DevBlock(b.p, b.cap, 0, c->device);
     b = DBuf{};
   }
   for (uint32_t j = 0; j < J; j++) {
@@ -1624,8 +1659,10 @@ void luda_ctx_destroy(luda_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
-  if (c->spare_out.p) (void)hipFree(c->spare_out.p);
+    if (kv.first == "out_tables")
+      dev_pool_put(c->device, kv.second);
+    else if (kv.second.p)
+      (void)hipFree(kv.second.p);
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
   for (auto e : c->kevents) (void)hipEventDestroy(e);
   if (c->d_crc) (void)hipFree(c->d_crc);
@@ -1788,7 +1825,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     out->internal = ri;
     if (nf) {
       DBuf& b = c->bufs["out_tables"];
-      ri->dev = new DevBlock(b.p, b.cap, 1);
+      ri->dev = new DevBlock(b.p, b.cap, 1, c->device);
       b = DBuf{};
       out->files = (luda_file*)calloc(nf, sizeof(luda_file));
       for (uint64_t f = 0; f < nf; f++) {

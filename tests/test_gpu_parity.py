@@ -180,3 +180,27 @@ def test_host_sort_gives_the_same_bytes():
             assert_same_files(r.files, ref.files, f"hostsort batch job {k}")
     finally:
         c.set_host_sort(False)
+
+
+def test_in_place_reads_of_host_and_device_outputs():
+    """A function applied to each output table before the library frees it
+    sees the same bytes as the copied-out tables: numpy views of host
+    outputs (several jobs in one pass: one pinned range each), torch views of
+    device outputs."""
+    import numpy as np
+    import torch
+    c = ctx()
+    jobs = [tiny_job(40 + s, bottommost=s % 2) for s in range(3)] + [config0()]
+    ins = [oracle.build_input_tables(j) for j in jobs]
+    for k, (j, i) in enumerate(zip(jobs, ins)):
+        ref = c.compact(i, j.options())
+        view = c.compact(i, j.options(), materialize=lambda a: (type(a), a.tobytes()))
+        assert all(t is np.ndarray for t, _ in view.files), k
+        assert [b for _, b in view.files] == ref.files, f"host view job {k}"
+        dev = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to("cuda") for b in i]
+        dview = c.compact_dev(dev, j.options(), materialize=lambda t: t.cpu().numpy().tobytes())
+        assert dview.files == ref.files, f"device view job {k}"
+    out = c.compact_batch([(i, j.options()) for i, j in zip(ins, jobs)], device_inputs=False,
+                          materialize=lambda a: a.tobytes())
+    for k, (j, i, r) in enumerate(zip(jobs, ins, out)):
+        assert r.files == oracle.compact(i, j.options()).files, f"batched host view job {k}"
