@@ -164,7 +164,8 @@ int luda_build_tables_dev(luda_ctx *ctx, uint64_t n, const uint8_t *keys, const 
 
 /* Release a result's tables and file list.  Device outputs go back to the
  * library's pool of output buffers on their device (reused by later calls
- * on any context, up to 32 GiB per device; hipFree past that): device work
+ * on any context; the pool holds up to half of the device's memory, its
+ * smallest buffers freed first past that; luda_pool_trim): device work
  * the caller queued that reads them must have completed before this call
  * (e.g. its stream synchronized).  Host outputs go back to the pinned pool
  * (luda_pin_reserve).  ctx may be NULL; thread-safe for distinct results,
@@ -231,6 +232,11 @@ int luda_set_host_sort(luda_ctx *ctx, int on);
  * the cap).  Returns the pool's size in bytes afterwards (smaller than asked
  * if the system refused to pin more).  Thread-safe; needs a HIP device. */
 uint64_t luda_pin_reserve(uint64_t bytes);
+
+/* Free the device's pooled output buffers (those of freed results, kept for
+ * reuse; see luda_result_free).  Returns the bytes freed.  Buffers held by
+ * live results and contexts are not touched.  Thread-safe. */
+uint64_t luda_pool_trim(int device);
 
 /* Host-side self check of the CRC32C shift tables (no device needed). */
 int luda_selftest_crc(void);

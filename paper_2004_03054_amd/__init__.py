@@ -5,5 +5,5 @@ this package holds those sources (csrc/), the build script and the ctypes
 binding.
 """
 from .binding import (  # noqa: F401
-    Context, Server, Result, Error, STATUS, EXPORTS, LIB_PATH, lib, selftest_crc, pin_reserve,
+    Context, Server, Result, Error, STATUS, EXPORTS, LIB_PATH, lib, selftest_crc, pin_reserve, pool_trim,
 )

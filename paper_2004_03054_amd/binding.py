@@ -67,7 +67,7 @@ EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compa
            "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters",
            "luda_server_create", "luda_server_submit", "luda_server_poll", "luda_server_stats",
            "luda_server_destroy", "luda_get_params", "luda_set_params", "luda_autotune", "luda_set_host_sort",
-           "luda_pin_reserve"]
+           "luda_pin_reserve", "luda_pool_trim"]
 
 _lib = None
 
@@ -128,6 +128,8 @@ def lib():
     L.luda_set_host_sort.restype = C.c_int
     L.luda_pin_reserve.argtypes = [C.c_uint64]
     L.luda_pin_reserve.restype = C.c_uint64
+    L.luda_pool_trim.argtypes = [C.c_int]
+    L.luda_pool_trim.restype = C.c_uint64
     L.luda_server_destroy.argtypes = [C.c_void_p]
     L.luda_server_destroy.restype = None
     _lib = L
@@ -417,6 +419,12 @@ class Context:
 
 def selftest_crc() -> int:
     return lib().luda_selftest_crc()
+
+
+def pool_trim(device: int = 0) -> int:
+    """Free the device's pooled output buffers (luda_pool_trim); returns the
+    bytes freed."""
+    return int(lib().luda_pool_trim(int(device)))
 
 
 def pin_reserve(nbytes: int) -> int:

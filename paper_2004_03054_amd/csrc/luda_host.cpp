@@ -395,16 +395,26 @@ struct DevBlock {
 };
 
 // Output buffers handed to results come back, when the results are freed, to
-// a pool per device (up to DEV_POOL_CAP bytes each) from which later calls
-// take their output buffers.  hipMalloc and hipFree of buffers of hundreds of
-// MB cost milliseconds, and hipFree waits for the whole device, which would
-// stall the passes of other contexts and server workers.
-constexpr size_t DEV_POOL_CAP = size_t(32) << 30;
+// a pool per device from which later calls take their output buffers.
+// hipMalloc and hipFree of buffers of hundreds of MB or more cost
+// milliseconds to seconds, and hipFree waits for the whole device, which
+// would stall the passes of other contexts and server workers.  The pool
+// holds up to half of the device's memory; past that its smallest buffers are
+// freed first.  luda_pool_trim empties it.
 std::mutex dev_pool_mu;
 std::map<int, std::multimap<size_t, void*>> dev_pool;  // device -> (capacity -> buffer)
 std::map<int, size_t> dev_pool_bytes;
+std::map<int, size_t> dev_pool_cap;
 
-// the smallest pooled buffer of at least `bytes` and at most 2x that
+void free_on(int device, void* p) {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != device) (void)hipSetDevice(device);
+  (void)hipFree(p);
+  if (cur != device) (void)hipSetDevice(cur);
+}
+
+// the smallest pooled buffer of at least `bytes` and at most about 2x that
 DBuf dev_pool_get(int device, size_t bytes) {
   std::lock_guard<std::mutex> lk(dev_pool_mu);
   auto& m = dev_pool[device];
@@ -418,19 +428,43 @@ DBuf dev_pool_get(int device, size_t bytes) {
 
 void dev_pool_put(int device, DBuf b) {
   if (!b.p) return;
+  std::vector<void*> drop;
   {
     std::lock_guard<std::mutex> lk(dev_pool_mu);
-    if (dev_pool_bytes[device] + b.cap <= DEV_POOL_CAP) {
-      dev_pool[device].emplace(b.cap, b.p);
+    size_t& cap = dev_pool_cap[device];
+    if (!cap) {
+      size_t total = 0;
+      cap = hipDeviceTotalMem(&total, device) == hipSuccess && total ? total / 2 : size_t(32) << 30;
+    }
+    if (b.cap > cap) {
+      drop.push_back(b.p);
+    } else {
+      auto& m = dev_pool[device];
+      m.emplace(b.cap, b.p);
       dev_pool_bytes[device] += b.cap;
-      return;
+      while (dev_pool_bytes[device] > cap) {  // the smallest go first
+        drop.push_back(m.begin()->second);
+        dev_pool_bytes[device] -= m.begin()->first;
+        m.erase(m.begin());
+      }
     }
   }
-  int cur = 0;
-  (void)hipGetDevice(&cur);
-  if (cur != device) (void)hipSetDevice(device);
-  (void)hipFree(b.p);
-  if (cur != device) (void)hipSetDevice(cur);
+  for (void* p : drop) free_on(device, p);
+}
+
+size_t dev_pool_trim(int device) {
+  std::multimap<size_t, void*> m;
+  {
+    std::lock_guard<std::mutex> lk(dev_pool_mu);
+    m.swap(dev_pool[device]);
+    dev_pool_bytes[device] = 0;
+  }
+  size_t n = 0;
+  for (auto& kv : m) {
+    free_on(device, kv.second);
+    n += kv.first;
+  }
+  return n;
 }
 
 // Pinned host memory for results in host memory (device-to-host copies at
@@ -1858,6 +1892,8 @@ int luda_set_host_sort(luda_ctx* c, int on) {
 }
 
 uint64_t luda_pin_reserve(uint64_t bytes) { return pin_reserve(bytes); }
+
+uint64_t luda_pool_trim(int device) { return device < 0 ? 0 : dev_pool_trim(device); }
 
 int luda_get_params(luda_ctx* c, luda_params* p) {
   if (!c || !p) return LUDA_INVALID_ARG;

@@ -204,3 +204,23 @@ def test_in_place_reads_of_host_and_device_outputs():
                           materialize=lambda a: a.tobytes())
     for k, (j, i, r) in enumerate(zip(jobs, ins, out)):
         assert r.files == oracle.compact(i, j.options()).files, f"batched host view job {k}"
+
+
+def test_pooled_output_buffers_are_reused_and_trimmed():
+    """Device outputs of freed results go back to the pool: the next call's
+    outputs are the same bytes, and trimming the pool frees them."""
+    import torch
+    from paper_2004_03054_amd import pool_trim
+    c = ctx()
+    j = config0()
+    i = oracle.build_input_tables(j)
+    ref = oracle.compact(i, j.options())
+    dev = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to("cuda") for b in i]
+    for _ in range(3):
+        r = c.compact_dev(dev, j.options())
+        assert [t.cpu().numpy().tobytes() for t in r.files] == ref.files
+    freed = pool_trim(0)
+    say(f"[gpu] pool trim freed {freed} bytes")
+    assert freed > 0 and pool_trim(0) == 0
+    r = c.compact_dev(dev, j.options())
+    assert [t.cpu().numpy().tobytes() for t in r.files] == ref.files
