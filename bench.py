@@ -102,6 +102,20 @@ def host_fingerprint(b: bytes, full: bool = True) -> tuple:
     return len(b), int(v.sum(dtype=np.uint64)), int(v[1::2].sum(dtype=np.uint64)), bytes(b[8 * n:])
 
 
+def host_info() -> dict:
+    """The host the oracle ran on: logical CPUs and CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def kernel_times(ctx):
     """Device time of each timed kernel in the last call (launches of the same
     kernel, e.g. merge rounds, summed)."""
@@ -119,6 +133,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="table size scale (1.0 = 64 MiB tables)")
+    ap.add_argument("--config", type=int, choices=[0, 1, 2], default=1,
+                    help="plain mode: 0 = small (3 x 10k entries), 1 = large (11 x 64 MiB), 2 = variable-size keys "
+                         "and values (7 x 32 MiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: bytes copied per launch (MiB)")
@@ -141,7 +158,11 @@ def main():
     ap.add_argument("--resident", action="store_true",
                     help="serve mode: outputs stay in HBM and half the requests read an earlier request's outputs")
     ap.add_argument("--jobs", type=int, default=256, help="batch mode: number of jobs")
-    ap.add_argument("--oracle-jobs", type=int, default=2, help="batch mode: jobs checked against the oracle")
+    ap.add_argument("--oracle-jobs", type=int, default=0,
+                    help="batch mode: jobs checked against the oracle and timed on the host cores "
+                         "(default: one per oracle thread)")
+    ap.add_argument("--oracle-threads", type=int, default=0,
+                    help="batch mode: host threads running oracle jobs at once (default: the host's cores, at most 16)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (jobs are independent: "
@@ -159,11 +180,11 @@ def main():
     import numpy as np
     import torch
     from paper_2004_03054_amd import Context
-    from workload import config1
+    from workload import config0, config1, config2
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.time()
-    job = config1(scale=args.scale)
+    job = {0: lambda: config0(), 1: lambda: config1(scale=args.scale), 2: lambda: config2(scale=args.scale)}[args.config]()
     log(f"[bench] generated {job.name}: {sum(r.n for r in job.runs)} entries in {time.time() - t0:.1f}s")
     ctx = Context(0)
     tables = device_tables(ctx, job)
@@ -180,8 +201,11 @@ def main():
     ktimes = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    step_s = []
     for _ in range(args.steps):
-        res = ctx.compact_dev(tables, opts, materialize=False)
+        ts = time.perf_counter()
+        res = ctx.compact_dev(tables, opts, materialize=False)  # returns after its stream is done
+        step_s.append(time.perf_counter() - ts)
         ktimes.append(kernel_times(ctx))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t_start
@@ -212,7 +236,9 @@ def main():
     dom = max(alg, key=lambda k: kavg.get(k, 0.0))
     achieved = alg[dom] / (kavg[dom] * 1e-3) / 1e9 if kavg.get(dom) else 0.0
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                # the committed counters were taken on the large workload only
+                "traffic": measured_traffic(dom) if args.config == 1 and args.scale == 1.0 else None,
                 "alg_bytes_per_launch": alg[dom], "avg_ms": round(kavg[dom], 4)}
     other = {k: {"avg_ms": round(kavg.get(k, 0.0), 4),
                  "gbps": round(alg[k] / (kavg[k] * 1e-3) / 1e9, 1) if kavg.get(k) else None}
@@ -250,7 +276,7 @@ def main():
                "sample": f"one full compaction of the same workload ({in_bytes / 2**20:.0f} MiB input), "
                          f"{cdt:.1f} s",
                "bit_exact": bool(ref.status == 0 and ref.files == gpu_files),
-               "inputs_identical": bool(same_inputs),
+               "inputs_identical": bool(same_inputs), "host": host_info(),
                "sha256_gpu": digest(gpu_files)[:16], "sha256_oracle": digest(ref.files)[:16]}
         log(f"[bench] oracle: {cdt:.1f}s, bit-exact {cpu['bit_exact']}")
 
@@ -273,6 +299,8 @@ def main():
                    "restart_interval": opts["restart_interval"], "bloom_bits_per_key": opts["bloom_bits_per_key"],
                    "bottommost": opts["bottommost"], "target_file_size": opts["target_file_size"],
                    "inputs_resident": "hbm", "outputs": "hbm"},
+        "step_ms": {"median": round(float(np.median(step_s)) * 1e3, 4), "min": round(min(step_s) * 1e3, 4),
+                    "p90": round(float(np.percentile(step_s, 90)) * 1e3, 4)},
         "end_to_end_gbps": e2e,
         "kernel_ms": {k: round(v, 4) for k, v in kavg.items()},
         "kernels": other,
@@ -342,23 +370,38 @@ def batch_main(args):
         f"({plain:.1f} GB/s)")
     kt = kernel_times(ctx)
     cpu = None
-    if args.oracle_jobs > 0:
+    threads = args.oracle_threads or min(16, os.cpu_count() or 1)
+    n_oracle = min(args.oracle_jobs or threads, len(tables))
+    if n_oracle > 0:
+        # the oracle on the host cores: independent jobs of the batch on
+        # `threads` threads at once (the oracle is C called through ctypes,
+        # which runs without the interpreter lock), aggregate input GB/s
+        from concurrent.futures import ThreadPoolExecutor
         import oracle
         from workload import config3_job as mk
-        tot_b, tot_t, exact = 0, 0.0, True
-        for j in range(args.oracle_jobs):
-            job = mk(j, scale=args.scale)
-            ins = oracle.build_input_tables(job)
+        jobs_o = [mk(j, scale=args.scale) for j in range(n_oracle)]
+        ins_o = [oracle.build_input_tables(job) for job in jobs_o]
+
+        def run_one(k):
+            return oracle.compact(ins_o[k], jobs_o[k].options())
+
+        t2 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            refs = list(ex.map(run_one, range(n_oracle)))
+        tot_t = time.perf_counter() - t2
+        tot_b = sum(sum(len(x) for x in ins) for ins in ins_o)
+        exact = True
+        for j in range(n_oracle):
             host = [t.cpu().numpy().tobytes() for t in tables[j]]
-            t2 = time.perf_counter()
-            ref = oracle.compact(ins, job.options())
-            tot_t += time.perf_counter() - t2
-            tot_b += sum(len(x) for x in ins)
-            r = ctx.compact(host, job.options())
-            exact = exact and ins == host and ref.status == 0 and ref.files == r.files
-        cpu = {"value": round(tot_b / tot_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"jobs 0..{args.oracle_jobs - 1} of the batch ({tot_b / 2**20:.0f} MiB), {tot_t:.1f} s",
-               "bit_exact": bool(exact)}
+            r = ctx.compact(host, jobs_o[j].options())
+            exact = exact and ins_o[j] == host and refs[j].status == 0 and refs[j].files == r.files
+        cpu = {"value": round(tot_b / tot_t / 1e9, 4), "unit": "GB/s", "cores": min(threads, n_oracle),
+               "kind": "oracle",
+               "sample": f"jobs 0..{n_oracle - 1} of the batch ({tot_b / 2**20:.0f} MiB) on "
+                         f"{min(threads, n_oracle)} threads, {tot_t:.1f} s wall",
+               "bit_exact": bool(exact), "host": host_info()}
+        log(f"[bench] oracle: {n_oracle} jobs on {min(threads, n_oracle)} threads in {tot_t:.1f}s, "
+            f"bit-exact {exact}")
     out = {
         "metric": "compaction input GB/s (batched)",
         "value": round(value, 2),

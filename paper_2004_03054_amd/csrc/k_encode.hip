@@ -371,22 +371,63 @@ __device__ __forceinline__ void enc_store(const CrcLds* T, const EncodeArgs& A, 
   __builtin_amdgcn_raw_buffer_store_b32(crc_mask(raw ^ 0xFFFFFFFFu), rs, lane_id() == 0 ? H.n : ENC_OOB, 0, 0);
 }
 
-// any block, one chunk at a time
-__device__ void enc_block_any(const CrcLds* T, const EncodeArgs& A, const EncH& H) {
+// Any block, 64 chunks per step.  Lane chunks cover 64 consecutive chunk
+// indices m at each step, [64i, 64i + 64).  The entries whose interiors can
+// hold them start at `base`, the entry found for the step's largest m one
+// step earlier.  They are loaded 64 at a time (one per lane, coalesced) and
+// searched by shuffles, as in the pipelined path.  A lane whose chunk lies
+// past those 64 entries (more than 64 entries start in 1 KiB of the block)
+// searches the global layout instead.  Every lane runs the same steps and
+// issues the same loads, so each wait is exact.
+__device__ void enc_block_any(const CrcLds* T, const EncodeArgs& A, const EncH& H, uint64_t safe) {
   uint8_t* dst = A.out + H.dst;
   const uint32_t n = H.n;
-  uint32_t acc = 0;
-  for (int64_t c = enc_top(H); c >= 0; c -= 64) {
-    const int64_t p0 = (int64_t)n - 16 * (c + 1);
-    const uint4 v = ldg16(enc_src_any(A, H, (uint32_t)((int64_t)H.J16 - 1 - c)));
-    if (p0 >= 0) {
-      __builtin_memcpy(dst + p0, &v, 16);
-      acc = crc_shift(T->sh[6], acc) ^ (p0 < 4 ? crc_chunk(T, v, p0) : crc_chunk_plain(T, v));
+  const EntL* E = A.entl + H.s0;
+  const int64_t ct = enc_top(H);
+  const uint32_t steps = (H.J16 + 63) / 64;
+  const int top_lane = 63 - (int)(H.J16 & 63);  // holds the largest m of every full step
+  uint32_t base = 0, acc = 0;
+  uint32_t wn = min(64u, H.cnt);  // entries in the window, >= 1
+  EntL W = E[min(lane_id(), wn - 1)];
+  for (uint32_t i = 0; i < steps; i++) {
+    const int64_t c = ct - 64 * (int64_t)i;
+    const bool act = c >= 0;
+    const uint32_t m = act ? (uint32_t)((int64_t)H.J16 - 1 - c) : 64 * i;
+    uint32_t lo = 0;
+    for (uint32_t step = wn > 1 ? 1u << (31 - __builtin_clz(wn - 1)) : 0u; step; step >>= 1) {
+      const uint32_t k = min(lo + step, wn - 1);
+      if ((uint32_t)__shfl((int)W.ia, (int)k, WAVE) <= m && lo + step < wn) lo += step;
+    }
+    const uint32_t ia = __shfl((int)W.ia, (int)lo, WAVE), pieces = __shfl((int)W.pieces, (int)lo, WAVE);
+    const uint32_t cum = __shfl((int)W.cum, (int)lo, WAVE);
+    const uint64_t vsrc = ((uint64_t)(uint32_t)__shfl((int)(W.vsrc >> 32), (int)lo, WAVE) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)W.vsrc, (int)lo, WAVE);
+    uint64_t src;
+    if (act && lo == 63 && base + 64 < H.cnt && E[base + 64].ia <= m) {
+      src = enc_src_any(A, H, m);
+    } else if (ia <= m && m < ia + pieces) {
+      src = vsrc + 16ull * m;
     } else {
-      const uint8_t* vb = (const uint8_t*)&v;
-      for (int k = 0; k < 16; k++)
-        if (p0 + k >= 0) dst[p0 + k] = vb[k];
-      acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
+      const uint32_t g = ia <= m ? m - cum - pieces : m;  // gap chunks before m
+      src = (uint64_t)(uintptr_t)(A.gapbuf + H.gap + 1 + g);
+    }
+    const uint4 v = ldg16(act ? src : safe);
+    // the next step's window is loaded while this chunk is in flight (on the
+    // last step too, in bounds and unused: no branch around the load)
+    base += (uint32_t)__shfl((int)lo, top_lane, WAVE);
+    wn = min(64u, H.cnt - base);
+    W = E[base + min(lane_id(), wn - 1)];
+    if (act) {
+      const int64_t p0 = (int64_t)n - 16 * (c + 1);
+      if (p0 >= 0) {
+        __builtin_memcpy(dst + p0, &v, 16);
+        acc = crc_shift(T->sh[6], acc) ^ (p0 < 4 ? crc_chunk(T, v, p0) : crc_chunk_plain(T, v));
+      } else {
+        const uint8_t* vb = (const uint8_t*)&v;
+        for (int k = 0; k < 16; k++)
+          if (p0 + k >= 0) dst[p0 + k] = vb[k];
+        acc = crc_shift(T->sh[6], acc) ^ crc_chunk(T, v, p0);
+      }
     }
   }
   const uint32_t raw = crc_wave_join(T, acc);
@@ -421,7 +462,7 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
     if (H1.piped) enc_load(A, H1, E1, safe, V1);
     const EntL E2 = enc_entl(A, H2);
     if (H0.piped) enc_store(&T, A, H0, V0);
-    else enc_block_any(&T, A, H0);
+    else enc_block_any(&T, A, H0, safe);
     H0 = H1;
     H1 = H2;
     H2 = H3;
