@@ -12,11 +12,13 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -112,6 +114,73 @@ struct DBuf {
   size_t cap = 0;
 };
 
+struct HostBlock;
+
+// Host threads that copy one buffer together (the pageable-to-pinned step of
+// uploads of host inputs).  copy() is called by one thread at a time.
+class CopyPool {
+ public:
+  explicit CopyPool(unsigned n) : n_threads_(n) {
+    for (unsigned i = 0; i < n; i++) th_.emplace_back([this, i] { loop(i); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void copy(void* dst, const void* src, size_t n) {
+    std::unique_lock<std::mutex> lk(mu_);
+    dst_ = (uint8_t*)dst;
+    src_ = (const uint8_t*)src;
+    n_ = n;
+    left_ = n_threads_;
+    gen_++;
+    cv_.notify_all();
+    done_.wait(lk, [&] { return left_ == 0; });
+  }
+
+ private:
+  void loop(unsigned i) {
+    uint64_t seen = 0;
+    for (;;) {
+      uint8_t* d;
+      const uint8_t* s;
+      size_t n;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        d = dst_;
+        s = src_;
+        n = n_;
+      }
+      const size_t part = ((n + n_threads_ - 1) / n_threads_ + 4095) & ~size_t(4095);
+      const size_t a = std::min(n, (size_t)i * part), b = std::min(n, a + part);
+      if (b > a) memcpy(d + a, s + a, b - a);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (--left_ == 0) done_.notify_one();
+      }
+    }
+  }
+  const unsigned n_threads_;
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  uint8_t* dst_ = nullptr;
+  const uint8_t* src_ = nullptr;
+  size_t n_ = 0;
+  uint64_t gen_ = 0;
+  unsigned left_ = 0;
+  bool stop_ = false;
+};
+
+constexpr int UP_SLOTS = 3;
+
 }  // namespace
 
 struct luda_ctx {
@@ -130,6 +199,12 @@ struct luda_ctx {
   uint8_t* stage = nullptr;
   size_t stage_cap = 0, stage_used = 0;
   UpSegs up_pending{};
+  // uploads of host inputs: pinned staging slots, their events, copy threads
+  HostBlock* up_slot[UP_SLOTS] = {};
+  hipEvent_t up_ev[UP_SLOTS] = {};
+  bool up_busy[UP_SLOTS] = {};
+  int up_next = 0;
+  std::unique_ptr<CopyPool> copier;
   // stage timing (LUDA_STAGE_TIMES) and hot-kernel timing (always)
   bool timing = false;
   bool host_sort = false;  // cooperative sort: order the entries on the host (luda_set_host_sort)
@@ -616,6 +691,44 @@ void release_dev(luda_ctx* c, ResultInternal* ri) {
   delete d;
 }
 
+// Host inputs live in pageable memory, which the runtime copies through its
+// own staging at a fraction of the link speed.  Large inputs go instead in
+// chunks through the context's pinned slots: host threads fill one slot
+// while the DMA engine moves the previous one.  Small inputs are copied
+// directly.
+constexpr size_t UP_CHUNK = size_t(32) << 20;
+constexpr size_t UP_DIRECT = size_t(4) << 20;
+
+void upload_host(luda_ctx* c, uint8_t* dst, const uint8_t* src, size_t n) {
+  if (n < UP_DIRECT) {
+    HIPCK(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream));
+    return;
+  }
+  if (!c->copier) {
+    for (int s = 0; s < UP_SLOTS; s++) {
+      if (!c->up_slot[s]) c->up_slot[s] = pin_get(UP_CHUNK);
+      if (!c->up_ev[s]) HIPCK(hipEventCreateWithFlags(&c->up_ev[s], hipEventDisableTiming));
+    }
+    const unsigned hw = std::thread::hardware_concurrency();
+    c->copier.reset(new CopyPool(std::max(1u, std::min(8u, hw ? hw / 2 : 1u))));
+  }
+  for (size_t off = 0; off < n; off += UP_CHUNK) {
+    const size_t len = std::min(UP_CHUNK, n - off);
+    const int s = c->up_next;
+    c->up_next = (s + 1) % UP_SLOTS;
+    HostBlock* h = c->up_slot[s];
+    if (!h || !h->seg) {  // no pinned slot: the runtime's own staging
+      HIPCK(hipMemcpyAsync(dst + off, src + off, len, hipMemcpyHostToDevice, c->stream));
+      continue;
+    }
+    if (c->up_busy[s]) HIPCK(hipEventSynchronize(c->up_ev[s]));  // its last copy has left the slot
+    c->copier->copy(h->p, src + off, len);
+    HIPCK(hipMemcpyAsync(dst + off, h->p, len, hipMemcpyHostToDevice, c->stream));
+    HIPCK(hipEventRecord(c->up_ev[s], c->stream));
+    c->up_busy[s] = true;
+  }
+}
+
 // the output buffer of this call, at least `bytes`: the context's own, else
 // one from the pool (the too small one goes back there), else a new one
 uint8_t* out_buffer(luda_ctx* c, size_t bytes) {
@@ -1091,7 +1204,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     for (uint32_t j = 0; j < J; j++)
       for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
         const luda_buf& b = jobs[j].inputs[i];
-        if (b.size) HIPCK(hipMemcpyAsync(arena + off, b.data, b.size, hipMemcpyHostToDevice, st));
+        if (b.size) upload_host(c, arena + off, b.data, b.size);
         in_ptr.push_back((uint64_t)(uintptr_t)(arena + off));
         off += (b.size + 255) & ~255ull;
       }
@@ -1692,6 +1805,11 @@ void luda_ctx_destroy(luda_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->copier.reset();
+  for (int s = 0; s < UP_SLOTS; s++) {
+    if (c->up_slot[s]) pin_put(c->up_slot[s]);
+    if (c->up_ev[s]) (void)hipEventDestroy(c->up_ev[s]);
+  }
   for (auto& kv : c->bufs)
     if (kv.first == "out_tables")
       dev_pool_put(c->device, kv.second);

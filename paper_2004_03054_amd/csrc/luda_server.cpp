@@ -103,7 +103,17 @@ void worker(luda_server* s, luda_ctx* ctx) {
       s->cv_turn.wait(lk, [&] { return s->copy_turn == seq; });
     }
     for (size_t k = 0; k < batch.size(); k++) {
-      if (s->cfg.host_outputs) luda::result_to_host(ctx, &res[k]);
+      if (s->cfg.host_outputs) {
+        const int rc = luda::result_to_host(ctx, &res[k]);
+        if (rc != LUDA_OK) {  // its outputs did not reach host memory: the job fails with that status
+          const luda_result keep = res[k];
+          luda_result_free(ctx, &res[k]);
+          res[k].entries_in = keep.entries_in;
+          res[k].bytes_in = keep.bytes_in;
+          res[k].ms_total = keep.ms_total;
+          res[k].status = res[k].error.status = rc;
+        }
+      }
       const Clock::time_point now = Clock::now();
       {
         std::lock_guard<std::mutex> lk(s->mu);
