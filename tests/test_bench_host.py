@@ -1,0 +1,37 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the output
+fingerprints that compare served and plain results, and the host record of
+the oracle's timing."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
+
+
+def test_host_fingerprint_tells_outputs_apart():
+    rng = np.random.default_rng(7)
+    a = rng.integers(0, 256, 4099, dtype=np.uint8).tobytes()
+    assert bench.host_fingerprint(a) == bench.host_fingerprint(bytes(a))
+    # the same bytes as a numpy view (the in-place read of host outputs)
+    assert bench.host_fingerprint(np.frombuffer(a, dtype=np.uint8)) == bench.host_fingerprint(a)
+    for at in (0, 8, 4095, 4098):  # a flip in a word, in an odd word, in the tail
+        b = bytearray(a)
+        b[at] ^= 1
+        assert bench.host_fingerprint(bytes(b)) != bench.host_fingerprint(a), at
+    assert bench.host_fingerprint(a[:-1]) != bench.host_fingerprint(a)
+
+
+def test_host_info_names_the_cores():
+    h = bench.host_info()
+    assert h["nproc"] == os.cpu_count() and isinstance(h["cpu_model"], str)
