@@ -1727,7 +1727,8 @@ extern "C" {
 
 int luda_selftest_crc(void) {
   static CrcTables T;
-  build_crc_tables(&T);
+  static std::once_flag built;
+  std::call_once(built, [] { build_crc_tables(&T); });
   uint32_t t0[256];
   byte_table(t0);
   // the byte table against the bitwise definition
@@ -1779,8 +1780,9 @@ int luda_ctx_create(int device, luda_ctx** out) {
     const void* dyn[] = {(const void*)k_filter, (const void*)k_seg_compose};
     for (const void* f : dyn)
       HIPCK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_limit - 2048));
-    static CrcTables T;
-    build_crc_tables(&T);
+    static CrcTables T;  // built once, also when contexts are created on several threads
+    static std::once_flag built;
+    std::call_once(built, [] { build_crc_tables(&T); });
     HIPCK(hipMalloc((void**)&c->d_crc, sizeof(CrcTables)));
     HIPCK(hipMemcpy(c->d_crc, &T, sizeof(CrcTables), hipMemcpyHostToDevice));
     c->mail_cap = 8u << 20;

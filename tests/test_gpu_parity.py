@@ -224,3 +224,38 @@ def test_pooled_output_buffers_are_reused_and_trimmed():
     assert freed > 0 and pool_trim(0) == 0
     r = c.compact_dev(dev, j.options())
     assert [t.cpu().numpy().tobytes() for t in r.files] == ref.files
+
+
+def test_contexts_on_threads_share_the_pools():
+    """Two contexts used from two host threads at once: staged uploads of
+    host inputs (each context's pinned slots and copy threads), results in
+    the shared pinned pool and output buffers back in the shared device pool
+    give every call the oracle's bytes."""
+    import threading
+    from paper_2004_03054_amd import Context
+    jobs = [config1(scale=1 / 16), config2(scale=1 / 16)]  # inputs of 4 MiB or more: the staged path
+    ins = [oracle.build_input_tables(j) for j in jobs]
+    refs = [oracle.compact(i, j.options()) for i, j in zip(ins, jobs)]
+    errors = []
+
+    def work(k):
+        try:
+            c = Context(0)
+            try:
+                for rep in range(3):
+                    r = c.compact(ins[k], jobs[k].options())
+                    assert r.status == 0, (k, rep, r.name)
+                    assert_same_files(r.files, refs[k].files, f"thread {k} call {rep}")
+            finally:
+                c.close()
+        except BaseException as e:  # noqa: BLE001 - reported by the main thread
+            errors.append(e)
+
+    say("[gpu] two contexts on two threads, 3 calls each")
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=100)
+    assert not any(t.is_alive() for t in th), "a thread did not finish"
+    assert not errors, errors[0]
