@@ -235,6 +235,8 @@ struct Fail {
 #define LAUNCH_CHECK() HIPCK(hipGetLastError())
 
 // grow-only named device buffers
+size_t dev_pool_trim(int device);
+
 template <typename T>
 T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
@@ -246,6 +248,10 @@ T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
     b.cap = 0;
     size_t want = bytes + bytes / 8;
     hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess && dev_pool_trim(c->device) > 0) {  // the pooled output buffers give way first
+      (void)hipGetLastError();
+      e = hipMalloc(&b.p, want);
+    }
     if (e != hipSuccess) {
       (void)hipGetLastError();
       throw Fail{LUDA_NOMEM, "device allocation of " + std::to_string(want) + " bytes for " + name + " failed"};
