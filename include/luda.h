@@ -195,7 +195,7 @@ int luda_debug_read(luda_ctx *ctx, const char *name, void *dst, uint64_t offset,
  * the device, never the output bytes. */
 typedef struct {
   uint32_t crc_waves;     /* waves per workgroup of the data-block checksum kernel: 4, 8 or 16 (default 8) */
-  uint32_t encode_waves;  /* most waves per workgroup of the block encoder, 2..16 (default 16; LDS may
+  uint32_t encode_waves;  /* most waves per workgroup of the block encoder, 2..16 (default 4; LDS may
                              allow fewer) */
   uint32_t stride_blocks; /* workgroups per compute unit of the grid-stride kernels, 1..64 (default 16) */
 } luda_params;

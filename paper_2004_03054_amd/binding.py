@@ -79,6 +79,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2004_03054_amd.build_lib.build()")
+    # torch first: the library then binds to the HIP runtime torch has
+    # loaded, and both share one runtime.  Loaded first, the library would
+    # bring in the system runtime, and torch could not initialise its own
+    # afterwards.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     L.luda_ctx_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
     L.luda_ctx_create.restype = C.c_int

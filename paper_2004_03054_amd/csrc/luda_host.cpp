@@ -185,7 +185,7 @@ constexpr int UP_SLOTS = 3;
 
 struct luda_ctx {
   int device = 0;
-  luda_params tp{8, 16, 16};  // launch parameters (luda_set_params / luda_autotune)
+  luda_params tp{8, 4, 16};  // launch parameters (luda_set_params / luda_autotune)
   hipStream_t own = nullptr;
   hipStream_t stream = nullptr;
   uint32_t* d_crc = nullptr;  // CrcTables image

@@ -4,6 +4,8 @@ Inputs are written by the oracle's table writer from seeded workloads; the
 GPU library compacts them and every output byte is compared with the
 oracle's compaction of the same inputs.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -259,3 +261,28 @@ def test_contexts_on_threads_share_the_pools():
         t.join(timeout=100)
     assert not any(t.is_alive() for t in th), "a thread did not finish"
     assert not errors, errors[0]
+
+
+def test_library_before_torch_in_a_fresh_process():
+    """A program that creates a context before it touches torch can still use
+    torch's device memory afterwards (the binding loads torch's HIP runtime
+    first), and compacts device inputs correctly."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
+        "from paper_2004_03054_amd import Context\n"
+        "c = Context(0)\n"
+        "import torch, oracle\n"
+        "from workload import config0\n"
+        "j = config0(); ins = oracle.build_input_tables(j)\n"
+        "dev = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to('cuda') for b in ins]\n"
+        "r = c.compact_dev(dev, j.options())\n"
+        "ok = [t.cpu().numpy().tobytes() for t in r.files] == oracle.compact(ins, j.options()).files\n"
+        "print('same' if ok else 'differ', flush=True)\n"
+    ) % (root, os.path.join(root, "tests"))
+    say("[gpu] fresh process: context before torch")
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=110)
+    assert p.returncode == 0, p.stderr[-2000:]
+    assert p.stdout.strip().endswith("same"), p.stdout
