@@ -55,6 +55,7 @@ extern "C" {
 #define LUDA_UNSUPPORTED (-5)      /* compressed block, or a size beyond the GPU path's limits */
 #define LUDA_NOMEM (-6)            /* device or host allocation failed */
 #define LUDA_DEVICE (-7)           /* HIP runtime error or a device-side wait gave up */
+#define LUDA_CANCELLED (-8)        /* a served job withdrawn before it started (luda_server_cancel) */
 
 /* where a reported corruption lies */
 #define LUDA_WHERE_FOOTER 0
@@ -97,10 +98,19 @@ typedef struct {
                       inside the file; saturates at 2^23 - 1 */
 } luda_error;
 
+/* One output table.  Its key range is what the store installs it under in
+ * level i+1 (the new tables replace the inputs there, Sec. II-A): the smallest
+ * and largest internal keys (user key || fixed64 tag) it holds, as byte
+ * ranges of luda_result.data (both are stored whole in the table: the first
+ * entry of its first data block, and the key of its last index entry). */
 typedef struct {
-  uint64_t offset;      /* start of this table inside luda_result.data */
-  uint64_t size;        /* bytes */
-  uint64_t num_entries; /* entries written to it */
+  uint64_t offset;       /* start of this table inside luda_result.data */
+  uint64_t size;         /* bytes */
+  uint64_t num_entries;  /* entries written to it */
+  uint64_t smallest_off; /* smallest internal key: luda_result.data[smallest_off .. + smallest_len) */
+  uint64_t smallest_len;
+  uint64_t largest_off;  /* largest internal key: luda_result.data[largest_off .. + largest_len) */
+  uint64_t largest_len;
 } luda_file;
 
 /* Result of one job.  `data` holds every output table back to back; it and
@@ -125,38 +135,81 @@ typedef struct {
   luda_options options;
 } luda_job;
 
-/* Create a context on a HIP device.  Returns LUDA_OK or LUDA_DEVICE. */
+/* Create a context on a HIP device: its stream, checksum tables and pinned
+ * staging memory (the GPU side of the paper's host/GPU split, Sec. III-A).
+ * Returns LUDA_OK, LUDA_NOMEM or LUDA_DEVICE; *out is NULL on failure. */
 int luda_ctx_create(int device, luda_ctx **out);
+/* Waits for the context's stream, then frees its buffers and the context. */
 void luda_ctx_destroy(luda_ctx *ctx);
 
 /* Use a caller-owned HIP stream (hipStream_t) for all work; NULL restores
- * the context's own stream.  The caller keeps ownership of the stream. */
+ * the context's own stream.  The caller keeps ownership of the stream.
+ * (The paper overlaps transfers with kernels on streams, Sec. III-D.) */
 int luda_set_stream(luda_ctx *ctx, void *hip_stream);
 
-/* Compact one job whose inputs are in host memory (inputs[0] = upper, newest
- * table).  Output tables are returned in host memory.  Zero inputs, or all
- * entries dropped, give LUDA_OK with zero files.  On error no file is
- * returned and out->error locates the first corruption. */
+/* Device memory from the caller (e.g. PyTorch's caching allocator), so that
+ * one allocator owns the device instead of two.  alloc(user, bytes, stream)
+ * returns device memory usable on `stream` (the context's stream, a
+ * hipStream_t) or NULL; free(user, ptr, bytes, stream) gives it back, and is
+ * called only after the context's stream has finished with it, or with a
+ * NULL stream for an output buffer released by luda_result_free (the
+ * caller's reads of it must be complete by then, as for any result).  With
+ * an allocator set every device buffer of the context's calls comes from it:
+ * working buffers and output tables; the library's own pool of output
+ * buffers is not used.  NULL (or a struct with alloc == NULL) restores
+ * hipMalloc.  The buffers the context already holds are given back to the
+ * allocator they came from first.  alloc and free must both be set or both
+ * NULL (else LUDA_INVALID_ARG); they may be called from the thread that
+ * calls into the context only. */
+typedef struct {
+  void *(*alloc)(void *user, uint64_t bytes, void *stream);
+  void (*free)(void *user, void *ptr, uint64_t bytes, void *stream);
+  void *user;
+} luda_allocator;
+int luda_set_allocator(luda_ctx *ctx, const luda_allocator *allocator);
+
+/* Most device bytes the context's working buffers and output-table buffer
+ * may hold at once (0: no limit, the default).  Buffers a call does not use
+ * are released first when a call needs more; a call that needs more than the
+ * limit by itself fails with LUDA_NOMEM.  The served form gives each worker
+ * the server's HBM budget.  luda_mem_held returns what the context holds. */
+int luda_set_mem_limit(luda_ctx *ctx, uint64_t bytes);
+uint64_t luda_mem_held(luda_ctx *ctx);
+
+/* Compact one job whose inputs are in host memory: the compaction of paper
+ * Sec. II-A (Phase 1 unpack: checksums and key restoration; Phase 2 sort
+ * and drop of stale versions; Phase 3 pack into new tables), run on the GPU
+ * as in Sec. III-A (copy in, kernels, copy out).  inputs[0] is the upper
+ * (newest) table, then the overlapping lower tables; input bytes are
+ * borrowed until return.  Output tables are returned in host memory owned by
+ * the library until luda_result_free.  Zero inputs, or all entries dropped,
+ * give LUDA_OK with zero files.  On error no file is returned, the status is
+ * also the return value, and out->error locates the first corruption. */
 int luda_compact(luda_ctx *ctx, const luda_buf *inputs, uint32_t n_inputs, const luda_options *opt,
                  luda_result *out);
 
-/* As luda_compact, with inputs already in device memory; the output tables
- * stay in device memory (out->data is a device pointer). */
+/* As luda_compact (Sec. II-A, III-A), with inputs already in device memory
+ * (the kernels' part of Sec. III-A alone; PCIe copies are the caller's); the
+ * output tables stay in device memory (out->data is a device pointer owned
+ * by the library until luda_result_free). */
 int luda_compact_dev(luda_ctx *ctx, const luda_buf *dev_inputs, uint32_t n_inputs,
                      const luda_options *opt, luda_result *out);
 
-/* Compact many independent jobs in one pass: every stage runs once over all
- * jobs together.  `device_inputs` selects device (1) or host (0) memory for
- * the inputs and outputs.  results[] receives one result per job; a job that
- * fails never changes another job's bytes.  Returns LUDA_OK unless the batch
- * as a whole could not run. */
+/* Compact many independent jobs (each one job of Sec. II-A) in one pass:
+ * every stage runs once over all jobs together (the paper runs one job at a
+ * time; batching is this library's own form).  `device_inputs` selects
+ * device (1) or host (0) memory for the inputs and outputs.  results[]
+ * receives one result per job; a job that fails never changes another job's
+ * bytes.  Returns LUDA_OK unless the batch as a whole could not run (then
+ * every result carries that status). */
 int luda_compact_batch(luda_ctx *ctx, const luda_job *jobs, uint32_t n_jobs, int device_inputs,
                        luda_result *results);
 
 /* Write ordered entries into tables with the same writer as the compaction
- * (a memtable flush).  Entries are struct-of-arrays in device memory: user
- * keys back to back with n + 1 offsets, tags, values back to back with n + 1
- * offsets; internal keys must be strictly increasing.  Output tables stay in
+ * (Phase 3 of Sec. II-A without the merge: a memtable flush).  Entries are
+ * struct-of-arrays in device memory: user keys back to back with n + 1
+ * offsets, tags, values back to back with n + 1 offsets; internal keys must
+ * be strictly increasing (else LUDA_UNSORTED_INPUT).  Output tables stay in
  * device memory.  Used to build input tables on the device. */
 int luda_build_tables_dev(luda_ctx *ctx, uint64_t n, const uint8_t *keys, const uint64_t *koff,
                           const uint64_t *tags, const uint8_t *vals, const uint64_t *voff,
@@ -172,17 +225,22 @@ int luda_build_tables_dev(luda_ctx *ctx, uint64_t n, const uint8_t *keys, const 
  * also results of one batched pass. */
 void luda_result_free(luda_ctx *ctx, luda_result *r);
 
+/* Name of a status code ("OK", "CORRUPT_CHECKSUM", ...); a static string. */
 const char *luda_status_str(int status);
+/* Text of the context's last failure (owned by the context, valid until its
+ * next call); "" if none. */
 const char *luda_last_error(luda_ctx *ctx);
 
-/* Device times (milliseconds) of the last call, measured with HIP events on
+/* Device times (milliseconds) of the last call (the stage costs the paper
+ * discusses in Sec. III-B and IV-C), measured with HIP events on
  * the context's stream: "kernel:<name>" for the hot kernels (always), and
  * stage spans when the environment variable LUDA_STAGE_TIMES is set.
  * names[] and ms[] receive up to `cap` entries; returns the count. */
 int luda_stage_times(luda_ctx *ctx, const char **names, double *ms, int cap);
 
-/* Counters of the last call (e.g. "data_bytes_in": bytes of the input data
- * blocks with trailers, "data_bytes_out", "entries_in", "survivors").
+/* Counters of the last call (the compaction volume of Sec. IV-C, e.g.
+ * "data_bytes_in": bytes of the input data blocks with trailers,
+ * "data_bytes_out", "entries_in", "survivors").
  * Same calling convention as luda_stage_times. */
 int luda_last_counters(luda_ctx *ctx, const char **names, double *values, int cap);
 
@@ -191,8 +249,9 @@ int luda_last_counters(luda_ctx *ctx, const char **names, double *values, int ca
  * Returns LUDA_OK, or LUDA_INVALID_ARG for an unknown name or range. */
 int luda_debug_read(luda_ctx *ctx, const char *name, void *dst, uint64_t offset, uint64_t bytes);
 
-/* Launch parameters of a context.  They change only how work is laid out on
- * the device, never the output bytes. */
+/* Launch parameters of a context (how the parallel work of Sec. III-C is
+ * laid out on this GPU).  They change only how work is laid out on the
+ * device, never the output bytes. */
 typedef struct {
   uint32_t crc_waves;     /* waves per workgroup of the data-block checksum kernel: 4, 8 or 16 (default 8) */
   uint32_t encode_waves;  /* most waves per workgroup of the block encoder, 2..16 (default 4; LDS may
@@ -200,11 +259,14 @@ typedef struct {
   uint32_t stride_blocks; /* workgroups per compute unit of the grid-stride kernels, 1..64 (default 16) */
 } luda_params;
 
+/* Read the context's parameters into *out (LUDA_INVALID_ARG for NULL). */
 int luda_get_params(luda_ctx *ctx, luda_params *out);
-/* LUDA_INVALID_ARG for a value outside the ranges above. */
+/* Set them for the context's later calls; LUDA_INVALID_ARG for a value
+ * outside the ranges above (the context keeps its old ones). */
 int luda_set_params(luda_ctx *ctx, const luda_params *p);
 
-/* Autotuner: runs the given jobs (as luda_compact_batch) rounds + 1 times
+/* Autotuner (this library's own; the paper fixes its launch shapes, Sec.
+ * III-C): runs the given jobs (as luda_compact_batch) rounds + 1 times
  * for each candidate setting, coordinate by coordinate, keeps the setting
  * with the least wall time in the context and returns it (and its time in
  * *best_ms, may be NULL).  Outputs are discarded.  Returns LUDA_OK or the
@@ -222,7 +284,8 @@ int luda_autotune(luda_ctx *ctx, const luda_job *jobs, uint32_t n_jobs, int devi
 int luda_set_host_sort(luda_ctx *ctx, int on);
 
 /* Host memory for results in host memory is pinned (page-locked), so that
- * the device-to-host copies run at link speed.  It comes from a process-wide
+ * the device-to-host copies (the return path of Sec. III-A and III-D) run at
+ * link speed.  It comes from a process-wide
  * pool of 1 GiB pinned segments, at most 32 GiB, kept until the process
  * ends; a result larger than a segment gets one of its own, released once
  * the result is freed, and past the cap results go to ordinary memory.
@@ -234,24 +297,33 @@ int luda_set_host_sort(luda_ctx *ctx, int on);
 uint64_t luda_pin_reserve(uint64_t bytes);
 
 /* Free the device's pooled output buffers (those of freed results, kept for
- * reuse; see luda_result_free).  Returns the bytes freed.  Buffers held by
+ * reuse across calls, as the new tables of Sec. II-A are handed to the
+ * store; see luda_result_free).  Returns the bytes freed.  Buffers held by
  * live results and contexts are not touched.  Thread-safe. */
 uint64_t luda_pool_trim(int device);
 
-/* Host-side self check of the CRC32C shift tables (no device needed). */
+/* Host-side self check of the CRC32C tables the block checksums use (Sec.
+ * II-A: every block carries a checksum; no device needed).  Returns 0 when
+ * every table agrees with the bitwise definition, else the failing check. */
 int luda_selftest_crc(void);
 
 /* ------------------------------------------------------------------------
- * Served form: a request loop in front of the batched compaction.  Jobs are
- * submitted as they arrive (any thread); a job is admitted when the device
- * memory it is expected to hold (its working set and outputs, estimated as
- * 2 x its input bytes) fits under the budget beside the jobs already
- * admitted.  Each worker (its own context and HIP stream) repeatedly takes
- * the admitted jobs waiting at that moment, up to max_batch_jobs, and runs
- * them as one batched pass (luda_compact_batch); with several workers,
- * batches that arrive while others are on the GPU run on the device at the
- * same time.  A job's outputs are identical to those of luda_compact_dev on
- * the same inputs, whatever it is batched with.
+ * Served form: a request loop in front of the batched compaction (the
+ * paper's store issues compaction jobs to the GPU as they arise, Sec. III-A;
+ * admission and continuous batching are this library's own).  Jobs are
+ * submitted as they arrive (any thread).  A job's expected device footprint
+ * is 3 x its input bytes + 1 MiB (outputs up to its input bytes, working set
+ * up to twice them: entries of 110 bytes or more on average); a job whose
+ * footprint exceeds the whole budget is refused (LUDA_NOMEM).  A job is
+ * admitted when its footprint fits under the budget beside the jobs already
+ * admitted.  Each worker (its own context and HIP stream, its device memory
+ * limited to the budget by luda_set_mem_limit) repeatedly takes the admitted
+ * jobs waiting at that moment, up to max_batch_jobs, and runs them as one
+ * batched pass (luda_compact_batch); with several workers, batches that
+ * arrive while others are on the GPU run on the device at the same time.  If
+ * a pass of several jobs fails as a whole (e.g. LUDA_NOMEM), each of its
+ * jobs is run again alone.  A job's outputs are identical to those of
+ * luda_compact_dev on the same inputs, whatever it is batched with.
  */
 typedef struct luda_server luda_server;
 
@@ -264,13 +336,27 @@ typedef struct {
                               of results (luda_pin_reserve) */
 } luda_server_cfg;
 
-/* Create a server on a HIP device.  LUDA_INVALID_ARG for a bad config. */
+/* Create a server on a HIP device (its workers' contexts and threads).
+ * LUDA_INVALID_ARG for a bad config; a context's failure status otherwise. */
 int luda_server_create(int device, const luda_server_cfg *cfg, luda_server **out);
 
 /* Submit a job whose inputs are in device memory; the input bytes are
  * borrowed until the job completes (the descriptor is copied).  Returns
- * LUDA_OK and a ticket, or LUDA_INVALID_ARG. */
+ * LUDA_OK and a ticket, LUDA_NOMEM (no ticket) for a job whose expected
+ * footprint exceeds the budget, or LUDA_INVALID_ARG. */
 int luda_server_submit(luda_server *s, const luda_job *job, uint64_t *ticket);
+
+/* Withdraw a job that no worker has taken yet: it completes at once with
+ * status LUDA_CANCELLED (collect it with luda_server_poll; its inputs are no
+ * longer borrowed).  Returns LUDA_OK if it was withdrawn, 1 if it has
+ * already started or completed (it then completes normally), or
+ * LUDA_INVALID_ARG for an unknown ticket. */
+int luda_server_cancel(luda_server *s, uint64_t ticket);
+
+/* Device memory of the server: bytes its workers' contexts hold now
+ * (luda_mem_held), and bytes in use on the device as a whole
+ * (hipMemGetInfo: total - free).  Returns 2. */
+int luda_server_memory(luda_server *s, uint64_t *held_by_workers, uint64_t *device_used);
 
 /* Collect a job: with wait != 0 blocks until it completes.  Returns LUDA_OK
  * and moves its result into *out (free it with luda_result_free(NULL, out)),
@@ -279,12 +365,15 @@ int luda_server_submit(luda_server *s, const luda_job *job, uint64_t *ticket);
  * time. */
 int luda_server_poll(luda_server *s, uint64_t ticket, int wait, luda_result *out, double *latency_ms);
 
-/* Counters since creation: jobs completed, batched passes run, the largest
- * batch, and the peak of admitted bytes.  Returns the number of values. */
+/* Counters since creation (the throughput and latency figures of Sec. IV-B
+ * and IV-D come from these jobs): jobs completed, batched passes run, the
+ * largest batch, and the peak of admitted (expected) bytes.  Returns the
+ * number of values. */
 int luda_server_stats(luda_server *s, uint64_t *jobs, uint64_t *batches, uint64_t *max_batch,
                       uint64_t *peak_admitted);
 
-/* Stop the workers (after the jobs already submitted) and free the server. */
+/* Stop the workers (after the jobs already submitted have completed) and
+ * free the server, its contexts and any results not collected. */
 void luda_server_destroy(luda_server *s);
 
 #ifdef __cplusplus

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libluda.so")
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "CORRUPT_FORMAT", -3: "CORRUPT_CHECKSUM",
-          -4: "UNSORTED_INPUT", -5: "UNSUPPORTED", -6: "NOMEM", -7: "DEVICE"}
+          -4: "UNSORTED_INPUT", -5: "UNSUPPORTED", -6: "NOMEM", -7: "DEVICE", -8: "CANCELLED"}
 
 
 class LudaBuf(C.Structure):
@@ -37,7 +37,17 @@ class LudaError(C.Structure):
 
 
 class LudaFile(C.Structure):
-    _fields_ = [("offset", C.c_uint64), ("size", C.c_uint64), ("num_entries", C.c_uint64)]
+    _fields_ = [("offset", C.c_uint64), ("size", C.c_uint64), ("num_entries", C.c_uint64),
+                ("smallest_off", C.c_uint64), ("smallest_len", C.c_uint64),
+                ("largest_off", C.c_uint64), ("largest_len", C.c_uint64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p)
+
+
+class LudaAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
 
 
 class LudaResult(C.Structure):
@@ -67,7 +77,8 @@ EXPORTS = ["luda_ctx_create", "luda_ctx_destroy", "luda_set_stream", "luda_compa
            "luda_last_error", "luda_stage_times", "luda_selftest_crc", "luda_debug_read", "luda_last_counters",
            "luda_server_create", "luda_server_submit", "luda_server_poll", "luda_server_stats",
            "luda_server_destroy", "luda_get_params", "luda_set_params", "luda_autotune", "luda_set_host_sort",
-           "luda_pin_reserve", "luda_pool_trim"]
+           "luda_pin_reserve", "luda_pool_trim", "luda_set_allocator", "luda_set_mem_limit", "luda_mem_held",
+           "luda_server_cancel", "luda_server_memory"]
 
 _lib = None
 
@@ -137,6 +148,16 @@ def lib():
     L.luda_pool_trim.restype = C.c_uint64
     L.luda_server_destroy.argtypes = [C.c_void_p]
     L.luda_server_destroy.restype = None
+    L.luda_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+    L.luda_server_cancel.restype = C.c_int
+    L.luda_server_memory.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.luda_server_memory.restype = C.c_int
+    L.luda_set_allocator.argtypes = [C.c_void_p, C.POINTER(LudaAllocator)]
+    L.luda_set_allocator.restype = C.c_int
+    L.luda_set_mem_limit.argtypes = [C.c_void_p, C.c_uint64]
+    L.luda_set_mem_limit.restype = C.c_int
+    L.luda_mem_held.argtypes = [C.c_void_p]
+    L.luda_mem_held.restype = C.c_uint64
     _lib = L
     return L
 
@@ -181,6 +202,8 @@ class Result:
     bytes_out: int = 0
     ms_total: float = 0.0
     file_sizes: List[int] = field(default_factory=list)
+    # per file: (smallest key offset, length, largest key offset, length), offsets inside the file
+    key_ranges: List[tuple] = field(default_factory=list)
 
     @property
     def name(self) -> str:
@@ -201,6 +224,9 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
                  entries_in=r.entries_in, entries_out=r.entries_out, dropped_shadowed=r.dropped_shadowed,
                  dropped_tombstones=r.dropped_tombstones, bytes_in=r.bytes_in, bytes_out=r.bytes_out,
                  ms_total=r.ms_total)
+    for i in range(r.num_files if r.status == 0 else 0):
+        f = r.files[i]
+        res.key_ranges.append((f.smallest_off - f.offset, f.smallest_len, f.largest_off - f.offset, f.largest_len))
     if r.status == 0 and r.num_files and callable(materialize):
         # apply a function to each output table in place, before the library
         # frees it (no copy): a torch uint8 tensor over device outputs, a
@@ -280,6 +306,7 @@ class Context:
 
     def __init__(self, device: int = 0):
         self._h = C.c_void_p()
+        self._alloc = None
         rc = lib().luda_ctx_create(device, C.byref(self._h))
         if rc != 0:
             raise RuntimeError(f"luda_ctx_create failed: {STATUS.get(rc, rc)}")
@@ -288,6 +315,7 @@ class Context:
         if self._h:
             lib().luda_ctx_destroy(self._h)
             self._h = C.c_void_p()
+            self._alloc = None
 
     def __del__(self):
         try:
@@ -362,6 +390,40 @@ class Context:
             keep.append(o)  # its snapshot array must outlive the call
             cjobs[j].options = o
         return cjobs, keep
+
+    def set_mem_limit(self, nbytes: int):
+        """Most device bytes the context's buffers may hold at once (0: none)."""
+        lib().luda_set_mem_limit(self._h, int(nbytes))
+
+    def mem_held(self) -> int:
+        return int(lib().luda_mem_held(self._h))
+
+    def use_torch_allocator(self, on: bool = True):
+        """Take the context's device memory from PyTorch's caching allocator
+        (luda_set_allocator), or (on=False) from hipMalloc again."""
+        if not on:
+            rc = lib().luda_set_allocator(self._h, None)
+            self._alloc = None
+            if rc != 0:
+                raise RuntimeError(f"luda_set_allocator: {STATUS.get(rc, rc)}")
+            return
+        import torch  # device memory plumbing only
+        dev = torch.cuda.current_device()
+
+        def _alloc(user, nbytes, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+            except Exception:  # noqa: BLE001 - out of memory is reported as NULL
+                return None
+
+        def _free(user, ptr, nbytes, stream):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        a = LudaAllocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+        rc = lib().luda_set_allocator(self._h, C.byref(a))
+        if rc != 0:
+            raise RuntimeError(f"luda_set_allocator: {STATUS.get(rc, rc)}")
+        self._alloc = a  # the callbacks live as long as the context uses them
 
     def set_host_sort(self, on: bool):
         """Cooperative sort: order the entries on the host instead of merging
@@ -462,6 +524,8 @@ class Server:
         job.options = o
         t = C.c_uint64()
         rc = lib().luda_server_submit(self._h, C.byref(job), C.byref(t))
+        if rc == -6:
+            raise MemoryError("luda_server_submit: the job's expected footprint exceeds the HBM budget")
         if rc != 0:
             raise RuntimeError(f"luda_server_submit failed: {STATUS.get(rc, rc)}")
         self._keep[t.value] = (bufs, list(inputs))
@@ -478,6 +542,18 @@ class Server:
             raise RuntimeError(f"luda_server_poll failed: {STATUS.get(rc, rc)}")
         self._keep.pop(ticket, None)
         return _take(None, r, device=not self._host, materialize=materialize), lat.value
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraw a job no worker has taken yet (True), else False."""
+        rc = lib().luda_server_cancel(self._h, ticket)
+        if rc < 0:
+            raise RuntimeError(f"luda_server_cancel failed: {STATUS.get(rc, rc)}")
+        return rc == 0
+
+    def memory(self) -> dict:
+        h, u = C.c_uint64(), C.c_uint64()
+        lib().luda_server_memory(self._h, C.byref(h), C.byref(u))
+        return dict(held_by_workers=h.value, device_used=u.value)
 
     def stats(self) -> dict:
         v = [C.c_uint64() for _ in range(4)]

@@ -50,6 +50,7 @@ struct OutFiles {
   uint64_t* size;      // whole file
   uint64_t* out;       // offset in the output buffer
   uint64_t* entries;
+  uint64_t* keyr;      // 4 per file: smallest key offset (in the file) and length, largest key offset and length
 };
 
 // decode
@@ -239,7 +240,8 @@ __global__ void k_ranges(const uint64_t* ient, const uint64_t* ibase, const uint
                          uint64_t* out);
 __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0);
 __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats);
-__global__ void k_file_entries(OutFiles of, OutBlocks ob, uint64_t nf);
+__global__ void k_file_entries(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint64_t* ie_off,
+                               uint64_t nf);
 __global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen);
 __global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,
                          const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv);

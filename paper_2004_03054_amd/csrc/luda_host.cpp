@@ -20,6 +20,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -112,6 +114,7 @@ void build_crc_tables(CrcTables* T) {
 struct DBuf {
   void* p = nullptr;
   size_t cap = 0;
+  uint64_t gen = 0;  // the call that last used it
 };
 
 struct HostBlock;
@@ -193,6 +196,9 @@ struct luda_ctx {
   size_t lds_limit = 64 * 1024;  // LDS per workgroup
   std::string last_error;
   std::map<std::string, DBuf> bufs;
+  uint64_t call_gen = 0;   // calls so far (begin_call)
+  uint64_t mem_limit = 0;  // most device bytes the named buffers may hold at once (0: no limit)
+  luda_allocator alloc{};  // caller's device allocator (luda_set_allocator); alloc.alloc == NULL: hipMalloc
   // pinned host memory: readbacks (written by k_mail) and staged uploads
   uint8_t* mail = nullptr;
   size_t mail_cap = 0;
@@ -234,23 +240,124 @@ struct Fail {
 
 #define LAUNCH_CHECK() HIPCK(hipGetLastError())
 
+// Runs fn and turns every exception into a status: Fail carries its own,
+// a failed host allocation is LUDA_NOMEM, anything else (e.g. a thread that
+// could not start) LUDA_DEVICE.  No exception crosses the C-ABI.
+template <typename F>
+int guarded(luda_ctx* c, F&& fn) {
+  std::string msg;
+  int st = LUDA_OK;
+  try {
+    fn();
+    return LUDA_OK;
+  } catch (const Fail& f) {
+    st = f.status;
+    msg = f.msg;
+  } catch (const std::bad_alloc&) {
+    st = LUDA_NOMEM;
+    msg = "host allocation failed";
+  } catch (const std::exception& e) {
+    st = LUDA_DEVICE;
+    msg = e.what();
+  } catch (...) {
+    st = LUDA_DEVICE;
+    msg = "unexpected failure";
+  }
+  if (c) {
+    try {
+      c->last_error = msg;
+    } catch (...) {
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipGetLastError();
+  }
+  return st;
+}
+
+
 // grow-only named device buffers
 size_t dev_pool_trim(int device);
+void dev_pool_put(int device, DBuf b);
+
+// Device memory of the context: the caller's allocator when one is set,
+// else hipMalloc.  A buffer is given back only once the context's stream has
+// finished with it (hipFree waits for the device by itself).
+hipError_t dmalloc(luda_ctx* c, void** p, size_t bytes) {
+  if (!c->alloc.alloc) return hipMalloc(p, bytes);
+  *p = c->alloc.alloc(c->alloc.user, bytes, (void*)c->stream);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+void dfree(luda_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (!c->alloc.alloc) {
+    HIPCK(hipFree(p));
+    return;
+  }
+  HIPCK(hipStreamSynchronize(c->stream));
+  c->alloc.free(c->alloc.user, p, bytes, (void*)c->stream);
+}
+// the output-table buffer goes back to the device pool (hipMalloc'd) or to
+// the caller's allocator
+void release_out(luda_ctx* c, DBuf b) {
+  if (!b.p) return;
+  if (c->alloc.alloc)
+    dfree(c, b.p, b.cap);
+  else
+    dev_pool_put(c->device, b);
+}
+
+// device bytes held by the context's named buffers
+size_t held_bytes(const luda_ctx* c) {
+  size_t n = 0;
+  for (auto& kv : c->bufs) n += kv.second.cap;
+  return n;
+}
+
+// Keep the named buffers within the context's memory limit when one of them
+// grows to `want` bytes: buffers that the current call has not used are
+// freed first; if the call itself needs more, it fails with LUDA_NOMEM.
+void fit_limit(luda_ctx* c, const std::string& name, size_t want) {
+  if (!c->mem_limit) return;
+  const size_t own = c->bufs[name].cap;
+  if (held_bytes(c) - own + want <= c->mem_limit) return;
+  HIPCK(hipStreamSynchronize(c->stream));
+  for (auto& kv : c->bufs)
+    if (kv.first != name && kv.second.gen != c->call_gen && kv.second.p) {
+      if (kv.first == "out_tables")
+        release_out(c, kv.second);
+      else
+        dfree(c, kv.second.p, kv.second.cap);
+      kv.second = DBuf{};
+    }
+  if (held_bytes(c) - own + want > c->mem_limit)
+    throw Fail{LUDA_NOMEM, "the call needs more device memory than the context's limit of " +
+                               std::to_string(c->mem_limit) + " bytes (" + name + ")"};
+}
 
 template <typename T>
 T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   bytes = (bytes + 255) & ~size_t(255);
+  c->bufs[name].gen = c->call_gen;
   DBuf& b = c->bufs[name];
   if (b.cap < bytes) {
-    if (b.p) HIPCK(hipFree(b.p));
+    size_t want = bytes + bytes / 8;
+    if (c->mem_limit) {
+      fit_limit(c, name, bytes);
+      if (held_bytes(c) - b.cap + want > c->mem_limit) want = bytes;
+    }
+    if (b.p) {
+      if (name == "out_tables")
+        release_out(c, b);
+      else
+        dfree(c, b.p, b.cap);
+    }
     b.p = nullptr;
     b.cap = 0;
-    size_t want = bytes + bytes / 8;
-    hipError_t e = hipMalloc(&b.p, want);
+    hipError_t e = dmalloc(c, &b.p, want);
     if (e != hipSuccess && dev_pool_trim(c->device) > 0) {  // the pooled output buffers give way first
       (void)hipGetLastError();
-      e = hipMalloc(&b.p, want);
+      e = dmalloc(c, &b.p, want);
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -335,12 +442,17 @@ struct Mail {
   luda_ctx* c;
   std::vector<MailSegs> segs;
   size_t used = 0;
+  // ranges that do not fit in the mailbox: copied into host memory of their own
+  std::vector<std::pair<const void*, std::vector<uint8_t>>> big;
   explicit Mail(luda_ctx* c_) : c(c_) { segs.emplace_back(); }
   template <typename T>
   const T* add(const T* dev, size_t count) {
     const size_t bytes = count * sizeof(T);
     const size_t off = (used + 15) & ~size_t(15);
-    if (off + bytes > c->mail_cap) throw Fail{LUDA_UNSUPPORTED, "readback larger than the pinned mailbox"};
+    if (off + bytes > c->mail_cap || bytes > 0xFFFFFFFFull) {
+      big.emplace_back((const void*)dev, std::vector<uint8_t>(std::max<size_t>(bytes, 1)));
+      return (const T*)big.back().second.data();
+    }
     used = off + bytes;
     if (!bytes) return (const T*)(c->mail + off);
     if (segs.back().n == 12) segs.emplace_back();
@@ -358,6 +470,9 @@ struct Mail {
         hipLaunchKernelGGL(k_mail, dim3(m.n), dim3(256), 0, c->stream, m, c->mail);
         LAUNCH_CHECK();
       }
+    for (auto& b : big)
+      if (b.first)
+        HIPCK(hipMemcpyAsync(b.second.data(), b.first, b.second.size(), hipMemcpyDeviceToHost, c->stream));
     sync(c);
   }
 };
@@ -399,23 +514,34 @@ struct KTimer {
   }
 };
 
-void collect_times(luda_ctx* c) {
-  c->stage_ms.clear();
-  if (c->timing && c->marks.size() > 1) {
-    for (size_t i = 1; i < c->marks.size(); i++) {
-      float t = 0;
-      HIPCK(hipEventElapsedTime(&t, c->marks[i - 1].second, c->marks[i].second));
-      c->stage_ms.emplace_back(c->marks[i].first, t);
+// Called after the call's final sync, when results may already hold
+// buffers: it never throws (a time that cannot be read is left out).
+void collect_times(luda_ctx* c) noexcept {
+  try {
+    c->stage_ms.clear();
+    if (c->timing && c->marks.size() > 1) {
+      for (size_t i = 1; i < c->marks.size(); i++) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, c->marks[i - 1].second, c->marks[i].second) == hipSuccess)
+          c->stage_ms.emplace_back(c->marks[i].first, t);
+        else
+          (void)hipGetLastError();
+      }
     }
-  }
-  for (auto& km : c->kmarks) {
-    float t = 0;
-    HIPCK(hipEventElapsedTime(&t, km.second.first, km.second.second));
-    c->stage_ms.emplace_back(std::string("kernel:") + km.first, t);
+    for (auto& km : c->kmarks) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, km.second.first, km.second.second) == hipSuccess)
+        c->stage_ms.emplace_back(std::string("kernel:") + km.first, t);
+      else
+        (void)hipGetLastError();
+    }
+  } catch (...) {
+    c->stage_ms.clear();
   }
 }
 
 void begin_call(luda_ctx* c) {
+  c->call_gen++;
   c->marks.clear();
   c->event_used = 0;
   c->kmarks.clear();
@@ -472,7 +598,9 @@ struct DevBlock {
   size_t cap = 0;
   std::atomic<int> refs{0};  // results of one pass may be freed from several threads
   int device = 0;
-  DevBlock(void* p_, size_t cap_, int refs_, int device_) : p(p_), cap(cap_), refs(refs_), device(device_) {}
+  luda_allocator alloc{};  // the caller's allocator it came from (alloc.alloc == NULL: the device pool)
+  DevBlock(void* p_, size_t cap_, int refs_, int device_, const luda_allocator& a)
+      : p(p_), cap(cap_), refs(refs_), device(device_), alloc(a) {}
 };
 
 // Output buffers handed to results come back, when the results are freed, to
@@ -693,7 +821,10 @@ void release_dev(luda_ctx* c, ResultInternal* ri) {
   ri->dev = nullptr;  // this result no longer holds the buffer, whoever frees it
   if (--d->refs > 0) return;
   (void)c;
-  dev_pool_put(d->device, DBuf{d->p, d->cap});
+  if (d->alloc.alloc)
+    d->alloc.free(d->alloc.user, d->p, d->cap, nullptr);
+  else
+    dev_pool_put(d->device, DBuf{d->p, d->cap});
   delete d;
 }
 
@@ -739,11 +870,17 @@ void upload_host(luda_ctx* c, uint8_t* dst, const uint8_t* src, size_t n) {
 // one from the pool (the too small one goes back there), else a new one
 uint8_t* out_buffer(luda_ctx* c, size_t bytes) {
   DBuf& b = c->bufs["out_tables"];
-  if (b.cap < bytes) {
+  if (b.cap < bytes && !c->alloc.alloc) {
     const size_t want = (bytes + 255) & ~size_t(255);
     DBuf got = dev_pool_get(c->device, want);
-    dev_pool_put(c->device, b);
-    b = got;
+    dev_pool_put(c->device, DBuf{b.p, b.cap});
+    b = DBuf{};
+    if (got.p && c->mem_limit && held_bytes(c) + got.cap > c->mem_limit) {  // too large for the limit
+      dev_pool_put(c->device, got);
+      got = DBuf{};
+    }
+    b.p = got.p;
+    b.cap = got.cap;
   }
   return dbuf<uint8_t>(c, "out_tables", bytes);
 }
@@ -767,8 +904,20 @@ struct PlanOut {
   uint8_t* d_out = nullptr;
   std::vector<uint64_t> file_out;  // nfiles + 1
   std::vector<uint64_t> file_entries;
+  std::vector<uint64_t> file_keys;  // 4 per file (k_file_entries)
   std::vector<uint64_t> job_f0;  // J + 1
 };
+
+// a result's file record: its place in the result's data and its key range
+void set_file(luda_file& x, const PlanOut& O, uint64_t f, uint64_t base) {
+  x.offset = O.file_out[f] - base;
+  x.size = O.file_out[f + 1] - O.file_out[f];
+  x.num_entries = O.file_entries[f];
+  x.smallest_off = x.offset + O.file_keys[4 * f + 0];
+  x.smallest_len = O.file_keys[4 * f + 1];
+  x.largest_off = x.offset + O.file_keys[4 * f + 2];
+  x.largest_len = O.file_keys[4 * f + 3];
+}
 
 void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   const uint32_t J = P.J;
@@ -906,6 +1055,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   of.size = dbuf<uint64_t>(c, "of_size", FC);
   of.out = dbuf<uint64_t>(c, "of_out", FC + 1);
   of.entries = dbuf<uint64_t>(c, "of_entries", FC);
+  of.keyr = dbuf<uint64_t>(c, "of_keyr", 4 * FC);
   hipLaunchKernelGGL(k_file_pre, dim3(blocks_for(FC)), dim3(256), 0, st, job_f0, J, job_ob0, file_first, ob_excl,
                      FC, of);
   LAUNCH_CHECK();
@@ -958,25 +1108,28 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   launch_scan<uint64_t, uint64_t>(of.size, NF, nullptr, of.out, scan_tmp, st);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, NF);
+  hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, P.d_surv, P.tu, ie_off, NF);
   LAUNCH_CHECK();
   BlockRec* brec = dbuf<BlockRec>(c, "blk_rec", NBLK);
   hipLaunchKernelGGL(k_block_dst, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.d_jobs, job_ob0 + J, NBLK, brec);
   LAUNCH_CHECK();
   O.file_out.assign(NF + 1, 0);
   O.file_entries.assign(NF, 0);
+  O.file_keys.assign(4 * NF, 0);
   uint32_t max_win = 0;
   uint64_t dout = 0;
   {
     Mail m(c);
     const uint64_t* fo = m.add(of.out, NF + 1);
     const uint64_t* fe = m.add(of.entries, NF);
+    const uint64_t* fk = m.add(of.keyr, 4 * NF);
     const uint64_t* jf = m.add(job_f0, J + 1);
     const uint32_t* mw = m.add(wstat, 1);
     const uint64_t* dx = m.add(ob_excl + NBLK, 1);
     m.flush();
     memcpy(O.file_out.data(), fo, (NF + 1) * 8);
     memcpy(O.file_entries.data(), fe, NF * 8);
+    memcpy(O.file_keys.data(), fk, NF * 32);
     memcpy(O.job_f0.data(), jf, (J + 1) * 8);
     max_win = *mw;
     dout = *dx;
@@ -1638,7 +1791,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   DevBlock* dblk = nullptr;
   if (dev_out && O.total_bytes) {
     DBuf& b = c->bufs["out_tables"];
-    dblk = new DevBlock(b.p, b.cap, 0, c->device);
+    dblk = new DevBlock(b.p, b.cap, 0, c->device, c->alloc);
     b = DBuf{};
   }
   for (uint32_t j = 0; j < J; j++) {
@@ -1663,9 +1816,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       r.files = (luda_file*)calloc(r.num_files, sizeof(luda_file));
       const uint64_t base = O.file_out[f0];
       for (uint64_t f = f0; f < f1; f++) {
-        r.files[f - f0].offset = O.file_out[f] - base;
-        r.files[f - f0].size = O.file_out[f + 1] - O.file_out[f];
-        r.files[f - f0].num_entries = O.file_entries[f];
+        set_file(r.files[f - f0], O, f, base);
       }
       r.data_size = O.file_out[f1] - base;
       r.bytes_out = r.data_size;
@@ -1772,8 +1923,9 @@ int luda_selftest_crc(void) {
 int luda_ctx_create(int device, luda_ctx** out) {
   if (!out) return LUDA_INVALID_ARG;
   *out = nullptr;
-  luda_ctx* c = new luda_ctx();
-  try {
+  luda_ctx* c = new (std::nothrow) luda_ctx();
+  if (!c) return LUDA_NOMEM;
+  const int st = guarded(nullptr, [&] {
     c->device = device;
     HIPCK(hipSetDevice(device));
     HIPCK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
@@ -1796,14 +1948,14 @@ int luda_ctx_create(int device, luda_ctx** out) {
     c->stage_cap = 16u << 20;
     HIPCK(hipHostMalloc((void**)&c->stage, c->stage_cap, hipHostMallocCoherent));
     c->timing = getenv("LUDA_STAGE_TIMES") != nullptr;
-  } catch (const Fail& f) {
-    fprintf(stderr, "luda_ctx_create: %s\n", f.msg.c_str());
+  });
+  if (st != LUDA_OK) {
     if (c->mail) (void)hipHostFree(c->mail);
     if (c->stage) (void)hipHostFree(c->stage);
     if (c->d_crc) (void)hipFree(c->d_crc);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
-    return f.status;
+    return st;
   }
   *out = c;
   return LUDA_OK;
@@ -1818,11 +1970,15 @@ void luda_ctx_destroy(luda_ctx* c) {
     if (c->up_slot[s]) pin_put(c->up_slot[s]);
     if (c->up_ev[s]) (void)hipEventDestroy(c->up_ev[s]);
   }
-  for (auto& kv : c->bufs)
-    if (kv.first == "out_tables")
-      dev_pool_put(c->device, kv.second);
-    else if (kv.second.p)
-      (void)hipFree(kv.second.p);
+  for (auto& kv : c->bufs) {
+    try {
+      if (kv.first == "out_tables")
+        release_out(c, kv.second);
+      else
+        dfree(c, kv.second.p, kv.second.cap);
+    } catch (...) {
+    }
+  }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
   for (auto e : c->kevents) (void)hipEventDestroy(e);
   if (c->d_crc) (void)hipFree(c->d_crc);
@@ -1838,21 +1994,44 @@ int luda_set_stream(luda_ctx* c, void* s) {
   return LUDA_OK;
 }
 
+int luda_set_allocator(luda_ctx* c, const luda_allocator* a) {
+  if (!c || (a && (!a->alloc != !a->free))) return LUDA_INVALID_ARG;
+  // the buffers already held came from the previous allocator: they go back to it
+  const int st = guarded(c, [&] {
+    HIPCK(hipSetDevice(c->device));
+    HIPCK(hipStreamSynchronize(c->stream));
+    for (auto& kv : c->bufs) {
+      if (kv.first == "out_tables")
+        release_out(c, kv.second);
+      else
+        dfree(c, kv.second.p, kv.second.cap);
+      kv.second = DBuf{};
+    }
+    c->alloc = (a && a->alloc) ? *a : luda_allocator{};
+  });
+  return st;
+}
+
+int luda_set_mem_limit(luda_ctx* c, uint64_t bytes) {
+  if (!c) return LUDA_INVALID_ARG;
+  c->mem_limit = bytes;
+  return LUDA_OK;
+}
+
+uint64_t luda_mem_held(luda_ctx* c) { return c ? (uint64_t)held_bytes(c) : 0; }
+
 static int run_guarded(luda_ctx* c, const luda_job* jobs, uint32_t n, bool dev, luda_result* res) {
-  try {
+  const int st = guarded(c, [&] {
     HIPCK(hipSetDevice(c->device));
     run_batch(c, jobs, n, dev, res);
-  } catch (const Fail& f) {
-    c->last_error = f.msg;
-    (void)hipStreamSynchronize(c->stream);
+  });
+  if (st != LUDA_OK)
     for (uint32_t j = 0; j < n; j++) {
       memset(&res[j], 0, sizeof(luda_result));
-      res[j].status = f.status;
-      res[j].error.status = f.status;
+      res[j].status = st;
+      res[j].error.status = st;
     }
-    return f.status;
-  }
-  return LUDA_OK;
+  return st;
 }
 
 int luda_compact_batch(luda_ctx* c, const luda_job* jobs, uint32_t n_jobs, int device_inputs, luda_result* results) {
@@ -1911,7 +2090,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     out->status = out->error.status = LUDA_INVALID_ARG;
     return LUDA_INVALID_ARG;
   }
-  try {
+  const int st = guarded(c, [&] {
     HIPCK(hipSetDevice(c->device));
     if (n > 0xFFFFFFF0ull) throw Fail{LUDA_UNSUPPORTED, "more than 2^32 entries"};
     hipStream_t st = c->stream;
@@ -1985,25 +2164,22 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     out->internal = ri;
     if (nf) {
       DBuf& b = c->bufs["out_tables"];
-      ri->dev = new DevBlock(b.p, b.cap, 1, c->device);
+      ri->dev = new DevBlock(b.p, b.cap, 1, c->device, c->alloc);
       b = DBuf{};
       out->files = (luda_file*)calloc(nf, sizeof(luda_file));
       for (uint64_t f = 0; f < nf; f++) {
-        out->files[f].offset = O.file_out[f];
-        out->files[f].size = O.file_out[f + 1] - O.file_out[f];
-        out->files[f].num_entries = O.file_entries[f];
+        set_file(out->files[f], O, f, 0);
       }
       out->data = (uint8_t*)ri->dev->p;
       out->data_size = O.file_out[nf];
       out->bytes_out = out->data_size;
     }
-  } catch (const Fail& f) {
-    c->last_error = f.msg;
-    (void)hipStreamSynchronize(c->stream);
-    out->status = out->error.status = f.status;
-    return f.status;
+  });
+  if (st != LUDA_OK) {
+    luda_result_free(c, out);
+    out->status = out->error.status = st;
   }
-  return LUDA_OK;
+  return st;
 }
 
 static bool params_ok(const luda_params* p) {
@@ -2097,6 +2273,7 @@ const char* luda_status_str(int s) {
     case LUDA_UNSUPPORTED: return "UNSUPPORTED";
     case LUDA_NOMEM: return "NOMEM";
     case LUDA_DEVICE: return "DEVICE";
+    case LUDA_CANCELLED: return "CANCELLED";
     default: return "UNKNOWN";
   }
 }
