@@ -2025,6 +2025,20 @@ static int run_guarded(luda_ctx* c, const luda_job* jobs, uint32_t n, bool dev, 
     HIPCK(hipSetDevice(c->device));
     run_batch(c, jobs, n, dev, res);
   });
+  if (st == LUDA_NOMEM) {
+    // buffers sized for a call that did not fit are given back: a later,
+    // smaller call starts from nothing rather than from their sizes
+    (void)guarded(c, [&] {
+      HIPCK(hipStreamSynchronize(c->stream));
+      for (auto& kv : c->bufs) {
+        if (kv.first == "out_tables")
+          release_out(c, kv.second);
+        else
+          dfree(c, kv.second.p, kv.second.cap);
+        kv.second = DBuf{};
+      }
+    });
+  }
   if (st != LUDA_OK)
     for (uint32_t j = 0; j < n; j++) {
       memset(&res[j], 0, sizeof(luda_result));

@@ -23,8 +23,8 @@ def corrupt(blob: bytes, at: int) -> bytes:
     return bytes(b)
 
 
-@pytest.mark.parametrize("budget_mib,workers,max_batch", [(1024, 2, 0), (4, 2, 3), (1, 1, 1)])
-def test_served_mix_matches_oracle(budget_mib, workers, max_batch):
+@pytest.mark.parametrize("budget,workers,max_batch", [("1GiB", 2, 0), ("tight", 2, 3), ("tight", 1, 1)])
+def test_served_mix_matches_oracle(budget, workers, max_batch):
     from paper_2004_03054_amd import Server
     jobs = [tiny_job(s, mode=("l0", "leveled")[s % 2], bottommost=s % 2) for s in range(8)]
     jobs += [config3_job(4, scale=1 / 64), config0(), config3_job(5, scale=1 / 128)]
@@ -32,8 +32,12 @@ def test_served_mix_matches_oracle(budget_mib, workers, max_batch):
     # one job with a corrupted data block: only it fails
     bad = 3
     ins[bad] = [corrupt(ins[bad][0], 7)] + ins[bad][1:]
-    say(f"[gpu] server: {len(jobs)} jobs, budget {budget_mib} MiB, {workers} workers, max batch {max_batch}")
-    srv = Server(0, hbm_budget=budget_mib << 20, max_batch_jobs=max_batch, workers=workers)
+    # "tight": twice the largest job's expected footprint (3x its input + 1 MiB),
+    # so that only a few jobs are admitted at a time and the rest wait
+    fp = max(3 * sum(map(len, i)) + (1 << 20) for i in ins)
+    budget_bytes = 1 << 30 if budget == "1GiB" else 2 * fp
+    say(f"[gpu] server: {len(jobs)} jobs, budget {budget_bytes >> 20} MiB, {workers} workers, max batch {max_batch}")
+    srv = Server(0, hbm_budget=budget_bytes, max_batch_jobs=max_batch, workers=workers)
     try:
         dev = [to_dev(i) for i in ins]
         tickets = [srv.submit(d, j.options()) for d, j in zip(dev, jobs)]
