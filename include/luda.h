@@ -195,6 +195,26 @@ int luda_compact(luda_ctx *ctx, const luda_buf *inputs, uint32_t n_inputs, const
 int luda_compact_dev(luda_ctx *ctx, const luda_buf *dev_inputs, uint32_t n_inputs,
                      const luda_options *opt, luda_result *out);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  The same
+ * compaction as luda_compact_dev, but it allocates no device memory and no
+ * pinned host memory: every working buffer of the call is carved from a
+ * static device array of LUDA_SCRATCH_BYTES (one copy per GPU, held until
+ * the process ends), and the output tables are written into the caller's
+ * device buffer out_buf of out_cap bytes (out_cap must cover the tables'
+ * total size plus 64 bytes).  On success out->data points into out_buf, and
+ * luda_result_free releases only the file list.  A call whose working buffers
+ * exceed the scratch array (about 200 bytes per entry plus key bytes: some
+ * 1.2 million entries), or whose tables exceed out_cap, fails with
+ * LUDA_NOMEM and a message naming the limit.  Every context of the process
+ * on one GPU shares that GPU's array, which keeps the last call's contents;
+ * the library therefore runs these calls one at a time per GPU (a call that
+ * overlaps another on the same GPU waits for it).  Arguments, inputs and
+ * errors as for luda_compact_dev. */
+#define LUDA_SCRATCH_BYTES (256ull << 20)
+int luda_compact_dev_noalloc(luda_ctx *ctx, const luda_buf *dev_inputs, uint32_t n_inputs,
+                             const luda_options *opt, uint8_t *out_buf, uint64_t out_cap, luda_result *out);
+
 /* Compact many independent jobs (each one job of Sec. II-A) in one pass:
  * every stage runs once over all jobs together (the paper runs one job at a
  * time; batching is this library's own form).  `device_inputs` selects

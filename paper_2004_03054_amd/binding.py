@@ -106,6 +106,9 @@ def lib():
         f = getattr(L, name)
         f.argtypes = [C.c_void_p, C.POINTER(LudaBuf), C.c_uint32, C.POINTER(LudaOptions), C.POINTER(LudaResult)]
         f.restype = C.c_int
+    L.luda_compact_dev_noalloc.argtypes = [C.c_void_p, C.POINTER(LudaBuf), C.c_uint32, C.POINTER(LudaOptions),
+                                           C.c_void_p, C.c_uint64, C.POINTER(LudaResult)]
+    L.luda_compact_dev_noalloc.restype = C.c_int
     L.luda_compact_batch.argtypes = [C.c_void_p, C.POINTER(LudaJob), C.c_uint32, C.c_int, C.POINTER(LudaResult)]
     L.luda_compact_batch.restype = C.c_int
     L.luda_build_tables_dev.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -346,6 +349,18 @@ class Context:
         r = LudaResult()
         lib().luda_compact_dev(self._h, bufs, len(inputs), C.byref(o), C.byref(r))
         return _take(self._h, r, device=True, materialize=materialize)
+
+    def compact_dev_noalloc(self, inputs: Sequence, opts: dict, out, materialize: bool = True) -> Result:
+        """compact_dev without device allocations: working buffers in the
+        library's static scratch memory, output tables written into `out` (a
+        torch uint8 cuda tensor).  The returned tables view `out` unless
+        materialize is a function (e.g. a clone) or False."""
+        bufs = _dev_bufs(inputs)
+        o = options(opts)
+        r = LudaResult()
+        lib().luda_compact_dev_noalloc(self._h, bufs, len(inputs), C.byref(o),
+                                       C.c_void_p(out.data_ptr() if out.numel() else None), out.numel(), C.byref(r))
+        return _take(self._h, r, device=True, materialize=materialize if materialize is not True else (lambda t: t))
 
     def compact_batch(self, jobs: Sequence, device_inputs: bool, materialize: bool = True) -> List[Result]:
         """jobs: sequence of (inputs, options dict)."""

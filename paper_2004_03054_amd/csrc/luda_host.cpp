@@ -198,6 +198,16 @@ struct luda_ctx {
   std::map<std::string, DBuf> bufs;
   uint64_t call_gen = 0;   // calls so far (begin_call)
   uint64_t mem_limit = 0;  // most device bytes the named buffers may hold at once (0: no limit)
+  // luda_compact_dev_noalloc: working buffers carved from the device's static
+  // scratch array and output tables written to the caller's buffer
+  struct Arena {
+    uint8_t* base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+    std::map<std::string, std::pair<void*, size_t>> named;
+    uint8_t* out = nullptr;
+    uint64_t out_cap = 0;
+  };
+  Arena* arena = nullptr;
   luda_allocator alloc{};  // caller's device allocator (luda_set_allocator); alloc.alloc == NULL: hipMalloc
   // pinned host memory: readbacks (written by k_mail) and staged uploads
   uint8_t* mail = nullptr;
@@ -334,10 +344,27 @@ void fit_limit(luda_ctx* c, const std::string& name, size_t want) {
                                std::to_string(c->mem_limit) + " bytes (" + name + ")"};
 }
 
+// a named buffer of the current call inside the scratch arena: reused when
+// large enough, else carved anew after everything the call has carved so far
+void* arena_buf(luda_ctx* c, const std::string& name, size_t bytes) {
+  luda_ctx::Arena& a = *c->arena;
+  auto it = a.named.find(name);
+  if (it != a.named.end() && it->second.second >= bytes) return it->second.first;
+  const size_t off = (a.used + 255) & ~size_t(255);
+  if (off > a.cap || bytes > a.cap - off)
+    throw Fail{LUDA_NOMEM, "the call's working buffers need more than the " + std::to_string(a.cap) +
+                               " bytes of static scratch memory (at " + name + ")"};
+  a.used = off + bytes;
+  a.peak = std::max(a.peak, a.used);
+  a.named[name] = {a.base + off, bytes};
+  return a.base + off;
+}
+
 template <typename T>
 T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   bytes = (bytes + 255) & ~size_t(255);
+  if (c->arena) return (T*)arena_buf(c, name, bytes);
   c->bufs[name].gen = c->call_gen;
   DBuf& b = c->bufs[name];
   if (b.cap < bytes) {
@@ -371,6 +398,11 @@ T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
 // counters that the kernels leave at zero: zero-filled when (re)allocated
 void fill_u32(luda_ctx* c, void* p, uint32_t v, uint64_t n);
 uint32_t* ticket_buf(luda_ctx* c, const std::string& name, uint64_t n) {
+  if (c->arena) {  // the scratch array keeps whatever the last call left there
+    uint32_t* p = dbuf<uint32_t>(c, name, n);
+    fill_u32(c, p, 0, n);
+    return p;
+  }
   const DBuf before = c->bufs[name];
   uint32_t* p = dbuf<uint32_t>(c, name, n);
   const DBuf& now = c->bufs[name];
@@ -869,6 +901,12 @@ void upload_host(luda_ctx* c, uint8_t* dst, const uint8_t* src, size_t n) {
 // the output buffer of this call, at least `bytes`: the context's own, else
 // one from the pool (the too small one goes back there), else a new one
 uint8_t* out_buffer(luda_ctx* c, size_t bytes) {
+  if (c->arena) {
+    if (bytes > c->arena->out_cap)
+      throw Fail{LUDA_NOMEM, "the output tables need " + std::to_string(bytes) + " bytes; the output buffer has " +
+                                 std::to_string(c->arena->out_cap)};
+    return c->arena->out;
+  }
   DBuf& b = c->bufs["out_tables"];
   if (b.cap < bytes && !c->alloc.alloc) {
     const size_t want = (bytes + 255) & ~size_t(255);
@@ -1789,7 +1827,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   const double ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
   // device outputs: the output buffer is handed over to the results
   DevBlock* dblk = nullptr;
-  if (dev_out && O.total_bytes) {
+  if (dev_out && O.total_bytes && !c->arena) {
     DBuf& b = c->bufs["out_tables"];
     dblk = new DevBlock(b.p, b.cap, 0, c->device, c->alloc);
     b = DBuf{};
@@ -1820,7 +1858,9 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
       }
       r.data_size = O.file_out[f1] - base;
       r.bytes_out = r.data_size;
-      if (dev_out) {
+      if (dev_out && c->arena) {  // the caller's buffer: nothing to free
+        r.data = O.d_out + base;
+      } else if (dev_out) {
         r.data = (uint8_t*)dblk->p + base;
         ri->dev = dblk;
         dblk->refs++;
@@ -1920,6 +1960,29 @@ int luda_selftest_crc(void) {
   return 0;
 }
 
+// Static scratch memory of luda_compact_dev_noalloc: one copy per GPU, held
+// until the process ends.  Host code never uses the array's name as an
+// address: the device address of each GPU's copy is looked up once, with that
+// device current, and kept here.
+static __device__ __align__(256) uint8_t scratch[LUDA_SCRATCH_BYTES];
+static std::mutex scratch_mu;
+static std::map<int, uint8_t*> scratch_ptr;  // device -> address of its copy of scratch
+
+static void scratch_setup(int device) {
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (scratch_ptr.count(device)) return;
+  void* p = nullptr;
+  HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Fail{LUDA_DEVICE, "no device address for the static scratch array"};
+  scratch_ptr[device] = (uint8_t*)p;
+}
+
+static uint8_t* scratch_of(int device) {
+  std::lock_guard<std::mutex> g(scratch_mu);
+  auto it = scratch_ptr.find(device);
+  return it == scratch_ptr.end() ? nullptr : it->second;
+}
+
 int luda_ctx_create(int device, luda_ctx** out) {
   if (!out) return LUDA_INVALID_ARG;
   *out = nullptr;
@@ -1948,6 +2011,7 @@ int luda_ctx_create(int device, luda_ctx** out) {
     c->stage_cap = 16u << 20;
     HIPCK(hipHostMalloc((void**)&c->stage, c->stage_cap, hipHostMallocCoherent));
     c->timing = getenv("LUDA_STAGE_TIMES") != nullptr;
+    scratch_setup(device);
   });
   if (st != LUDA_OK) {
     if (c->mail) (void)hipHostFree(c->mail);
@@ -2025,7 +2089,7 @@ static int run_guarded(luda_ctx* c, const luda_job* jobs, uint32_t n, bool dev, 
     HIPCK(hipSetDevice(c->device));
     run_batch(c, jobs, n, dev, res);
   });
-  if (st == LUDA_NOMEM) {
+  if (st == LUDA_NOMEM && !c->arena) {
     // buffers sized for a call that did not fit are given back: a later,
     // smaller call starts from nothing rather than from their sizes
     (void)guarded(c, [&] {
@@ -2080,6 +2144,31 @@ static int compact_one(luda_ctx* c, const luda_buf* inputs, uint32_t n, const lu
 
 int luda_compact(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda_options* opt, luda_result* out) {
   return compact_one(c, inputs, n, opt, out, false);
+}
+
+int luda_compact_dev_noalloc(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda_options* opt,
+                             uint8_t* out_buf, uint64_t out_cap, luda_result* out) {
+  if (!c || !out || (out_cap && !out_buf)) return LUDA_INVALID_ARG;
+  uint8_t* base = scratch_of(c->device);
+  if (!base) {
+    memset(out, 0, sizeof *out);
+    c->last_error = "no static scratch memory on this device";
+    out->status = out->error.status = LUDA_DEVICE;
+    return LUDA_DEVICE;
+  }
+  // every context on this GPU shares its copy of the array: one call at a time
+  static std::mutex dev_mu[64];
+  std::lock_guard<std::mutex> g(dev_mu[c->device & 63]);
+  luda_ctx::Arena a;
+  a.base = base;
+  a.cap = LUDA_SCRATCH_BYTES;
+  a.out = out_buf;
+  a.out_cap = out_cap;
+  c->arena = &a;
+  const int rc = compact_one(c, inputs, n, opt, out, true);
+  c->arena = nullptr;
+  c->counters.emplace_back("scratch_bytes_used", (double)a.peak);
+  return rc;
 }
 
 int luda_compact_dev(luda_ctx* c, const luda_buf* inputs, uint32_t n, const luda_options* opt, luda_result* out) {
