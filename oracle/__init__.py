@@ -9,4 +9,5 @@ from .oracle import (  # noqa: F401
     put_varint64, get_varint32, get_varint64,
     bloom_build, bloom_may_match, bloom_size,
     build_tables, build_input_tables, decode_table, compact, compact_job,
+    snappy_compress, snappy_decompress, STATUS_CODES,
 )

@@ -360,6 +360,195 @@ static void bloom_build_view(const view_t *v, uint64_t e0, uint64_t e1, uint32_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Compressed blocks (block type 1).  The paper's prototype stores blocks
+ * uncompressed and names compression as future work (Sec. IV-A); its base,
+ * LevelDB, compresses data blocks with Snappy.  The stored form of a type-1
+ * block is a Snappy raw stream, written here from the public format
+ * description: a varint32 of the uncompressed length, then elements whose
+ * tag byte's low two bits select a literal (0), a copy with an 11-bit offset
+ * and length 4..11 (1), a copy with a 16-bit offset (2) or with a 32-bit
+ * offset (3); copies may overlap the bytes they produce. */
+
+/* Decode a stream of n bytes.  Returns REF_OK and a malloc'd buffer of the
+ * declared length, or REF_CORRUPT_FORMAT with *err_off = the offset of the
+ * first element that cannot be decoded (0 for a bad length preamble, n when
+ * the stream ends before the declared length is produced). */
+int ref_snappy_decompress(const uint8_t *src, uint64_t n, uint8_t **out, uint64_t *out_len,
+                          uint64_t *err_off) {
+  *out = NULL;
+  *out_len = 0;
+  *err_off = 0;
+  uint32_t len;
+  int a = ref_get_varint32(src, src + n, &len);
+  if (!a) return REF_CORRUPT_FORMAT;
+  /* an element of b bytes yields at most 64/3 * b bytes, so a stream of n
+   * bytes never yields 22 * n: a larger declared length fails before the
+   * buffer is full */
+  uint64_t cap = len < 22 * n ? len : 22 * n;
+  uint8_t *o = (uint8_t *)malloc(cap + 1);
+  if (!o) return REF_NOMEM;
+  uint64_t ip = (uint64_t)a, op = 0;
+  while (ip < n) {
+    uint64_t t = ip;
+    uint8_t tag = src[ip++];
+    uint64_t L, off = 0;
+    int kind = tag & 3;
+    if (kind == 0) {
+      L = (uint64_t)(tag >> 2) + 1;
+      if (L > 60) {
+        uint32_t nb = (uint32_t)(L - 60); /* 1..4 length bytes follow */
+        if (nb > n - ip) goto bad;
+        L = 0;
+        for (uint32_t k = 0; k < nb; k++) L |= (uint64_t)src[ip + k] << (8 * k);
+        L += 1;
+        ip += nb;
+      }
+      if (L > n - ip || L > len - op) goto bad;
+      memcpy(o + op, src + ip, L);
+      ip += L;
+      op += L;
+      continue;
+    }
+    if (kind == 1) {
+      if (1 > n - ip) goto bad;
+      L = ((tag >> 2) & 7) + 4;
+      off = ((uint64_t)(tag >> 5) << 8) | src[ip];
+      ip += 1;
+    } else if (kind == 2) {
+      if (2 > n - ip) goto bad;
+      L = (uint64_t)(tag >> 2) + 1;
+      off = (uint64_t)src[ip] | ((uint64_t)src[ip + 1] << 8);
+      ip += 2;
+    } else {
+      if (4 > n - ip) goto bad;
+      L = (uint64_t)(tag >> 2) + 1;
+      off = rd32(src + ip);
+      ip += 4;
+    }
+    if (off == 0 || off > op || L > len - op) goto bad;
+    for (uint64_t k = 0; k < L; k++) o[op + k] = o[op - off + k];
+    op += L;
+    continue;
+  bad:
+    free(o);
+    *err_off = t;
+    return REF_CORRUPT_FORMAT;
+  }
+  if (op != len) {
+    free(o);
+    *err_off = n;
+    return REF_CORRUPT_FORMAT;
+  }
+  *out = o;
+  *out_len = len;
+  return REF_OK;
+}
+
+/* The writer's compressor.  Any valid stream decodes to the same bytes; the
+ * bytes of the stream itself follow from these rules, which the GPU writer
+ * follows as well:
+ *   - the block is cut into 64 KiB fragments; copies stay inside a fragment;
+ *   - inside a fragment, positions are taken in groups of 64; each position p
+ *     with 4 bytes left looks up a 4096-entry table under the hash of those
+ *     4 bytes (Knuth's multiplicative hash: the little-endian word times
+ *     0x9E3779B1, top 12 bits), whose entry is the last earlier position with
+ *     that hash among the groups before p's group; after the group's lookups,
+ *     every position of the group is entered, later positions last;
+ *   - parsing is greedy from the fragment start: at position p, if its
+ *     candidate's 4 bytes equal p's, the copy runs as far as the bytes keep
+ *     agreeing (up to the fragment end) and p moves past it; otherwise p
+ *     moves on by one and the byte joins the pending literal;
+ *   - a literal is one element however long; a copy of length L at offset d
+ *     is split into pieces of 64 while L >= 68, one of 60 if L is then above
+ *     64, and a last piece in the 2-byte form (tag 1) when it is at most 11
+ *     long with d < 2048, else in the 3-byte form (tag 2). */
+
+#define SNAPPY_FRAGMENT 65536u
+#define SNAPPY_GROUP 64u
+#define SNAPPY_HASH_BITS 12
+
+uint64_t ref_snappy_max(uint64_t n) { return n + 5 * (n / SNAPPY_FRAGMENT + 1) + 5; }
+
+static uint32_t snappy_hash(uint32_t v) { return (v * 0x9E3779B1u) >> (32 - SNAPPY_HASH_BITS); }
+
+static uint64_t put_literal(uint8_t *d, const uint8_t *s, uint64_t k) {
+  if (k == 0) return 0;
+  uint64_t p = 0, m = k - 1;
+  if (m < 60) {
+    d[p++] = (uint8_t)(m << 2);
+  } else {
+    uint32_t nb = 1;
+    while (nb < 4 && (m >> (8 * nb))) nb++;
+    d[p++] = (uint8_t)((59 + nb) << 2);
+    for (uint32_t i = 0; i < nb; i++) d[p++] = (uint8_t)(m >> (8 * i));
+  }
+  memcpy(d + p, s, k);
+  return p + k;
+}
+
+static uint64_t put_copy_piece(uint8_t *d, uint64_t off, uint64_t L) {
+  if (L <= 11 && off < 2048) {
+    d[0] = (uint8_t)(1 | ((L - 4) << 2) | ((off >> 8) << 5));
+    d[1] = (uint8_t)(off & 0xFF);
+    return 2;
+  }
+  d[0] = (uint8_t)(2 | ((L - 1) << 2));
+  d[1] = (uint8_t)(off & 0xFF);
+  d[2] = (uint8_t)(off >> 8);
+  return 3;
+}
+
+static uint64_t put_copy(uint8_t *d, uint64_t off, uint64_t L) {
+  uint64_t p = 0;
+  while (L >= 68) {
+    d[p++] = (uint8_t)(2 | (63 << 2));
+    d[p++] = (uint8_t)(off & 0xFF);
+    d[p++] = (uint8_t)(off >> 8);
+    L -= 64;
+  }
+  if (L > 64) {
+    d[p++] = (uint8_t)(2 | (59 << 2));
+    d[p++] = (uint8_t)(off & 0xFF);
+    d[p++] = (uint8_t)(off >> 8);
+    L -= 60;
+  }
+  return p + put_copy_piece(d + p, off, L);
+}
+
+/* Compress n bytes into dst (ref_snappy_max(n) bytes); returns the length. */
+uint64_t ref_snappy_compress(const uint8_t *src, uint64_t n, uint8_t *dst) {
+  uint64_t q = (uint64_t)ref_put_varint64(dst, n);
+  int32_t table[1 << SNAPPY_HASH_BITS];
+  int32_t cand[SNAPPY_GROUP];
+  for (uint64_t f0 = 0; f0 < n; f0 += SNAPPY_FRAGMENT) {
+    const uint8_t *r = src + f0;
+    uint64_t m = n - f0 < SNAPPY_FRAGMENT ? n - f0 : SNAPPY_FRAGMENT;
+    for (uint32_t h = 0; h < (1u << SNAPPY_HASH_BITS); h++) table[h] = -1;
+    uint64_t pos = 0, lit = 0;
+    for (uint64_t b = 0; b < m; b += SNAPPY_GROUP) {
+      uint64_t e = b + SNAPPY_GROUP < m ? b + SNAPPY_GROUP : m;
+      for (uint64_t p = b; p < e; p++) cand[p - b] = p + 4 <= m ? table[snappy_hash(rd32(r + p))] : -1;
+      for (uint64_t p = b; p < e && p + 4 <= m; p++) table[snappy_hash(rd32(r + p))] = (int32_t)p;
+      while (pos < e) {
+        int32_t c = cand[pos - b];
+        if (c >= 0 && memcmp(r + c, r + pos, 4) == 0) {
+          uint64_t L = 4;
+          while (pos + L < m && r[c + L] == r[pos + L]) L++;
+          q += put_literal(dst + q, r + lit, pos - lit);
+          q += put_copy(dst + q, pos - (uint64_t)c, L);
+          pos += L;
+          lit = pos;
+        } else {
+          pos++;
+        }
+      }
+    }
+    q += put_literal(dst + q, r + lit, m - lit);
+  }
+  return q;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Phase 3 "Pack" (Sec. II-A): group entries into data blocks by the block
  * size, prefix-compress each key against the previous key of its block (every
  * R-th entry of a block is a restart point and stores its key whole), then
@@ -396,13 +585,41 @@ typedef struct {
   buf_t ikey;
 } packer_t;
 
-static void append_block(buf_t *out, const uint8_t *contents, uint64_t n) {
+static void append_typed_block(buf_t *out, const uint8_t *contents, uint64_t n, uint8_t type) {
   uint8_t tr[5];
-  tr[0] = 0; /* block type: no compression (Sec. IV-A: compression left out) */
+  tr[0] = type;
   uint32_t crc = ref_crc32c_extend(ref_crc32c(contents, n), tr, 1);
   put_fixed32(tr + 1, ref_mask_crc(crc));
   buf_put(out, contents, n);
   buf_put(out, tr, 5);
+}
+
+/* filter, metaindex and index blocks, and data blocks without compression:
+ * block type 0 (the prototype stores every block uncompressed, Sec. IV-A) */
+static void append_block(buf_t *out, const uint8_t *contents, uint64_t n) {
+  append_typed_block(out, contents, n, 0);
+}
+
+/* A data block with compression on: stored as a type-1 block when the
+ * compressed form saves at least an eighth of the raw bytes, else as type 0
+ * (LevelDB's rule).  Returns the stored size. */
+static uint64_t append_data_block(buf_t *out, const uint8_t *contents, uint64_t n, uint32_t compression) {
+  if (compression == 1) {
+    uint8_t *z = (uint8_t *)malloc(ref_snappy_max(n));
+    if (!z) {
+      out->oom = 1;
+      return 0;
+    }
+    uint64_t zn = ref_snappy_compress(contents, n, z);
+    if (zn < n - n / 8) {
+      append_typed_block(out, z, zn, 1);
+      free(z);
+      return zn;
+    }
+    free(z);
+  }
+  append_block(out, contents, n);
+  return n;
 }
 
 static void block_reset(packer_t *pk) {
@@ -440,11 +657,10 @@ static void flush_block(packer_t *pk, uint64_t end_entry) {
   for (uint64_t i = 0; i < pk->restarts.n; i++) buf_fixed32(&pk->blk, (uint32_t)pk->restarts.p[i]);
   buf_fixed32(&pk->blk, (uint32_t)pk->restarts.n);
   vec_push(&pk->blk_off, pk->out.n - pk->file_base);
-  vec_push(&pk->blk_size, pk->blk.n);
   vec_push(&pk->blk_first, pk->blk_first_entry);
   vec_push(&pk->blk_end, end_entry);
   vec_push(&pk->block_first, pk->blk_first_entry);
-  append_block(&pk->out, pk->blk.p, pk->blk.n);
+  vec_push(&pk->blk_size, append_data_block(&pk->out, pk->blk.p, pk->blk.n, pk->opt->compression));
   block_reset(pk);
 }
 
@@ -596,7 +812,7 @@ static int pack_view(const view_t *in, const ref_options *opt, ref_result *res) 
 
 static int check_options(const ref_options *opt) {
   if (!opt || opt->block_size < 1 || opt->restart_interval < 1 || opt->bloom_bits_per_key < 1 ||
-      opt->target_file_size < 1 || opt->reserved != 0 || (opt->n_snapshots && !opt->snapshots))
+      opt->target_file_size < 1 || opt->compression > 1 || (opt->n_snapshots && !opt->snapshots))
     return REF_INVALID_ARG;
   for (uint32_t i = 0; i < opt->n_snapshots; i++)
     if (opt->snapshots[i] >> 56 || (i && opt->snapshots[i] <= opt->snapshots[i - 1])) return REF_INVALID_ARG;
@@ -726,7 +942,7 @@ corrupt:
 
 /* Read the 5-byte trailer of the block at [off, off + size): the checksum
  * covers the contents and the type byte. */
-static blk_err check_trailer(const uint8_t *sst, uint64_t off, uint64_t size) {
+static blk_err check_trailer(const uint8_t *sst, uint64_t off, uint64_t size, int allow_snappy) {
   blk_err e = {REF_OK, REF_PHASE_TRAILER, 0};
   const uint8_t *c = sst + off;
   uint32_t stored = ref_unmask_crc(rd32(c + size + 1));
@@ -735,7 +951,36 @@ static blk_err check_trailer(const uint8_t *sst, uint64_t off, uint64_t size) {
     e.status = REF_CORRUPT_CHECKSUM;
     return e;
   }
-  if (c[size] != 0) e.status = REF_UNSUPPORTED; /* compressed blocks are not supported */
+  /* type 0: stored raw; type 1 (Snappy): data blocks only */
+  if (c[size] > (allow_snappy ? 1 : 0)) e.status = REF_UNSUPPORTED;
+  return e;
+}
+
+/* The raw contents of a data block whose trailer checked out: the stored
+ * bytes themselves (type 0), or their decompression (type 1), kept in *keep
+ * until the job ends (decoded values point into it).  A stream that cannot
+ * be decoded is a trailer-phase error at the offending element's offset. */
+static blk_err block_contents(const uint8_t *sst, uint64_t off, uint64_t size, const uint8_t **raw,
+                              uint64_t *raw_size, vec_t *keep) {
+  blk_err e = {REF_OK, REF_PHASE_TRAILER, 0};
+  *raw = sst + off;
+  *raw_size = size;
+  if (sst[off + size] == 0) return e;
+  uint8_t *z;
+  uint64_t zn, at;
+  e.status = ref_snappy_decompress(sst + off, size, &z, &zn, &at);
+  if (e.status != REF_OK) {
+    e.offset = at;
+    return e;
+  }
+  vec_push(keep, (uint64_t)(uintptr_t)z);
+  if (keep->oom) {
+    free(z);
+    e.status = REF_NOMEM;
+    return e;
+  }
+  *raw = z;
+  *raw_size = zn;
   return e;
 }
 
@@ -763,6 +1008,7 @@ static int index_visit(void *vctx, const uint8_t *key, uint64_t klen, const uint
 typedef struct {
   buf_t keys;
   vec_t koff, tags, vptr, vlen, input_first;
+  vec_t raw; /* decompressed data blocks (their values are pointed into) */
   int have_prev;
   uint64_t prev_koff, prev_klen, prev_tag;
 } dec_t;
@@ -828,7 +1074,7 @@ static int decode_one(const uint8_t *sst, uint64_t size, uint32_t input, dec_t *
   (void)msize;
   /* index block */
   err->where = REF_WHERE_INDEX;
-  blk_err be = check_trailer(sst, ioff, isize);
+  blk_err be = check_trailer(sst, ioff, isize, 0);
   index_ctx ix;
   memset(&ix, 0, sizeof ix);
   ix.limit = limit;
@@ -846,8 +1092,11 @@ static int decode_one(const uint8_t *sst, uint64_t size, uint32_t input, dec_t *
   d->have_prev = 0;
   for (uint64_t k = 0; k < ix.off.n; k++) {
     err->block = k;
-    be = check_trailer(sst, ix.off.p[k], ix.size.p[k]);
-    if (be.status == REF_OK) be = walk_block(sst + ix.off.p[k], ix.size.p[k], data_visit, d, &key);
+    be = check_trailer(sst, ix.off.p[k], ix.size.p[k], 1);
+    const uint8_t *raw = NULL;
+    uint64_t raw_size = 0;
+    if (be.status == REF_OK) be = block_contents(sst, ix.off.p[k], ix.size.p[k], &raw, &raw_size, &d->raw);
+    if (be.status == REF_OK) be = walk_block(raw, raw_size, data_visit, d, &key);
     if (be.status != REF_OK) {
       err->status = be.status;
       err->phase = be.phase;
@@ -866,6 +1115,8 @@ static int decode_one(const uint8_t *sst, uint64_t size, uint32_t input, dec_t *
 }
 
 static void dec_free(dec_t *d) {
+  for (uint64_t i = 0; i < d->raw.n; i++) free((void *)(uintptr_t)d->raw.p[i]);
+  free(d->raw.p);
   free(d->keys.p);
   free(d->koff.p);
   free(d->tags.p);

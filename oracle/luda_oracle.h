@@ -20,6 +20,13 @@
  * entries use the verbatim last internal key of each block; the filter block
  * holds one Bloom filter per 2 KiB window of block start offsets, built with
  * XXH64 double hashing at the configured bits per key (10 in the paper).
+ * With compression on, data blocks are stored as Snappy raw streams (block
+ * type 1) when that saves at least an eighth of their bytes; the stream
+ * follows the deterministic rules written out above ref_snappy_compress in
+ * luda_oracle.c.  Inputs may hold type-1 data blocks whatever the option.
+ * Parity unpinned: agreement with a stock Snappy library (none is available
+ * here); the codec is pinned by hand-assembled streams, closed forms of the
+ * writer's rules and an independent decoder in the tests.
  */
 #ifndef LUDA_ORACLE_H
 #define LUDA_ORACLE_H
@@ -50,7 +57,7 @@ typedef struct {
   uint64_t target_file_size;   /* output file cut threshold (>= 1) */
   const uint64_t *snapshots;   /* live snapshot sequence numbers, strictly ascending, < 2^56 */
   uint32_t n_snapshots;        /* 0: no snapshots */
-  uint32_t reserved;           /* 0 */
+  uint32_t compression;        /* data blocks: 0 stored raw, 1 Snappy when it saves >= 1/8 */
 } ref_options;
 
 typedef struct {
@@ -115,6 +122,14 @@ uint64_t ref_bloom_size(uint64_t n, uint32_t bits_per_key);
 void ref_bloom_build(const uint8_t *keys, const uint64_t *koff, uint64_t n, uint32_t bits_per_key,
                      uint8_t *out);
 int ref_bloom_may_match(const uint8_t *filter, uint64_t len, const uint8_t *key, uint64_t klen);
+
+/* Snappy raw streams (block type 1): decompress returns REF_OK with a
+ * malloc'd buffer, or REF_CORRUPT_FORMAT with *err_off at the first element
+ * that cannot be decoded; compress writes at most ref_snappy_max(n) bytes. */
+int ref_snappy_decompress(const uint8_t *src, uint64_t n, uint8_t **out, uint64_t *out_len,
+                          uint64_t *err_off);
+uint64_t ref_snappy_max(uint64_t n);
+uint64_t ref_snappy_compress(const uint8_t *src, uint64_t n, uint8_t *dst);
 
 /* Phase 3 over an already ordered list (used to write input tables too). */
 int ref_build_tables(const ref_entries *in, const ref_options *opt, ref_result **out);

@@ -15,6 +15,7 @@ _LIB = os.path.join(_HERE, "libluda_oracle.so")
 
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "CORRUPT_FORMAT", -3: "CORRUPT_CHECKSUM",
                 -4: "UNSORTED_INPUT", -5: "UNSUPPORTED", -6: "NOMEM"}
+STATUS_CODES = {v: k for k, v in STATUS_NAMES.items()}
 WHERE_NAMES = {0: "footer", 1: "index", 2: "data"}
 PHASE_NAMES = {0: "trailer", 1: "restarts", 2: "entries"}
 
@@ -33,7 +34,7 @@ class _Options(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("restart_interval", C.c_uint32),
                 ("bloom_bits_per_key", C.c_uint32), ("bottommost", C.c_uint32),
                 ("target_file_size", C.c_uint64), ("snapshots", C.POINTER(C.c_uint64)),
-                ("n_snapshots", C.c_uint32), ("reserved", C.c_uint32)]
+                ("n_snapshots", C.c_uint32), ("compression", C.c_uint32)]
 
 
 class _Error(C.Structure):
@@ -93,6 +94,12 @@ def lib():
         L.ref_compact.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_uint32,
                                   C.POINTER(_Options), C.POINTER(C.POINTER(_Result)), C.POINTER(_Error)]
         L.ref_compact.restype = C.c_int
+        L.ref_snappy_decompress.argtypes = [u8p, u64, C.POINTER(C.POINTER(C.c_uint8)), C.POINTER(C.c_uint64),
+                                            C.POINTER(C.c_uint64)]
+        L.ref_snappy_decompress.restype = C.c_int
+        L.ref_snappy_max.argtypes = [u64]; L.ref_snappy_max.restype = C.c_uint64
+        L.ref_snappy_compress.argtypes = [u8p, u64, u8p]; L.ref_snappy_compress.restype = C.c_uint64
+        L.free.argtypes = [C.c_void_p]; L.free.restype = None
         L.ref_free_result.argtypes = [C.POINTER(_Result)]; L.ref_free_result.restype = None
         L.ref_free_decoded.argtypes = [C.POINTER(_Decoded)]; L.ref_free_decoded.restype = None
         _lib = L
@@ -176,6 +183,28 @@ def bloom_may_match(filt: bytes, key: bytes) -> bool:
     return bool(lib().ref_bloom_may_match(_ptr(f), f.size, _ptr(k), len(key)))
 
 
+def snappy_compress(b) -> bytes:
+    """The writer's Snappy stream for a block's raw bytes."""
+    a = _u8(b) if len(b) else np.zeros(1, np.uint8)
+    out = np.zeros(lib().ref_snappy_max(len(b)), dtype=np.uint8)
+    n = lib().ref_snappy_compress(_ptr(a), len(b), _ptr(out))
+    return out[:n].tobytes()
+
+
+def snappy_decompress(b):
+    """(status, bytes or None, error offset) for a Snappy stream."""
+    a = _u8(b) if len(b) else np.zeros(1, np.uint8)
+    p = C.POINTER(C.c_uint8)()
+    n = C.c_uint64()
+    at = C.c_uint64()
+    st = lib().ref_snappy_decompress(_ptr(a), len(b), C.byref(p), C.byref(n), C.byref(at))
+    if st != 0:
+        return st, None, at.value
+    out = bytes(C.string_at(p, n.value)) if n.value else b""
+    lib().free(C.cast(p, C.c_void_p))
+    return st, out, 0
+
+
 def _opts(o: dict) -> _Options:
     """Options for the C oracle; o["snapshots"] (optional) lists the live
     snapshot sequence numbers in ascending order."""
@@ -183,7 +212,7 @@ def _opts(o: dict) -> _Options:
     arr = (C.c_uint64 * max(1, len(snaps)))(*snaps)
     r = _Options(int(o["block_size"]), int(o["restart_interval"]), int(o["bloom_bits_per_key"]),
                  int(o["bottommost"]), int(o["target_file_size"]), C.cast(arr, C.POINTER(C.c_uint64)),
-                 len(snaps), 0)
+                 len(snaps), int(o.get("compression", 0)))
     r._keep = arr  # the array lives as long as the options
     return r
 

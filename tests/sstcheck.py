@@ -89,18 +89,69 @@ class Entry:
 @dataclass
 class Block:
     offset: int
-    size: int
+    size: int  # stored bytes (the handle's size)
     entries: List[Entry]
     restarts: List[int]
+    raw_size: int = 0  # bytes of the raw contents
 
 
-def read_block(f: bytes, off: int, size: int, crc_fn=crc32c_fast) -> bytes:
+def snappy_decode(z: bytes) -> bytes:
+    """A Snappy raw stream, decoded element by element (format description:
+    varint32 length, then literals (tag & 3 == 0) and copies with 1-, 2- or
+    4-byte offsets (tag & 3 == 1, 2, 3)); raises on any malformed element."""
+    n, p = varint(z, 0, len(z), 5)
+    out = bytearray()
+    while p < len(z):
+        tag = z[p]
+        p += 1
+        kind = tag & 3
+        if kind == 0:
+            ln = (tag >> 2) + 1
+            if ln > 60:
+                nb = ln - 60
+                assert p + nb <= len(z), "literal length runs past the stream"
+                ln = int.from_bytes(z[p:p + nb], "little") + 1
+                p += nb
+            assert p + ln <= len(z), "literal runs past the stream"
+            out += z[p:p + ln]
+            p += ln
+            continue
+        if kind == 1:
+            assert p + 1 <= len(z)
+            ln = 4 + ((tag >> 2) & 7)
+            off = ((tag >> 5) << 8) | z[p]
+            p += 1
+        elif kind == 2:
+            assert p + 2 <= len(z)
+            ln = (tag >> 2) + 1
+            off = int.from_bytes(z[p:p + 2], "little")
+            p += 2
+        else:
+            assert p + 4 <= len(z)
+            ln = (tag >> 2) + 1
+            off = int.from_bytes(z[p:p + 4], "little")
+            p += 4
+        assert 0 < off <= len(out), "copy offset outside the bytes produced"
+        for _ in range(ln):  # byte by byte: a copy may overlap what it writes
+            out.append(out[-off])
+    assert len(out) == n, "stream length differs from its preamble"
+    return bytes(out)
+
+
+def read_block(f: bytes, off: int, size: int, crc_fn=crc32c_fast, allow_snappy: bool = False) -> bytes:
+    """A block's raw contents: type 0 stored as is; type 1 (data blocks of
+    tables written with compression) a Snappy stream that saves at least an
+    eighth of the raw bytes."""
     assert off + size + 5 <= len(f), "block beyond file"
     c = f[off:off + size]
     t = f[off + size]
     stored = struct.unpack_from("<I", f, off + size + 1)[0]
-    assert t == 0, "block type must be 0 (uncompressed)"
+    assert t == 0 or (allow_snappy and t == 1), f"block type {t} not allowed here"
     assert stored == mask(crc_fn(f[off:off + size + 1])), "bad block checksum"
+    if t == 1:
+        raw = snappy_decode(c)
+        assert len(c) < len(raw) - len(raw) // 8, "compressed form saves less than an eighth"
+        return raw
     return c
 
 
@@ -169,7 +220,7 @@ class Table:
 
 
 def check_table(f: bytes, restart_interval: int, bits_per_key: int = 10,
-                crc_fn=crc32c_fast) -> Table:
+                crc_fn=crc32c_fast, compression: int = 0) -> Table:
     """Validate one table; returns its parsed data blocks."""
     assert len(f) >= 48
     assert struct.unpack_from("<Q", f, len(f) - 8)[0] == MAGIC, "bad magic"
@@ -191,7 +242,7 @@ def check_table(f: bytes, restart_interval: int, bits_per_key: int = 10,
         bsize, q = varint(ie.value, q, len(ie.value))
         assert q == len(ie.value)
         assert boff == pos, "data blocks must tile the data region"
-        c = read_block(f, boff, bsize, crc_fn)
+        c = read_block(f, boff, bsize, crc_fn, allow_snappy=bool(compression))
         ents, rest = parse_entries(c)
         assert ents, "empty data block"
         # writer restart pattern: a restart every R entries, from entry 0
@@ -210,7 +261,7 @@ def check_table(f: bytes, restart_interval: int, bits_per_key: int = 10,
                     lcp += 1
                 assert e.shared == lcp, "shared must be the full common prefix"
         assert ie.ikey == ents[-1].ikey, "index key must be the block's last key"
-        blocks.append(Block(boff, bsize, ents, rest))
+        blocks.append(Block(boff, bsize, ents, rest, len(c)))
         pos = boff + bsize + 5
     data_bytes = pos
     # metaindex -> filter
@@ -249,7 +300,8 @@ def check_output(files: List[bytes], options: dict) -> List[Tuple[bytes, bytes]]
     bs = options["block_size"]
     target = options["target_file_size"]
     out = []
-    tables = [check_table(f, R, options["bloom_bits_per_key"]) for f in files]
+    tables = [check_table(f, R, options["bloom_bits_per_key"], compression=options.get("compression", 0))
+              for f in files]
     nblocks_total = sum(len(t.blocks) for t in tables)
     bi = 0
     for ti, t in enumerate(tables):

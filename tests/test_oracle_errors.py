@@ -113,14 +113,30 @@ def test_index_block_checksum_and_handle_range():
     assert (r.status, r.error.input, r.error.where) == (NAMES["CORRUPT_CHECKSUM"], 1, 1)
 
 
-def test_compressed_block_unsupported():
+def test_unknown_block_type_unsupported():
     job, ts = _tables()
     _, hs = handles(ts[0])
     bo, bs = hs[0]
-    ts[0][bo + bs] = 1  # block type 1 (compressed)
+    ts[0][bo + bs] = 2  # block type 2: neither raw (0) nor Snappy (1)
     reseal(ts[0], bo, bs)
     r = run(ts, job)
     assert (r.status, r.error.input, r.error.where, r.error.block) == (NAMES["UNSUPPORTED"], 0, 2, 0)
+
+
+def test_raw_contents_marked_snappy_are_a_bad_stream():
+    # a raw block relabelled type 1: its first bytes (shared 0, non_shared,
+    # value length varints) read as a Snappy preamble and elements, which
+    # fail inside the block's stored bytes in the trailer phase
+    job, ts = _tables()
+    _, hs = handles(ts[0])
+    bo, bs = hs[0]
+    ts[0][bo + bs] = 1
+    reseal(ts[0], bo, bs)
+    r = run(ts, job)
+    assert (r.status, r.error.input, r.error.where, r.error.block, r.error.phase) == \
+        (NAMES["CORRUPT_FORMAT"], 0, 2, 0, 0)
+    st, _, at = oracle.snappy_decompress(bytes(ts[0][bo:bo + bs]))
+    assert st == NAMES["CORRUPT_FORMAT"] and r.error.offset == at
 
 
 def test_restart_array_errors():

@@ -87,11 +87,15 @@ class Job:
     target_file_size: int = 2 * MiB
     name: str = ""
     meta: dict = field(default_factory=dict)
+    compression: int = 0  # 1: data blocks stored as Snappy streams when that saves >= 1/8
 
     def options(self) -> dict:
-        return dict(block_size=self.block_size, restart_interval=self.restart_interval,
-                    bloom_bits_per_key=self.bloom_bits_per_key, bottommost=self.bottommost,
-                    target_file_size=self.target_file_size)
+        o = dict(block_size=self.block_size, restart_interval=self.restart_interval,
+                 bloom_bits_per_key=self.bloom_bits_per_key, bottommost=self.bottommost,
+                 target_file_size=self.target_file_size)
+        if self.compression:
+            o["compression"] = self.compression
+        return o
 
     def table_options(self) -> dict:
         """Options for writing this job's *input* tables (one file per run)."""
@@ -489,3 +493,45 @@ def tiny_job(seed: int, n_inputs: int = 3, entries: int = 40, key_alphabet: int 
     return Job(runs, block_size=block_size, restart_interval=restart_interval,
                bloom_bits_per_key=bloom_bits_per_key, bottommost=bottommost,
                target_file_size=target_file_size, name=f"tiny-{mode}-{seed}")
+
+
+# ----------------------------------------------------------------------------
+# compressible variants (block compression, the prototype's future work)
+
+
+def compressible(job: Job, seed: int = 0, compression: int = 1) -> Job:
+    """The same job (keys, tags, value lengths) with values that compress, and
+    compression switched on for its input and output tables.
+
+    Even-numbered values repeat a short random pattern (1-12 bytes, from a pool
+    of 64), so they hold copies at small offsets; odd-numbered values are
+    slices of one 16 KiB random text, so entries of a block share substrings
+    at offsets up to a few KiB.  One stretch of 40 consecutive entries in four
+    (drawn at random) keeps random values, so some blocks do not compress
+    enough and are stored raw.
+    """
+    rng = np.random.default_rng(seed ^ 0x534E4150)  # "SNAP"
+    pats = [rng.bytes(int(rng.integers(1, 13))) for _ in range(64)]
+    text = np.frombuffer(rng.bytes(16384), dtype=np.uint8)
+    runs = []
+    for r in job.runs:
+        vl = np.diff(r.voff).astype(np.int64)
+        out = np.empty(int(r.voff[-1]), dtype=np.uint8)
+        raw = rng.integers(0, 4, r.n // 40 + 1) == 0
+        for i in range(r.n):
+            a, n = int(r.voff[i]), int(vl[i])
+            if n == 0:
+                continue
+            if raw[i // 40]:
+                out[a:a + n] = np.frombuffer(rng.bytes(n), dtype=np.uint8)
+            elif i % 2 == 0:
+                p = np.frombuffer(pats[int(rng.integers(0, 64))], dtype=np.uint8)
+                out[a:a + n] = np.resize(p, n)
+            else:
+                o = int(rng.integers(0, 16384))
+                out[a:a + n] = np.resize(np.roll(text, -o), n)
+        runs.append(Run(r.keys, r.koff, r.tags, out, r.voff))
+    return Job(runs, block_size=job.block_size, restart_interval=job.restart_interval,
+               bloom_bits_per_key=job.bloom_bits_per_key, bottommost=job.bottommost,
+               target_file_size=job.target_file_size, name=job.name + "-snappy", meta=dict(job.meta),
+               compression=compression)
