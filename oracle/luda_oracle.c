@@ -467,7 +467,10 @@ int ref_snappy_decompress(const uint8_t *src, uint64_t n, uint8_t **out, uint64_
 #define SNAPPY_GROUP 64u
 #define SNAPPY_HASH_BITS 12
 
-uint64_t ref_snappy_max(uint64_t n) { return n + 5 * (n / SNAPPY_FRAGMENT + 1) + 5; }
+/* A literal of k > 60 bytes has a header of 2 or more bytes and the copy
+ * after it may save only one byte (4 raw bytes in 3), so a stream can exceed
+ * its input by about one byte per 65; n / 6 + 32 covers that with room. */
+uint64_t ref_snappy_max(uint64_t n) { return n + n / 6 + 32; }
 
 static uint32_t snappy_hash(uint32_t v) { return (v * 0x9E3779B1u) >> (32 - SNAPPY_HASH_BITS); }
 

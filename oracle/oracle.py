@@ -20,14 +20,22 @@ WHERE_NAMES = {0: "footer", 1: "index", 2: "data"}
 PHASE_NAMES = {0: "trailer", 1: "restarts", 2: "entries"}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into oracle/libluda_oracle.so."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
-    return _LIB
+_SAN_LIB = os.path.join(_HERE, "libluda_oracle_san.so")
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc into oracle/libluda_oracle.so; with
+    sanitize, an AddressSanitizer + UndefinedBehaviorSanitizer build into
+    oracle/libluda_oracle_san.so (loaded when LUDA_ORACLE_SANITIZE=1, with
+    libasan preloaded into the interpreter)."""
+    lib_path = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(lib_path):
+        tmp = lib_path + ".tmp"
+        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc"] + flags + ["-std=gnu11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 class _Options(C.Structure):
@@ -71,9 +79,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        L = C.CDLL(_LIB)
+        san = os.environ.get("LUDA_ORACLE_SANITIZE") == "1"
+        path = build(force=False, sanitize=san)
+        L = C.CDLL(path)
         u8p, u64 = C.c_void_p, C.c_uint64
         L.ref_crc32c.argtypes = [u8p, u64]; L.ref_crc32c.restype = C.c_uint32
         L.ref_crc32c_bitwise.argtypes = [u8p, u64]; L.ref_crc32c_bitwise.restype = C.c_uint32

@@ -272,3 +272,19 @@ def test_a_bad_copy_in_a_data_block_is_reported_at_its_element():
     st, err, _ = oracle.decode_table(bytes(t), 1)
     assert st == oracle.STATUS_CODES["CORRUPT_FORMAT"]
     assert (err.input, err.where, err.phase, err.block, err.offset) == (1, 2, 0, k, at)
+
+
+def test_worst_case_expansion_stays_within_the_bound():
+    # 61 random bytes, then 4 bytes repeated from 2080 back (a 3-byte copy
+    # when it is found): such a pair costs 2 + 61 + 3 bytes for 65 raw bytes
+    rng = np.random.default_rng(5)
+    b = bytearray(rng.bytes(200000))
+    for i in range(2080 // 65 + 1, len(b) // 65):
+        p = 65 * i + 61
+        b[p:p + 4] = b[p - 2080:p - 2076]
+    b = bytes(b)
+    z = oracle.snappy_compress(b)
+    assert len(z) > len(b)  # it does expand
+    assert len(z) <= oracle.lib().ref_snappy_max(len(b))
+    st, back, _ = oracle.snappy_decompress(z)
+    assert st == 0 and back == b
