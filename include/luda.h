@@ -81,7 +81,9 @@ typedef struct {
                                   memory (for every entry point); copied during the call (by
                                   luda_server_submit: before it returns); NULL when n_snapshots is 0 */
   uint32_t n_snapshots;        /* at most LUDA_MAX_SNAPSHOTS; 0: no snapshots */
-  uint32_t reserved;           /* must be 0 */
+  uint32_t compression;        /* output data blocks: 0 stored raw (the prototype, Sec. IV-A); 1 stored as
+                                  Snappy streams (block type 1) when that saves >= 1/8 of their bytes.
+                                  Inputs may hold type-1 data blocks whatever this is. */
 } luda_options;
 #define LUDA_MAX_SNAPSHOTS 65536
 

@@ -28,7 +28,7 @@ class LudaOptions(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("restart_interval", C.c_uint32),
                 ("bloom_bits_per_key", C.c_uint32), ("bottommost", C.c_uint32),
                 ("target_file_size", C.c_uint64), ("snapshots", C.POINTER(C.c_uint64)),
-                ("n_snapshots", C.c_uint32), ("reserved", C.c_uint32)]
+                ("n_snapshots", C.c_uint32), ("compression", C.c_uint32)]
 
 
 class LudaError(C.Structure):
@@ -172,7 +172,8 @@ def options(d: dict) -> LudaOptions:
     arr = (C.c_uint64 * max(1, len(snaps)))(*snaps)
     o = LudaOptions(int(d["block_size"]), int(d["restart_interval"]), int(d["bloom_bits_per_key"]),
                     int(d["bottommost"]), int(d["target_file_size"]),
-                    C.cast(arr, C.POINTER(C.c_uint64)) if snaps else None, len(snaps), 0)
+                    C.cast(arr, C.POINTER(C.c_uint64)) if snaps else None, len(snaps),
+                    int(d.get("compression", 0)))
     o._keep = arr  # the array lives as long as the options
     return o
 
@@ -206,7 +207,11 @@ class Result:
     ms_total: float = 0.0
     file_sizes: List[int] = field(default_factory=list)
     # per file: (smallest key offset, length, largest key offset, length), offsets inside the file
+    # (a table whose first data block is stored compressed keeps its smallest key right after it,
+    # so that offset is the table's size)
     key_ranges: List[tuple] = field(default_factory=list)
+    # per file: (smallest internal key, largest internal key) as bytes, read from the result
+    key_bytes: List[tuple] = field(default_factory=list)
 
     @property
     def name(self) -> str:
@@ -230,6 +235,15 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
     for i in range(r.num_files if r.status == 0 else 0):
         f = r.files[i]
         res.key_ranges.append((f.smallest_off - f.offset, f.smallest_len, f.largest_off - f.offset, f.largest_len))
+        if materialize is not False:
+            if device:
+                import torch  # device memory plumbing only
+                def grab(off, n):
+                    return torch.as_tensor(_DevView(r.data + off, n), device="cuda").cpu().numpy().tobytes()
+            else:
+                def grab(off, n):
+                    return C.string_at(r.data + off, n)
+            res.key_bytes.append((grab(f.smallest_off, f.smallest_len), grab(f.largest_off, f.largest_len)))
     if r.status == 0 and r.num_files and callable(materialize):
         # apply a function to each output table in place, before the library
         # frees it (no copy): a torch uint8 tensor over device outputs, a

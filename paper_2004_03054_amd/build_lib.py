@@ -18,8 +18,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libluda.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_decode.hip", "k_merge.hip", "k_plan.hip", "k_encode.hip", "k_misc.hip", "luda_host.cpp",
-           "luda_server.cpp"]
+SOURCES = ["k_decode.hip", "k_merge.hip", "k_plan.hip", "k_encode.hip", "k_misc.hip", "k_snappy.hip",
+           "luda_host.cpp", "luda_server.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -68,11 +68,41 @@ __device__ inline void blk_err(const WalkSet& ws, const Inputs& in, uint32_t b, 
   report_err(&err[in.job[g]], err_key(in.local[g], ws.where, ws.local[b], phase, off, code));
 }
 
-// restart count of every block (size >= 4, 1 <= n <= (size - 4) / 4)
-__global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long long* err) {
+// restart count of every block (size >= 4, 1 <= n <= (size - 4) / 4).
+// Data blocks, first pass (z.cap set): a block of type 1 (Snappy) gets no
+// restart count yet; it is given staging room for its raw bytes instead (the
+// declared length, but no more than 22x its stored bytes: an element of b
+// bytes yields at most 64/3 b, so a longer declared length cannot be
+// produced), counted in z.tot.  Second pass (z.only_z): the blocks that were
+// decompressed, now pointing at their raw bytes.
+__global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long long* err, ZPass z) {
   const uint64_t nb = *ws.n_dev;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x) {
+    if (z.only_z && (!z.cap[b] || !z.ok[b])) {
+      if (z.cap[b]) nr_out[b] = 0;
+      continue;
+    }
     uint32_t nr = 0;
+    if (z.cap && !z.only_z) {
+      uint64_t cap = 0;
+      if (!ws.skip[b]) {
+        const uint8_t* c = (const uint8_t*)ws.ptr[b];
+        const uint32_t size = ws.size[b];
+        if (c[size] == 1) {
+          uint32_t len = 0;
+          const uint64_t most = 22ull * size;
+          const uint64_t raw = get_varint32(c, c + size, &len) ? (len < most ? len : most) : 0;
+          cap = ((raw + 15) & ~15ull) + ZSTAGE_PAD;
+          atomicAdd(&z.tot[0], 1ull);
+          atomicAdd(&z.tot[1], (unsigned long long)cap);
+        }
+      }
+      z.cap[b] = cap;
+      if (cap) {
+        nr_out[b] = 0;
+        continue;
+      }
+    }
     if (!ws.skip[b]) {
       const uint8_t* c = (const uint8_t*)ws.ptr[b];
       const uint32_t size = ws.size[b];
@@ -135,7 +165,7 @@ __device__ inline uint8_t check_crc(const WalkSet& ws, const Inputs& in, uint32_
     if (lane_id() == 0) blk_err(ws, in, b, P_TRAILER, 0, EC_CHECKSUM, err);
     return 0;
   }
-  if (type != 0) {
+  if (type > 1) {  // 0: stored raw; 1: a Snappy stream, decompressed later
     if (lane_id() == 0) blk_err(ws, in, b, P_TRAILER, 0, EC_UNSUPPORTED, err);
     return 0;
   }

@@ -91,15 +91,16 @@ __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, cons
 // a restart point (shared 0), and every index entry is a restart point whose
 // key is the last internal key of its block.
 __global__ void k_file_entries(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint64_t* ie_off,
-                               uint64_t nf) {
+                               uint64_t nf, const uint8_t* ztype) {
   const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
   const uint64_t b0 = of.b0[f], last = b0 + of.nb[f] - 1;
   of.entries[f] = ob.s0[last] + ob.cnt[last] - ob.s0[b0];
   const uint32_t e0 = surv[ob.s0[b0]];
   const uint32_t k0 = tu.ulen[e0] + 8;
-  // first data block at file offset 0: varint shared (1 byte), non_shared, value length, key
-  of.keyr[4 * f + 0] = 1 + varint_len(k0) + varint_len(tu.vlen[e0]);
+  // first data block at file offset 0: varint shared (1 byte), non_shared, value length, key;
+  // when that block is stored compressed, the key is kept right after the table
+  of.keyr[4 * f + 0] = (ztype && ztype[b0]) ? of.size[f] : 1 + varint_len(k0) + varint_len(tu.vlen[e0]);
   of.keyr[4 * f + 1] = k0;
   const uint32_t e1 = surv[ob.s0[last] + ob.cnt[last] - 1];
   const uint32_t k1 = tu.ulen[e1] + 8;

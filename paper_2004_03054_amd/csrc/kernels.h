@@ -71,7 +71,20 @@ struct WalkArgs {
   unsigned long long* err;
 };
 __global__ void k_footer(Inputs in, WalkSet idx, unsigned long long* err);
-__global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long long* err);
+// compressed data blocks (type 1): staging room per block, then the second
+// restart-count pass over the decompressed ones
+constexpr uint64_t ZSTAGE_PAD = 64;  // readable bytes after each staged raw block
+struct ZPass {
+  uint64_t* cap;             // per block: staging bytes (0: not compressed); null for index blocks
+  unsigned long long* tot;   // [0] compressed blocks, [1] staging bytes
+  const uint8_t* ok;         // second pass: the block decompressed cleanly
+  int only_z;                // second pass
+};
+__global__ void k_blk_nr(WalkSet ws, Inputs in, uint32_t* nr_out, unsigned long long* err, ZPass z);
+// one wave per compressed data block: its Snappy stream into staging (at
+// zoff), then the block table points at the raw bytes
+__global__ void k_unsnappy(WalkSet ws, Inputs in, uint8_t* ok, const uint64_t* zcap, const uint64_t* zoff,
+                           uint8_t* stage, unsigned long long* err);
 __global__ void k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
                            unsigned long long* bytes_total);
 // checksums of the inputs' index blocks against their trailers
@@ -241,7 +254,7 @@ __global__ void k_ranges(const uint64_t* ient, const uint64_t* ibase, const uint
 __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0);
 __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats);
 __global__ void k_file_entries(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint64_t* ie_off,
-                               uint64_t nf);
+                               uint64_t nf, const uint8_t* ztype);
 __global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen);
 __global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64_t* tags, const uint8_t* vals,
                          const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv);
@@ -250,5 +263,20 @@ __global__ void k_check_sorted(Tuples tu, uint32_t kw8, uint64_t n, uint32_t* ba
 // written); part and ticket as for k_crc_multi
 void launch_crc_files(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
                       uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
+
+// compressed output blocks (k_snappy.hip)
+__global__ void k_zprep(OutBlocks ob, const uint64_t* nblocks, uint64_t cap, uint32_t* zraw, uint64_t* zstride);
+__global__ void k_block_dst_stage(OutBlocks ob, const uint64_t* zoff, const JobDesc* jobs, const uint64_t* nblocks,
+                                  uint64_t cap, BlockRec* br);
+__global__ void k_zsnappy(OutBlocks ob, const JobDesc* jobs, const uint64_t* nblocks, const uint8_t* stage,
+                          const uint64_t* zoff, const uint32_t* zraw, uint8_t* zbuf, uint8_t* ztype);
+__global__ void k_zplace(const BlockRec* br, const uint64_t* nblocks, const uint8_t* stage, const uint8_t* zbuf,
+                         const uint64_t* zoff, const uint8_t* ztype, uint8_t* out);
+void launch_crc_zblocks(const BlockRec* br, const uint64_t* nblocks, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
+                        uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
+__global__ void k_zslots(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint8_t* ztype,
+                         const uint64_t* nfiles, uint64_t cap, uint64_t* stride);
+__global__ void k_zkeys(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint8_t* ztype,
+                        uint32_t kw8, uint64_t nf, uint8_t* out);
 
 }  // namespace luda

@@ -614,7 +614,7 @@ luda_error decode_err(uint64_t key, const std::vector<uint64_t>& in_size, uint32
 
 int check_opt(const luda_options* o) {
   if (!o || o->block_size == 0 || o->restart_interval == 0 || o->bloom_bits_per_key == 0 ||
-      o->target_file_size == 0 || o->reserved != 0 || o->n_snapshots > LUDA_MAX_SNAPSHOTS ||
+      o->target_file_size == 0 || o->compression > 1 || o->n_snapshots > LUDA_MAX_SNAPSHOTS ||
       (o->n_snapshots && !o->snapshots))
     return LUDA_INVALID_ARG;
   for (uint32_t i = 0; i < o->n_snapshots; i++)
@@ -935,12 +935,14 @@ struct PlanIn {
   const uint32_t* d_surv;
   std::vector<uint64_t> job_s0;  // J + 1, host copy
   const uint64_t* d_job_s0;
+  bool compress = false;  // some job stores data blocks compressed
 };
 
 struct PlanOut {
   uint64_t total_bytes = 0;
   uint8_t* d_out = nullptr;
-  std::vector<uint64_t> file_out;  // nfiles + 1
+  std::vector<uint64_t> file_out;  // nfiles + 1: where each table starts in the output buffer
+  std::vector<uint64_t> file_size;  // each table's bytes (a key slot may follow a table)
   std::vector<uint64_t> file_entries;
   std::vector<uint64_t> file_keys;  // 4 per file (k_file_entries)
   std::vector<uint64_t> job_f0;  // J + 1
@@ -949,12 +951,29 @@ struct PlanOut {
 // a result's file record: its place in the result's data and its key range
 void set_file(luda_file& x, const PlanOut& O, uint64_t f, uint64_t base) {
   x.offset = O.file_out[f] - base;
-  x.size = O.file_out[f + 1] - O.file_out[f];
+  x.size = O.file_size[f];
   x.num_entries = O.file_entries[f];
   x.smallest_off = x.offset + O.file_keys[4 * f + 0];
   x.smallest_len = O.file_keys[4 * f + 1];
   x.largest_off = x.offset + O.file_keys[4 * f + 2];
   x.largest_len = O.file_keys[4 * f + 3];
+}
+
+// the encoder over nblk output blocks (A.blk gives their destinations)
+void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk) {
+  const int waves = (int)c->tp.encode_waves;
+  int occ = 0;
+  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, 0));
+  occ = std::max(occ, 1);
+  const uint64_t want = (nblk + waves - 1) / waves;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
+  KTimer kt(c, "k_encode");
+  hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), 0, c->stream, A);
+  LAUNCH_CHECK();
+  kt.stop();
+  c->counters.emplace_back("encode_waves_per_group", (double)waves);
+  c->counters.emplace_back("encode_groups", (double)grid);
+  c->counters.emplace_back("encode_groups_per_cu", (double)occ);
 }
 
 void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
@@ -1042,8 +1061,68 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   hipLaunchKernelGGL(k_block_meta, dim3(blocks_for(OB)), dim3(256), 0, st, job_ob0, J, d_sj, P.d_jobs, seg_first,
                      sz_r, sz_n, erec, OB, ob, ent_off, entl, gapcnt);
   LAUNCH_CHECK();
-  uint64_t* ob_excl = dbuf<uint64_t>(c, "ob_excl", OB + 1);
   uint64_t* scan_tmp = dbuf<uint64_t>(c, "scan_tmp64", OB / 2048 + 8);
+  uint64_t* gap_base = dbuf<uint64_t>(c, "gap_base", OB + 1);
+  uint64_t* scan_gap = dbuf<uint64_t>(c, "scan_tmp_gap", OB / 2048 + 8);
+  EncodeArgs A{};
+  A.jobs = P.d_jobs;
+  A.ob = ob;
+  A.tu = P.tu;
+  A.surv = P.d_surv;
+  A.sz_r = sz_r;
+  A.sz_n = sz_n;
+  A.shr = shr;
+  A.nblocks = job_ob0 + J;
+  A.g_crc = c->d_crc;
+  A.ent_off = ent_off;
+  A.rec = erec;
+  A.kw8 = P.kw8;
+  A.entl = entl;
+  A.gap_base = gap_base;
+  // Compression: every block is encoded raw into staging first, then
+  // compressed; the stored sizes (ob.size / ob.full) drive the cuts below.
+  uint8_t* zstage = nullptr;
+  uint8_t* zbuf = nullptr;
+  uint64_t* zoff = nullptr;
+  uint8_t* ztype = nullptr;
+  if (P.compress) {
+    uint32_t* zraw = dbuf<uint32_t>(c, "zw_raw", OB);
+    uint64_t* zstride = dbuf<uint64_t>(c, "zw_stride", OB);
+    zoff = dbuf<uint64_t>(c, "zw_off", OB + 1);
+    ztype = dbuf<uint8_t>(c, "zw_type", OB);
+    hipLaunchKernelGGL(k_zprep, dim3(blocks_for(OB)), dim3(256), 0, st, ob, job_ob0 + J, OB, zraw, zstride);
+    LAUNCH_CHECK();
+    launch_scan<uint64_t, uint64_t>(zstride, OB, nullptr, zoff, scan_tmp, st);
+    LAUNCH_CHECK();
+    launch_scan<uint32_t, uint64_t>(gapcnt, OB, nullptr, gap_base, scan_gap, st);
+    LAUNCH_CHECK();
+    uint64_t zbytes = 0;
+    {
+      Mail m(c);
+      const uint64_t* zt = m.add(zoff + OB, 1);
+      m.flush();
+      zbytes = *zt;
+    }
+    zstage = dbuf<uint8_t>(c, "zw_stage", zbytes + 64);
+    zbuf = dbuf<uint8_t>(c, "zw_buf", zbytes + 64);
+    BlockRec* zrec = dbuf<BlockRec>(c, "zw_rec", OB);
+    hipLaunchKernelGGL(k_block_dst_stage, dim3(blocks_for(OB)), dim3(256), 0, st, ob, zoff, P.d_jobs, job_ob0 + J,
+                       OB, zrec);
+    LAUNCH_CHECK();
+    A.out = zstage;
+    A.blk = zrec;
+    A.gapbuf = dbuf<uint4>(c, "gap_buf", zbytes / 16 + 2 * OB + 1);
+    hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, OB * 16)), dim3(256), 0, st, A);
+    LAUNCH_CHECK();
+    launch_encode(c, A, OB);
+    KTimer kz(c, "k_zsnappy");
+    hipLaunchKernelGGL(k_zsnappy, dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((OB + 3) / 4,
+                                                                                       (uint64_t)c->n_cu * 8))),
+                       dim3(256), 0, st, ob, P.d_jobs, job_ob0 + J, zstage, zoff, zraw, zbuf, ztype);
+    LAUNCH_CHECK();
+    kz.stop();
+  }
+  uint64_t* ob_excl = dbuf<uint64_t>(c, "ob_excl", OB + 1);
   launch_scan<uint64_t, uint64_t>(ob.full, OB, nullptr, ob_excl, scan_tmp, st);
   LAUNCH_CHECK();
 
@@ -1144,14 +1223,24 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_file_layout, dim3(blocks_for(NF)), dim3(256), 0, st, job_f0 + J, of, win_off, ie_off, NF);
   LAUNCH_CHECK();
-  launch_scan<uint64_t, uint64_t>(of.size, NF, nullptr, of.out, scan_tmp, st);
+  if (P.compress) {  // a table whose first block is compressed keeps its smallest key after it
+    uint64_t* stride = dbuf<uint64_t>(c, "zw_fstride", NF);
+    hipLaunchKernelGGL(k_zslots, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, P.d_surv, P.tu, ztype, job_f0 + J,
+                       NF, stride);
+    LAUNCH_CHECK();
+    launch_scan<uint64_t, uint64_t>(stride, NF, nullptr, of.out, scan_tmp, st);
+  } else {
+    launch_scan<uint64_t, uint64_t>(of.size, NF, nullptr, of.out, scan_tmp, st);
+  }
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, P.d_surv, P.tu, ie_off, NF);
+  hipLaunchKernelGGL(k_file_entries, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, P.d_surv, P.tu, ie_off, NF,
+                     (const uint8_t*)ztype);
   LAUNCH_CHECK();
   BlockRec* brec = dbuf<BlockRec>(c, "blk_rec", NBLK);
   hipLaunchKernelGGL(k_block_dst, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.d_jobs, job_ob0 + J, NBLK, brec);
   LAUNCH_CHECK();
   O.file_out.assign(NF + 1, 0);
+  O.file_size.assign(NF, 0);
   O.file_entries.assign(NF, 0);
   O.file_keys.assign(4 * NF, 0);
   uint32_t max_win = 0;
@@ -1160,6 +1249,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     Mail m(c);
     const uint64_t* fo = m.add(of.out, NF + 1);
     const uint64_t* fe = m.add(of.entries, NF);
+    const uint64_t* fs = m.add(of.size, NF);
     const uint64_t* fk = m.add(of.keyr, 4 * NF);
     const uint64_t* jf = m.add(job_f0, J + 1);
     const uint32_t* mw = m.add(wstat, 1);
@@ -1167,6 +1257,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     m.flush();
     memcpy(O.file_out.data(), fo, (NF + 1) * 8);
     memcpy(O.file_entries.data(), fe, NF * 8);
+    memcpy(O.file_size.data(), fs, NF * 8);
     memcpy(O.file_keys.data(), fk, NF * 32);
     memcpy(O.job_f0.data(), jf, (J + 1) * 8);
     max_win = *mw;
@@ -1182,50 +1273,35 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   O.d_out = out;
 
   // --- writers
-  {
-    EncodeArgs A;
-    A.jobs = P.d_jobs;
-    A.ob = ob;
+  if (P.compress) {
+    // stored bytes into place, then their trailers' checksums
+    hipLaunchKernelGGL(k_zplace, dim3(std::max<uint32_t>(1, (uint32_t)std::min<uint64_t>((NBLK + 3) / 4,
+                                                                                      (uint64_t)c->n_cu * 16))),
+                       dim3(256), 0, st, brec, job_ob0 + J, zstage, zbuf, zoff, ztype, out);
+    LAUNCH_CHECK();
+    const uint64_t segs = dout / CRC_SEG_BYTES + NBLK + 1;
+    uint32_t* part = dbuf<uint32_t>(c, "zw_crc_part", segs);
+    uint32_t* ticket = ticket_buf(c, "zw_crc_ticket", NBLK);
+    launch_crc_zblocks(brec, job_ob0 + J, NBLK, out, c->d_crc, part, ticket, crc_multi_grid(c, dout, NBLK), st);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_zkeys, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, P.d_surv, P.tu, ztype, P.kw8, NF,
+                       out);
+    LAUNCH_CHECK();
+  } else {
     A.of = of;
-    A.tu = P.tu;
-    A.surv = P.d_surv;
-    A.sz_r = sz_r;
-    A.sz_n = sz_n;
-    A.shr = shr;
-    A.nblocks = job_ob0 + J;
     A.out = out;
-    A.g_crc = c->d_crc;
-    A.ent_off = ent_off;
-    A.rec = erec;
     A.blk = brec;
-    A.kw8 = P.kw8;
-    A.entl = entl;
     // gap chunks: every block's chunk slots (J16 + 1 at most), then the
     // chunks that are not value interiors assembled once
-    uint64_t* gap_base = dbuf<uint64_t>(c, "gap_base", NBLK + 1);
-    uint64_t* scan_gap = dbuf<uint64_t>(c, "scan_tmp_gap", NBLK / 2048 + 8);
     launch_scan<uint32_t, uint64_t>(gapcnt, NBLK, nullptr, gap_base, scan_gap, st);
     LAUNCH_CHECK();
     const uint64_t slots = dout / 16 + 2 * NBLK + 1;
-    A.gap_base = gap_base;
     A.gapbuf = dbuf<uint4>(c, "gap_buf", slots);
     KTimer kg(c, "k_gaps");
     hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, NBLK * 16)), dim3(256), 0, st, A);  // 16 threads per block
     LAUNCH_CHECK();
     kg.stop();
-    const int waves = (int)c->tp.encode_waves;
-    int occ = 0;
-    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, 0));
-    occ = std::max(occ, 1);
-    const uint64_t want = (NBLK + waves - 1) / waves;
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * occ));
-    KTimer kt(c, "k_encode");
-    hipLaunchKernelGGL(k_encode, dim3(grid), dim3(waves * 64), 0, st, A);
-    LAUNCH_CHECK();
-    kt.stop();
-    c->counters.emplace_back("encode_waves_per_group", (double)waves);
-    c->counters.emplace_back("encode_groups", (double)grid);
-    c->counters.emplace_back("encode_groups_per_cu", (double)occ);
+    launch_encode(c, A, NBLK);
   }
   mark(c, "encode");
   if (NW) {
@@ -1369,6 +1445,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   std::vector<uint32_t> in_job, in_local;
   std::vector<uint64_t> snaps;  // every job's live snapshots, back to back
   uint64_t G = 0, total_in = 0;
+  bool any_compression = false;
   for (uint32_t j = 0; j < J; j++) {
     if (snaps.size() + jobs[j].options.n_snapshots > 0xFFFFFFF0ull)
       throw Fail{LUDA_UNSUPPORTED, "too many snapshots in one call"};
@@ -1377,7 +1454,9 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     job_in_first[j] = G;
     const luda_options& o = jobs[j].options;
     jd[j] = JobDesc{o.block_size, o.restart_interval, o.bloom_bits_per_key, o.bottommost ? 1u : 0u,
-                    o.target_file_size, (uint32_t)G, jobs[j].n_inputs, (uint32_t)snaps.size(), o.n_snapshots};
+                    o.target_file_size, (uint32_t)G, jobs[j].n_inputs, (uint32_t)snaps.size(), o.n_snapshots,
+                    o.compression, 0};
+    if (o.compression) any_compression = true;
     snaps.insert(snaps.end(), o.snapshots, o.snapshots + o.n_snapshots);
     for (uint32_t i = 0; i < jobs[j].n_inputs; i++) {
       in_size.push_back(jobs[j].inputs[i].size);
@@ -1458,7 +1537,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   if (NG) {
     hipLaunchKernelGGL(k_footer, dim3(blocks_for(NG)), dim3(256), 0, st, in, ix, err);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_blk_nr, dim3(blocks_for(NG)), dim3(256), 0, st, ix, in, IX.nr, err);
+    hipLaunchKernelGGL(k_blk_nr, dim3(blocks_for(NG)), dim3(256), 0, st, ix, in, IX.nr, err, ZPass{});
     LAUNCH_CHECK();
     {
       const uint64_t segs = total_in / CRC_SEG_BYTES + NG + 1;
@@ -1536,8 +1615,12 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   DB.nr = dbuf<uint32_t>(c, "db_nr", NB);
   DB.ibase = dbuf<uint64_t>(c, "db_ibase", NB + 1);
   DB.ok = dbuf<uint8_t>(c, "db_ok", NB);
+  uint64_t* zcap = dbuf<uint64_t>(c, "z_cap", NB);
+  unsigned long long* ztot = dbuf<unsigned long long>(c, "z_tot", 2);
+  fill_u64(c, ztot, 0, 2);
   if (NB) {
-    hipLaunchKernelGGL(k_blk_nr, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, in, DB.nr, err);
+    hipLaunchKernelGGL(k_blk_nr, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, in, DB.nr, err,
+                       ZPass{zcap, ztot, nullptr, 0});
     LAUNCH_CHECK();
     uint64_t* scan_b = dbuf<uint64_t>(c, "scan_tmp_b", NB / 2048 + 8);
     launch_scan<uint32_t, uint64_t>(DB.nr, NB, nullptr, DB.ibase, scan_b, st);
@@ -1559,9 +1642,36 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     Mail m(c);
     const uint64_t* p = m.add(DB.ibase + NB, 1);
     const unsigned long long* by = m.add(d_bytes, 1);
+    const unsigned long long* zt = m.add(ztot, 2);
     m.flush();
     DB.NI = *p;
     c->counters.emplace_back("data_bytes_in", (double)*by);
+    const uint64_t zblocks = zt[0], zbytes = zt[1];
+    if (zblocks) {
+      // compressed blocks: raw bytes into staging, then their restart counts
+      // and the interval bases again
+      c->counters.emplace_back("compressed_blocks_in", (double)zblocks);
+      uint8_t* stage = dbuf<uint8_t>(c, "z_stage", zbytes + 64);
+      uint64_t* zoff = dbuf<uint64_t>(c, "z_off", NB + 1);
+      uint64_t* scan_z = dbuf<uint64_t>(c, "scan_tmp_z", NB / 2048 + 8);
+      launch_scan<uint64_t, uint64_t>(zcap, NB, nullptr, zoff, scan_z, st);
+      LAUNCH_CHECK();
+      KTimer kt(c, "k_unsnappy");
+      hipLaunchKernelGGL(k_unsnappy, dim3(std::max<uint32_t>(1, (uint32_t)std::min<uint64_t>((zblocks + 1) / 2,
+                                                                                         (uint64_t)c->n_cu * 8))),
+                         dim3(128), 0, st, db, in, DB.ok, zcap, zoff, stage, err);
+      LAUNCH_CHECK();
+      kt.stop();
+      hipLaunchKernelGGL(k_blk_nr, dim3(stride_grid(c, NB)), dim3(256), 0, st, db, in, DB.nr, err,
+                         ZPass{zcap, ztot, DB.ok, 1});
+      LAUNCH_CHECK();
+      launch_scan<uint32_t, uint64_t>(DB.nr, NB, nullptr, DB.ibase, scan_b, st);
+      LAUNCH_CHECK();
+      Mail m2(c);
+      const uint64_t* p2 = m2.add(DB.ibase + NB, 1);
+      m2.flush();
+      DB.NI = *p2;
+    }
   } else {
     fill_u64(c, DB.ibase, 0, 1);
     c->counters.emplace_back("data_bytes_in", 0.0);
@@ -1780,6 +1890,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
   P.d_surv = surv;
   P.job_s0.assign(J + 1, 0);
   P.d_job_s0 = d_job_s0;
+  P.compress = any_compression;
   std::vector<uint64_t> h_shadow(J), h_tomb(J);
   {
     Mail m(c);
@@ -1857,7 +1968,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
         set_file(r.files[f - f0], O, f, base);
       }
       r.data_size = O.file_out[f1] - base;
-      r.bytes_out = r.data_size;
+      for (uint64_t f = f0; f < f1; f++) r.bytes_out += O.file_size[f];
       if (dev_out && c->arena) {  // the caller's buffer: nothing to free
         r.data = O.d_out + base;
       } else if (dev_out) {
@@ -2239,7 +2350,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     }
     if (bad) throw Fail{LUDA_UNSORTED_INPUT, "entries are not strictly increasing internal keys"};
     JobDesc jd{opt->block_size, opt->restart_interval, opt->bloom_bits_per_key, opt->bottommost ? 1u : 0u,
-               opt->target_file_size, 0, 0};
+               opt->target_file_size, 0, 0, 0, 0, opt->compression, 0};
     JobDesc* d_jobs = dbuf<JobDesc>(c, "jobs", 1);
     uint64_t* d_job_s0 = dbuf<uint64_t>(c, "job_s0", 2);
     const uint64_t hs0[2] = {0, n};
@@ -2254,6 +2365,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
     P.d_surv = surv;
     P.job_s0.assign(hs0, hs0 + 2);
     P.d_job_s0 = d_job_s0;
+    P.compress = opt->compression != 0;
     PlanOut O;
     plan_and_write(c, P, O);
     sync(c);
@@ -2275,7 +2387,7 @@ int luda_build_tables_dev(luda_ctx* c, uint64_t n, const uint8_t* keys, const ui
       }
       out->data = (uint8_t*)ri->dev->p;
       out->data_size = O.file_out[nf];
-      out->bytes_out = out->data_size;
+      for (uint64_t f = 0; f < nf; f++) out->bytes_out += O.file_size[f];
     }
   });
   if (st != LUDA_OK) {

@@ -39,6 +39,8 @@ struct JobDesc {
   uint32_t n_in;
   uint32_t snap_first;  // the job's live snapshots: [snap_first, snap_first + n_snap) of the call's list
   uint32_t n_snap;
+  uint32_t compression;  // output data blocks: 0 raw, 1 Snappy when it saves an eighth
+  uint32_t pad;
 };
 
 struct Inputs {

@@ -69,7 +69,11 @@ def test_block_level_errors():
     t = bytearray(ts[0])
     t[bo + bs] = 1
     reseal(t, bo, bs)
-    both([t], job.options(), "compressed")
+    both([t], job.options(), "raw contents marked compressed")
+    t = bytearray(ts[0])
+    t[bo + bs] = 2
+    reseal(t, bo, bs)
+    both([t], job.options(), "unknown block type")
     nr = struct.unpack_from("<I", ts[0], bo + bs - 4)[0]
     t = bytearray(ts[0])
     t[bo + bs - 4:bo + bs] = struct.pack("<I", bs)

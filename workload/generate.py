@@ -511,25 +511,34 @@ def compressible(job: Job, seed: int = 0, compression: int = 1) -> Job:
     enough and are stored raw.
     """
     rng = np.random.default_rng(seed ^ 0x534E4150)  # "SNAP"
-    pats = [rng.bytes(int(rng.integers(1, 13))) for _ in range(64)]
+    plen = rng.integers(1, 13, 64)
+    pstart = np.concatenate([[0], np.cumsum(plen)[:-1]])
+    pbytes = np.frombuffer(rng.bytes(int(plen.sum())), dtype=np.uint8)
     text = np.frombuffer(rng.bytes(16384), dtype=np.uint8)
     runs = []
     for r in job.runs:
         vl = np.diff(r.voff).astype(np.int64)
+        n = r.n
+        raw = np.repeat(rng.integers(0, 4, n // 40 + 1) == 0, 40)[:n]
+        pat = rng.integers(0, 64, n)
+        shift = rng.integers(0, 16384, n)
         out = np.empty(int(r.voff[-1]), dtype=np.uint8)
-        raw = rng.integers(0, 4, r.n // 40 + 1) == 0
-        for i in range(r.n):
-            a, n = int(r.voff[i]), int(vl[i])
-            if n == 0:
+        step = max(1, (8 << 20) // max(1, int(vl.mean()) if n else 1))
+        for e0 in range(0, n, step):  # entries in slices of about 8 MiB of values
+            e1 = min(n, e0 + step)
+            lens = vl[e0:e1]
+            tot = int(lens.sum())
+            if tot == 0:
                 continue
-            if raw[i // 40]:
-                out[a:a + n] = np.frombuffer(rng.bytes(n), dtype=np.uint8)
-            elif i % 2 == 0:
-                p = np.frombuffer(pats[int(rng.integers(0, 64))], dtype=np.uint8)
-                out[a:a + n] = np.resize(p, n)
-            else:
-                o = int(rng.integers(0, 16384))
-                out[a:a + n] = np.resize(np.roll(text, -o), n)
+            ent = np.repeat(np.arange(e0, e1), lens)
+            pos = np.arange(tot) - np.repeat(r.voff[e0:e1] - r.voff[e0], lens)
+            even = (ent % 2) == 0
+            b = np.where(even, pbytes[pstart[pat[ent]] + pos % plen[pat[ent]]],
+                         text[(shift[ent] + pos) % 16384])
+            rnd = raw[ent]
+            if rnd.any():
+                b[rnd] = np.frombuffer(rng.bytes(int(rnd.sum())), dtype=np.uint8)
+            out[int(r.voff[e0]):int(r.voff[e0]) + tot] = b
         runs.append(Run(r.keys, r.koff, r.tags, out, r.voff))
     return Job(runs, block_size=job.block_size, restart_interval=job.restart_interval,
                bloom_bits_per_key=job.bloom_bits_per_key, bottommost=job.bottommost,
