@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_gaps(EncodeArgs A) {
 // lane with nothing to store uses an offset past its end, which the hardware
 // drops), so each wait is for exactly the loads it needs.
 
-constexpr uint32_t ENC_QS = 5;             // chunks per lane in registers: blocks up to 5 KiB pipelined
+constexpr uint32_t ENC_QS = ENC_PIPE_CHUNKS;  // chunks per lane in registers: blocks up to 6 KiB pipelined
 constexpr uint32_t ENC_OOB = 0x80000000u;  // a buffer offset past any block
 
 struct EncH {  // one block, the same in every lane
@@ -461,13 +461,103 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
     EncV V1;
     if (H1.piped) enc_load(A, H1, E1, safe, V1);
     const EntL E2 = enc_entl(A, H2);
-    if (H0.piped) enc_store(&T, A, H0, V0);
-    else enc_block_any(&T, A, H0, safe);
+    if (H0.piped) enc_store(&T, A, H0, V0);  // other blocks: k_encode_big
     H0 = H1;
     H1 = H2;
     H2 = H3;
     E1 = E2;
     V0 = V1;
+  }
+}
+
+// Blocks off the pipelined path (over 6 KiB or 64 entries): one wave per
+// block.  The block's entry layout is staged in LDS first, so that every
+// chunk's source is found by a binary search in LDS without waiting on
+// memory; the chunk loads of ENCB_Q steps (64 chunks each) are then in
+// flight together before they are stored and folded.  Blocks of more than
+// ENCB_ENTS entries take the windowed walk of enc_block_any instead.
+constexpr uint32_t ENCB_WAVES = 8;
+constexpr uint32_t ENCB_ENTS = 64;
+constexpr uint32_t ENCB_Q = 4;
+
+struct EncbEnt {
+  uint64_t vsrc;
+  uint32_t ia, pieces, cum, pad;
+};
+
+__global__ void __launch_bounds__(ENCB_WAVES * 64) k_encode_big(EncodeArgs A) {
+  __shared__ CrcLds T;
+  __shared__ EncbEnt L[ENCB_WAVES][ENCB_ENTS];
+  load_crc_tables(&T, A.g_crc, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const uint64_t nb = *A.nblocks;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const uint64_t stride = (uint64_t)gridDim.x * ENCB_WAVES;
+  const uint64_t safe = (uint64_t)(uintptr_t)A.g_crc;
+  EncbEnt* E = L[wv];
+  for (uint64_t b = (uint64_t)blockIdx.x * ENCB_WAVES + wv; b < nb; b += stride) {
+    const EncH H = enc_handle(A, b, nb);
+    if (H.piped) continue;
+    if (H.cnt > ENCB_ENTS) {
+      enc_block_any(&T, A, H, safe);
+      continue;
+    }
+    for (uint32_t i = lane_id(); i < H.cnt; i += WAVE) {
+      const EntL e = A.entl[H.s0 + i];
+      E[i] = EncbEnt{e.vsrc, e.ia, e.pieces, e.cum, 0};
+    }
+    wave_sync();
+    uint8_t* dst = A.out + H.dst;
+    const uint32_t n = H.n;
+    const int64_t ct = enc_top(H);
+    const uint32_t steps = (H.J16 + 63) / 64;
+    uint32_t acc = 0;
+    for (uint32_t i0 = 0; i0 < steps; i0 += ENCB_Q) {
+      uint4 v[ENCB_Q];
+#pragma unroll
+      for (uint32_t q = 0; q < ENCB_Q; q++) {
+        const int64_t c = ct - 64 * (int64_t)(i0 + q);
+        uint64_t src = safe;
+        if (c >= 0) {
+          const uint32_t m = (uint32_t)((int64_t)H.J16 - 1 - c);
+          uint32_t lo = 0, hi = H.cnt;  // the last entry whose interior starts at or before m (entry 0 if none)
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (E[mid].ia <= m) lo = mid;
+            else hi = mid;
+          }
+          const EncbEnt e = E[lo];
+          if (e.ia <= m && m < e.ia + e.pieces) {
+            src = e.vsrc + 16ull * m;
+          } else {
+            const uint32_t g = e.ia <= m ? m - e.cum - e.pieces : m;  // gap chunks before m
+            src = (uint64_t)(uintptr_t)(A.gapbuf + H.gap + 1 + g);
+          }
+        }
+        v[q] = ldg16(src);
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < ENCB_Q; q++) {
+        const int64_t c = ct - 64 * (int64_t)(i0 + q);
+        if (c < 0) continue;
+        const int64_t p0 = (int64_t)n - 16 * (c + 1);
+        if (p0 >= 0) {
+          __builtin_memcpy(dst + p0, &v[q], 16);
+          acc = crc_shift(T.sh[6], acc) ^ (p0 < 4 ? crc_chunk(&T, v[q], p0) : crc_chunk_plain(&T, v[q]));
+        } else {
+          const uint8_t* vb = (const uint8_t*)&v[q];
+          for (int k = 0; k < 16; k++)
+            if (p0 + k >= 0) dst[p0 + k] = vb[k];
+          acc = crc_shift(T.sh[6], acc) ^ crc_chunk(&T, v[q], p0);
+        }
+      }
+    }
+    const uint32_t raw = crc_wave_join(&T, acc);
+    if (lane_id() == 0) {
+      const uint32_t mk = crc_mask(raw ^ 0xFFFFFFFFu);
+      __builtin_memcpy(dst + n, &mk, 4);
+    }
+    wave_sync();  // the layout slots are reused by the next block
   }
 }
 

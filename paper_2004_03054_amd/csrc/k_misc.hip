@@ -51,12 +51,14 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
   }
   __syncthreads();
   const uint64_t nb = job_ob0[J];
-  uint32_t sz = 0, cn = 0;
+  uint32_t sz = 0, cn = 0, tiny = 0;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb && b < cap;
        b += (uint64_t)gridDim.x * blockDim.x) {
     sz = max(sz, ob.size[b]);
     cn = max(cn, ob.cnt[b]);
+    if (ob.size[b] < 15) tiny = 1;  // a message (contents + type byte) under 16 bytes
   }
+  if (__ballot(tiny) && lane_id() == 0) atomicMax(&stats[2], 1u);
   sz = wave_max(sz);
   cn = wave_max(cn);
   if (lane_id() == 0) {

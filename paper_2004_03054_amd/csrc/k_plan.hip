@@ -12,9 +12,13 @@
 //   k_seg_exit     per chunk of 2048 items: next() for every item, then
 //                  pointer doubling in LDS gives each item's exit from the
 //                  chunk and the number of starts it passes on the way
-//   k_seg_compose  per job: the chunks' entry->exit maps (offsets below the
-//                  largest step) are composed with a Hillis-Steele scan, which
-//                  gives every chunk's true entry point and start count
+//   k_seg_compose  per job: every chunk's true entry point and start count.
+//                  Short steps: the chunks' entry->exit maps (offsets below
+//                  the largest step) composed by a Hillis-Steele scan.  Long
+//                  steps: in order over the chunks, where a chunk whose
+//                  candidate entry points all leave it at the same exit needs
+//                  no entry (the usual case: greedy chains merge within a few
+//                  segments)
 //   k_seg_mark     per chunk: marks the orbit from the entry point by doubling
 //                  and writes the starts in order
 #include "dev_common.h"
@@ -83,6 +87,7 @@ __global__ void k_prep(const uint32_t* surv, Tuples tu, uint32_t kw8, const uint
 }
 
 struct BlockNext {
+  static constexpr bool kStaged = true;
   const JobDesc* jobs;
   const SegJob* sj;
   const uint32_t* sz_r;
@@ -107,9 +112,33 @@ struct BlockNext {
     }
     return m;
   }
+  // sizes of items [lo, hi) are also in LDS (SR, SN at item - lo)
+  __device__ uint32_t staged(uint32_t j, uint32_t i, uint32_t lo, uint32_t hi, const uint32_t* SR,
+                             const uint32_t* SN) const {
+    const uint64_t base = sj[j].base;
+    const uint32_t m = sj[j].m;
+    const uint32_t R = jobs[j].restart_interval;
+    const uint64_t bs = jobs[j].block_size;
+    uint64_t E = 0;
+    uint32_t r = 0;  // (t - i) % R
+    uint64_t nrest = 0;
+    for (uint32_t t = i; t < m; t++) {
+      const bool in = t < hi;
+      if (r == 0) {
+        E += in ? SR[t - lo] : sz_r[base + t];
+        nrest++;
+      } else {
+        E += in ? SN[t - lo] : sz_n[base + t];
+      }
+      if (++r == R) r = 0;
+      if (E + 4 * nrest + 4 >= bs) return t + 1;
+    }
+    return m;
+  }
 };
 
 struct FileNext {
+  static constexpr bool kStaged = false;
   const JobDesc* jobs;
   const SegJob* sj;
   const uint64_t* ob_excl;
@@ -130,6 +159,9 @@ struct FileNext {
   }
 };
 
+constexpr uint32_t SEG_STAGE_MIN = 12;     // stage when the chunk's first segment has this many items
+constexpr uint32_t SEG_COMPOSE_SCAN = 32;  // longest step for which compose scans the chunk maps
+
 template <typename Next>
 __global__ void __launch_bounds__(256) k_seg_exit(const SegChunk* ch, const uint32_t* nch_dev, const SegJob* sj,
                                                   Next nf, uint32_t* nxt, uint32_t* ex, uint32_t* cnt,
@@ -145,8 +177,30 @@ __global__ void __launch_bounds__(256) k_seg_exit(const SegChunk* ch, const uint
   const uint32_t c0 = k.start, c1 = k.end, len = c1 - c0;
   if (threadIdx.x == 0) sbm = 0;
   uint32_t bm = 0;
+  uint32_t hi = 0;
+  bool staged = false;
+  if constexpr (Next::kStaged) {
+    // Long segments (many items each): the sizes of this chunk are read into
+    // LDS once, instead of each item's walk reading them again (items past
+    // the chunk are read directly).  Short segments read them directly.
+    if (threadIdx.x == 0) sbm = nf(j, c0) - c0;  // the first item's segment length
+    __syncthreads();
+    staged = sbm >= SEG_STAGE_MIN;
+    __syncthreads();
+    if (threadIdx.x == 0) sbm = 0;
+    if (staged) {  // in the second doubling buffers, free until the doubling starts
+      hi = c1;
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        P[1][i] = nf.sz_r[base + c0 + i];
+        K[1][i] = nf.sz_n[base + c0 + i];
+      }
+    }
+    __syncthreads();
+  }
   for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-    const uint32_t v = nf(j, c0 + i);
+    uint32_t v;
+    if constexpr (Next::kStaged) v = staged ? nf.staged(j, c0 + i, c0, hi, P[1], K[1]) : nf(j, c0 + i);
+    else v = nf(j, c0 + i);
     P[0][i] = v;
     K[0][i] = 1;
     nxt[base + c0 + i] = v;
@@ -178,8 +232,8 @@ __global__ void __launch_bounds__(256) k_seg_exit(const SegChunk* ch, const uint
   if (threadIdx.x == 0) atomicMax(&job_bmax[j], sbm);
 }
 
-// one workgroup per job; dynamic LDS holds two composition buffers of
-// `cap` 16-bit entries each
+// one workgroup per job; dynamic LDS holds two buffers of `cap` 16-bit
+// entries (the scan) or cap chunks' common exits
 __global__ void __launch_bounds__(256) k_seg_compose(const SegJob* sj, uint32_t J, const uint32_t* ex,
                                                      const uint32_t* cnt, const uint32_t* job_bmax,
                                                      uint32_t* chunk_entry, uint32_t* chunk_seg0,
@@ -195,9 +249,18 @@ __global__ void __launch_bounds__(256) k_seg_compose(const SegJob* sj, uint32_t 
     return;
   }
   const uint32_t bm = job_bmax[j] ? job_bmax[j] : 1;
+  // A segment spans at most bm items, so with bm <= SEG_C a chunk's entry
+  // point (its first start) lies in its first bm items.  Chains of greedy
+  // cuts from different starting points merge within a few segments, so the
+  // exits from all those candidates are usually one and the same: then the
+  // chunk's exit is known without its entry, and only chunks whose
+  // candidates disagree need the entry of the chunk before them.
+  uint32_t* conv = (uint32_t*)smem;  // per chunk: the common exit, or DIFFER
+  const uint32_t DIFFER = 0xFFFFFFFEu;
   const uint16_t END = 0xFFFF;
-  const bool parallel = bm <= SEG_C && bm < 0xFFFF && (uint64_t)nch * bm <= cap;
-  if (parallel) {
+  if (bm <= SEG_COMPOSE_SCAN && (uint64_t)nch * bm <= cap) {
+    // short steps: the chunks' entry->exit maps (offsets below bm) composed
+    // with a Hillis-Steele scan in LDS
     uint16_t* A = (uint16_t*)smem;
     uint16_t* B = A + cap;
     const uint32_t tot = nch * bm;
@@ -230,6 +293,28 @@ __global__ void __launch_bounds__(256) k_seg_compose(const SegJob* sj, uint32_t 
     for (uint32_t c = threadIdx.x; c < nch; c += blockDim.x) {
       const uint32_t e = (c == 0) ? 0 : A[(c - 1) * bm];
       chunk_entry[ch0 + c] = (e == END) ? 0xFFFFFFFFu : c * SEG_C + e;
+    }
+  } else if (bm <= SEG_C && nch <= cap / 2) {
+    // each chunk's first candidate's exit, then one pass over all candidates
+    for (uint32_t c = threadIdx.x; c < nch; c += blockDim.x) conv[c] = ex[base + (uint64_t)c * SEG_C];
+    __syncthreads();
+    const uint64_t tot = (uint64_t)nch * bm;
+    for (uint64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+      const uint32_t c = (uint32_t)(idx / bm), o = (uint32_t)(idx % bm);
+      const uint64_t item = (uint64_t)c * SEG_C + o;
+      if (o > 0 && item < m && ex[base + item] != ex[base + (uint64_t)c * SEG_C]) conv[c] = DIFFER;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t e = 0;
+      for (uint32_t c = 0; c < nch; c++) {
+        if (e >= m) {
+          chunk_entry[ch0 + c] = 0xFFFFFFFFu;
+          continue;
+        }
+        chunk_entry[ch0 + c] = e;
+        if (e < (c + 1) * SEG_C) e = conv[c] != DIFFER ? conv[c] : ex[base + e];
+      }
     }
   } else if (threadIdx.x == 0) {
     // long steps or too many chunks: walk the chunk exits in order

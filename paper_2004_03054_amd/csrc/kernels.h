@@ -207,7 +207,11 @@ struct EncodeArgs {
   uint4* gapbuf;            // gap chunks (16 bytes each)
 };
 __global__ void k_gaps(EncodeArgs A);
+// chunks per lane of the pipelined encoder: it takes blocks whose message
+// (contents + type byte) is 16 to 64 * 16 * ENC_PIPE_CHUNKS bytes, of at most 64 entries
+constexpr uint32_t ENC_PIPE_CHUNKS = 6;
 __global__ void k_encode(EncodeArgs A);
+__global__ void k_encode_big(EncodeArgs A);  // the blocks k_encode leaves (over 5 KiB or 64 entries)
 struct FilterArgs {
   const JobDesc* jobs;
   OutBlocks ob;

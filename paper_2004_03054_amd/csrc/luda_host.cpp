@@ -959,8 +959,10 @@ void set_file(luda_file& x, const PlanOut& O, uint64_t f, uint64_t base) {
   x.largest_len = O.file_keys[4 * f + 3];
 }
 
-// the encoder over nblk output blocks (A.blk gives their destinations)
-void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk) {
+// the encoder over nblk output blocks (A.blk gives their destinations);
+// `big`: some block is off the pipelined path (over 5 KiB of message, over
+// 64 entries, or under 16 bytes), so k_encode_big runs after k_encode
+void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk, bool big) {
   const int waves = (int)c->tp.encode_waves;
   int occ = 0;
   HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, 0));
@@ -974,6 +976,13 @@ void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk) {
   c->counters.emplace_back("encode_waves_per_group", (double)waves);
   c->counters.emplace_back("encode_groups", (double)grid);
   c->counters.emplace_back("encode_groups_per_cu", (double)occ);
+  if (big) {
+    const uint32_t gb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nblk + 7) / 8, (uint64_t)c->n_cu * 3));
+    KTimer kb(c, "k_encode_big");
+    hipLaunchKernelGGL(k_encode_big, dim3(gb), dim3(512), 0, c->stream, A);
+    LAUNCH_CHECK();
+    kb.stop();
+  }
 }
 
 void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
@@ -1114,7 +1123,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.gapbuf = dbuf<uint4>(c, "gap_buf", zbytes / 16 + 2 * OB + 1);
     hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, OB * 16)), dim3(256), 0, st, A);
     LAUNCH_CHECK();
-    launch_encode(c, A, OB);
+    launch_encode(c, A, OB, true);
     KTimer kz(c, "k_zsnappy");
     hipLaunchKernelGGL(k_zsnappy, dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((OB + 3) / 4,
                                                                                        (uint64_t)c->n_cu * 8))),
@@ -1186,17 +1195,19 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   LAUNCH_CHECK();
   uint64_t NBLK, NF, NW;
   uint32_t max_bsize;
+  bool big_blocks = true;
   {
     Mail m(c);
     const uint64_t* a = m.add(job_ob0 + J, 1);
     const uint64_t* b = m.add(job_f0 + J, 1);
     const uint64_t* w = m.add(of.w0 + FC, 1);
-    const uint32_t* x = m.add(stats, 2);
+    const uint32_t* x = m.add(stats, 3);
     m.flush();
     NBLK = *a;
     NF = *b;
     NW = *w;
     max_bsize = x[0];
+    big_blocks = (uint64_t)x[0] + 1 > 64 * 16 * ENC_PIPE_CHUNKS || x[1] > 64 || x[2] != 0;
     c->counters.emplace_back("max_block_bytes", (double)max_bsize);
   }
 
@@ -1301,7 +1312,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, NBLK * 16)), dim3(256), 0, st, A);  // 16 threads per block
     LAUNCH_CHECK();
     kg.stop();
-    launch_encode(c, A, NBLK);
+    launch_encode(c, A, NBLK, big_blocks);
   }
   mark(c, "encode");
   if (NW) {
