@@ -130,12 +130,16 @@ def host_info() -> dict:
 
 def kernel_times(ctx):
     """Device time of each timed kernel in the last call (launches of the same
-    kernel, e.g. merge rounds, summed)."""
+    kernel, e.g. merge rounds, summed).  The encoder is two kernels (the
+    pipelined blocks, then the large ones): "k_encode" is their sum, and
+    "k_encode_big" is also given alone."""
     out = {}
     for k, v in ctx.stage_times():
         if k.startswith("kernel:"):
             name = k.split(":", 1)[1]
             out[name] = out.get(name, 0.0) + v
+            if name == "k_encode_big":
+                out["k_encode"] = out.get("k_encode", 0.0) + v
     return out
 
 
@@ -151,11 +155,13 @@ def parse_args(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: bytes copied per launch (MiB)")
-    ap.add_argument("--mode", choices=["headline", "plain", "batch", "serve", "copy", "coopsort"], default="headline",
+    ap.add_argument("--mode", choices=["headline", "plain", "batch", "serve", "copy", "coopsort", "batchpass"],
+                    default="headline",
                     help="headline (default): batched vs plain on the 256-job batch workload, with a served "
                          "record at 200 jobs/s and the plain large compaction as sub-records; plain: one large "
-                         "compaction; batch: the batched pass alone; serve: Poisson arrivals through the request "
-                         "loop vs plain per-job launches")
+                         "compaction; batch: the batched pass vs a loop of plain calls; serve: Poisson arrivals "
+                         "through the request loop vs plain per-job launches; batchpass: batched passes only, for "
+                         "profiling; copy: a device copy, for scaling byte counters")
     ap.add_argument("--rate", type=str, default="50",
                     help="serve mode: arrivals per second (a comma-separated list runs each on one job pool)")
     ap.add_argument("--workers", type=int, default=2, help="serve mode: the served form's workers")
@@ -197,6 +203,8 @@ def main():
         return copy_main(args)
     if args.mode == "coopsort":
         return coopsort_main(args)
+    if args.mode == "batchpass":
+        return batchpass_main(args)
     out = plain_record(args, args.config, args.scale, args.steps, args.warmup, not args.no_cpu_baseline,
                        args.e2e_steps)
     print(json.dumps(out), flush=True)
@@ -619,6 +627,31 @@ def coopsort_main(args):
                       "entries_in": int(sum(r.n for r in job.runs)), "host_threads": min(16, os.cpu_count() or 1),
                       "device_merge": out["device_merge"], "host_sort": out["host_sort"],
                       "outputs_identical": prints["device_merge"] == prints["host_sort"]}), flush=True)
+
+
+def batchpass_main(args):
+    """The batched pass alone (for profiling): build the batch workload's
+    tables on the device, then `--steps` batched passes; one JSON line of
+    their times.  No plain loop, no verification, no oracle."""
+    import torch
+    from paper_2004_03054_amd import Context
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = Context(0)
+    jobs, tables, in_bytes = build_batch_pool(ctx, args.jobs, args.scale)
+    batch = [(tables[j], jobs[j][1]) for j in range(len(jobs))]
+    ms = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.compact_batch(batch, device_inputs=True, materialize=False)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        assert all(r.status == 0 for r in out)
+        del out
+    print(json.dumps({"mode": "batchpass", "jobs": len(jobs), "input_bytes": in_bytes,
+                      "ms_per_pass": [round(x, 3) for x in ms]}), flush=True)
+    ctx.close()
 
 
 def copy_main(args):

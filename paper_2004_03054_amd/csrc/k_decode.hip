@@ -311,15 +311,40 @@ __global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev
 // entry area: RESTARTS phase).  KIND 0 = index block, 1 = data block;
 // MODE 0 = count and check, 1 = emit.
 
+// The data emit pass stages the entry records of a wave's 64 intervals in
+// LDS (their outputs are one contiguous range) and stores them with
+// contiguous, whole-line writes; a lane walking its interval would otherwise
+// write each record field to 64 scattered places per instruction.  Records
+// past EMIT_CAP in the range are stored directly.
+constexpr uint32_t EMIT_CAP = 256;
+constexpr uint32_t EMIT_WAVES = 4;  // waves per workgroup (the launch bound)
+
+template <uint32_t CAP>
+struct EmitStage {
+  uint64_t kd[CAP], sn[CAP], vp[CAP];
+  uint32_t vlen[CAP], blk[CAP], eoff[CAP];
+};
+
 template <int KIND, int MODE>
 __global__ void __launch_bounds__(256) k_walk(WalkArgs A) {
+  constexpr bool STAGED = KIND == 1 && MODE == 1;
+  __shared__ EmitStage<STAGED ? EMIT_CAP : 1> stage_all[STAGED ? EMIT_WAVES : 1];
+  EmitStage<STAGED ? EMIT_CAP : 1>& S = stage_all[STAGED ? threadIdx.x / WAVE : 0];
   const uint64_t ni = *A.ni_dev;
   uint32_t maxk_all = 0;  // longest key this thread saw (count pass over data blocks)
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t b = A.iblk[i];
-    const uint32_t k = (uint32_t)(i - A.ibase[b]);
+  const uint64_t lane0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint32_t)(WAVE - 1));
+  // the loop runs the same number of times in every lane of a wave
+  for (uint64_t i0 = lane0; i0 < ni; i0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = i0 + lane_id();
+    uint64_t wbase = 0, wn = 0;  // this wave's output range (staged emit)
+    if constexpr (STAGED) {
+      wbase = A.ient[i0];
+      wn = A.ient[min(i0 + WAVE, ni)] - wbase;
+    }
+    const uint32_t b = i < ni ? A.iblk[i] : 0u;
+    const uint32_t k = i < ni ? (uint32_t)(i - A.ibase[b]) : 0u;
     uint32_t cnt = 0, maxk = 0;
-    if (A.ok[b]) {
+    if (i < ni && A.ok[b]) {
       const uint8_t* c = (const uint8_t*)A.ws.ptr[b];
       const uint32_t size = A.ws.size[b];
       const uint32_t nr = A.nr[b];
@@ -396,14 +421,24 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs A) {
             if (MODE == 0) blk_err(A.ws, A.in, b, P_ENTRIES, o, EC_FORMAT, A.err);
             break;
           }
-          if (KIND == 1 && MODE == 1) {
+          if constexpr (STAGED) {
             const uint64_t gaddr = (uint64_t)(uintptr_t)c;
-            A.tu.kd[out] = gaddr + o + hdr;
-            A.tu.sn[out] = (uint64_t)shared | ((uint64_t)ns << 32);
-            A.tu.vp[out] = gaddr + o + hdr + ns;
-            A.tu.vlen[out] = vlen;
-            A.tu.blk[out] = b;
-            A.tu.eoff[out] = (uint32_t)o;
+            const uint64_t rel = out - wbase;
+            if (rel < EMIT_CAP) {
+              S.kd[rel] = gaddr + o + hdr;
+              S.sn[rel] = (uint64_t)shared | ((uint64_t)ns << 32);
+              S.vp[rel] = gaddr + o + hdr + ns;
+              S.vlen[rel] = vlen;
+              S.blk[rel] = b;
+              S.eoff[rel] = (uint32_t)o;
+            } else {
+              A.tu.kd[out] = gaddr + o + hdr;
+              A.tu.sn[out] = (uint64_t)shared | ((uint64_t)ns << 32);
+              A.tu.vp[out] = gaddr + o + hdr + ns;
+              A.tu.vlen[out] = vlen;
+              A.tu.blk[out] = b;
+              A.tu.eoff[out] = (uint32_t)o;
+            }
           }
           out++;
           cnt++;
@@ -414,8 +449,23 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs A) {
         }
       }
     }
-    if (MODE == 0) A.icnt[i] = cnt;
+    if (MODE == 0 && i < ni) A.icnt[i] = cnt;
     maxk_all = max(maxk_all, maxk);
+    if constexpr (STAGED) {
+      // every walk emits exactly the records its count pass counted (the same
+      // checks stop both), so the staged part of the range is complete
+      wave_sync();
+      const uint32_t m = (uint32_t)min(wn, (uint64_t)EMIT_CAP);
+      for (uint32_t q = lane_id(); q < m; q += WAVE) {
+        A.tu.kd[wbase + q] = S.kd[q];
+        A.tu.sn[wbase + q] = S.sn[q];
+        A.tu.vp[wbase + q] = S.vp[q];
+        A.tu.vlen[wbase + q] = S.vlen[q];
+        A.tu.blk[wbase + q] = S.blk[q];
+        A.tu.eoff[wbase + q] = S.eoff[q];
+      }
+      wave_sync();
+    }
   }
   if (KIND == 1 && MODE == 0) {
     maxk_all = wave_max(maxk_all);
