@@ -232,8 +232,8 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
                  entries_in=r.entries_in, entries_out=r.entries_out, dropped_shadowed=r.dropped_shadowed,
                  dropped_tombstones=r.dropped_tombstones, bytes_in=r.bytes_in, bytes_out=r.bytes_out,
                  ms_total=r.ms_total)
-    for i in range(r.num_files if r.status == 0 else 0):
-        f = r.files[i]
+    fs = r.files[:r.num_files] if r.status == 0 and r.num_files else []  # one copy of the file records
+    for f in fs:
         res.key_ranges.append((f.smallest_off - f.offset, f.smallest_len, f.largest_off - f.offset, f.largest_len))
         if materialize is not False:
             if device:
@@ -262,8 +262,8 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
             res.files.append(materialize(t))
     elif r.status == 0 and r.num_files and not materialize:
         res.files = [None] * r.num_files
-        res.file_entries = [r.files[i].num_entries for i in range(r.num_files)]
-        res.file_sizes = [r.files[i].size for i in range(r.num_files)]
+        res.file_entries = [f.num_entries for f in fs]
+        res.file_sizes = [f.size for f in fs]
     elif r.status == 0 and r.num_files:
         import torch  # device memory plumbing only
         for i in range(r.num_files):
@@ -309,8 +309,9 @@ def _torch_sync():
     torch.cuda.current_stream().synchronize()
 
 
-def _dev_bufs(inputs) -> LudaBuf:
-    _torch_sync()
+def _dev_bufs(inputs, sync: bool = True) -> LudaBuf:
+    if sync:
+        _torch_sync()
     bufs = (LudaBuf * max(1, len(inputs)))()
     for i, t in enumerate(inputs):
         bufs[i].data = t.data_ptr() if t.numel() else None
@@ -381,9 +382,11 @@ class Context:
         J = len(jobs)
         cjobs = (LudaJob * max(1, J))()
         keep = []
+        if device_inputs:
+            _torch_sync()  # once for the whole batch
         for j, (inputs, opts) in enumerate(jobs):
             if device_inputs:
-                bufs = _dev_bufs(inputs)
+                bufs = _dev_bufs(inputs, sync=False)
             else:
                 bufs, arrs = _bufs(inputs)
                 keep.append(arrs)
@@ -406,9 +409,11 @@ class Context:
         J = len(jobs)
         cjobs = (LudaJob * max(1, J))()
         keep = []
+        if device_inputs:
+            _torch_sync()  # once for the whole batch
         for j, (inputs, opts) in enumerate(jobs):
             if device_inputs:
-                bufs = _dev_bufs(inputs)
+                bufs = _dev_bufs(inputs, sync=False)
             else:
                 bufs, arrs = _bufs(inputs)
                 keep.append(arrs)

@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_gaps(EncodeArgs A) {
 // lane with nothing to store uses an offset past its end, which the hardware
 // drops), so each wait is for exactly the loads it needs.
 
-constexpr uint32_t ENC_QS = ENC_PIPE_CHUNKS;  // chunks per lane in registers: blocks up to 6 KiB pipelined
+constexpr uint32_t ENC_QS = ENC_PIPE_CHUNKS;  // chunks per lane in registers: blocks up to 5 KiB pipelined
 constexpr uint32_t ENC_OOB = 0x80000000u;  // a buffer offset past any block
 
 struct EncH {  // one block, the same in every lane
@@ -285,7 +285,7 @@ __device__ __forceinline__ EncH enc_handle(const EncodeArgs& A, uint64_t b, uint
   h.J16 = (h.n + 15) / 16;
   h.gshift = 16 * h.J16 - h.n;
   h.valid = b < nb;
-  h.piped = h.J16 <= 64 * ENC_QS && h.cnt <= WAVE && h.n >= 16;
+  h.piped = enc_pipelined(r.size, r.cnt);
   return h;
 }
 
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(1024) k_encode(EncodeArgs A) {
   }
 }
 
-// Blocks off the pipelined path (over 6 KiB or 64 entries): one wave per
+// Blocks off the pipelined path (over 5 KiB or 64 entries): one wave per
 // block.  The block's entry layout is staged in LDS first, so that every
 // chunk's source is found by a binary search in LDS without waiting on
 // memory; the chunk loads of ENCB_Q steps (64 chunks each) are then in
@@ -485,17 +485,20 @@ struct EncbEnt {
   uint32_t ia, pieces, cum, pad;
 };
 
-__global__ void __launch_bounds__(ENCB_WAVES * 64) k_encode_big(EncodeArgs A) {
+__global__ void __launch_bounds__(ENCB_WAVES * 64) k_encode_big(EncodeArgs A, const uint64_t* list, uint64_t nlist) {
   __shared__ CrcLds T;
   __shared__ EncbEnt L[ENCB_WAVES][ENCB_ENTS];
   load_crc_tables(&T, A.g_crc, threadIdx.x, blockDim.x);
   __syncthreads();
   const uint64_t nb = *A.nblocks;
+  const uint64_t ni = list ? nlist : nb;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const uint64_t stride = (uint64_t)gridDim.x * ENCB_WAVES;
   const uint64_t safe = (uint64_t)(uintptr_t)A.g_crc;
   EncbEnt* E = L[wv];
-  for (uint64_t b = (uint64_t)blockIdx.x * ENCB_WAVES + wv; b < nb; b += stride) {
+  for (uint64_t i = (uint64_t)blockIdx.x * ENCB_WAVES + wv; i < ni; i += stride) {
+    const uint64_t b = list ? list[i] : i;
+    if (b >= nb) continue;
     const EncH H = enc_handle(A, b, nb);
     if (H.piped) continue;
     if (H.cnt > ENCB_ENTS) {

@@ -51,14 +51,18 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
   }
   __syncthreads();
   const uint64_t nb = job_ob0[J];
-  uint32_t sz = 0, cn = 0, tiny = 0;
+  uint32_t sz = 0, cn = 0, tiny = 0, off = 0;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb && b < cap;
        b += (uint64_t)gridDim.x * blockDim.x) {
-    sz = max(sz, ob.size[b]);
-    cn = max(cn, ob.cnt[b]);
-    if (ob.size[b] < 15) tiny = 1;  // a message (contents + type byte) under 16 bytes
+    const uint32_t s = ob.size[b], c = ob.cnt[b];
+    sz = max(sz, s);
+    cn = max(cn, c);
+    if (s < 15) tiny = 1;  // a message (contents + type byte) under 16 bytes
+    off += enc_pipelined(s, c) ? 0 : 1;
   }
   if (__ballot(tiny) && lane_id() == 0) atomicMax(&stats[2], 1u);
+  off = wave_sum(off);
+  if (off && lane_id() == 0) atomicAdd(&stats[3], off);
   sz = wave_max(sz);
   cn = wave_max(cn);
   if (lane_id() == 0) {
@@ -74,17 +78,28 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
 
 // encoder records of the output blocks (after the file layout)
 __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
-                            BlockRec* br) {
+                            BlockRec* br, uint64_t* big_list, uint32_t* big_n) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= cap || b >= *nblocks) return;
-  BlockRec r;
-  r.dst = of.out[ob.file[b]] + ob.off[b];
-  r.s0 = ob.s0[b];
-  r.cnt = ob.cnt[b];
-  r.size = ob.size[b];
-  r.R = jobs[ob.job[b]].restart_interval;
-  r.pad = 0;
-  br[b] = r;
+  const bool in = b < cap && b < *nblocks;
+  BlockRec r{};
+  if (in) {
+    r.dst = of.out[ob.file[b]] + ob.off[b];
+    r.s0 = ob.s0[b];
+    r.cnt = ob.cnt[b];
+    r.size = ob.size[b];
+    r.R = jobs[ob.job[b]].restart_interval;
+    r.pad = 0;
+    br[b] = r;
+  }
+  if (!big_list) return;
+  // one atomic per wave for its off-path blocks
+  const bool big = in && !enc_pipelined(r.size, r.cnt);
+  const uint64_t m = __ballot(big);
+  if (!m) return;
+  uint32_t base = 0;
+  if (lane_id() == (uint32_t)__builtin_ctzll(m)) base = atomicAdd(big_n, (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, __builtin_ctzll(m), WAVE);
+  if (big) big_list[base + __popcll(m & ((1ull << lane_id()) - 1))] = b;
 }
 
 // Per file: its entry count, and where its smallest and largest internal

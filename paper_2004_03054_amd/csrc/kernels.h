@@ -184,8 +184,16 @@ struct BlockRec {
   uint32_t R;     // restart interval
   uint32_t pad;
 };
+// chunks per lane of the pipelined encoder: it takes blocks whose message
+// (contents + type byte) is 16 to 64 * 16 * ENC_PIPE_CHUNKS bytes, of at most 64 entries
+constexpr uint32_t ENC_PIPE_CHUNKS = 5;
+__host__ __device__ constexpr bool enc_pipelined(uint32_t size, uint32_t cnt) {
+  return size + 1 >= 16 && size + 1 <= 64 * 16 * ENC_PIPE_CHUNKS && cnt <= 64;
+}
+// big_list (optional): the ids of the blocks off the pipelined path, in any
+// order, counted in big_n (room for exactly as many as there are)
 __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
-                            BlockRec* br);
+                            BlockRec* br, uint64_t* big_list, uint32_t* big_n);
 struct EncodeArgs {
   const JobDesc* jobs;
   OutBlocks ob;
@@ -207,11 +215,10 @@ struct EncodeArgs {
   uint4* gapbuf;            // gap chunks (16 bytes each)
 };
 __global__ void k_gaps(EncodeArgs A);
-// chunks per lane of the pipelined encoder: it takes blocks whose message
-// (contents + type byte) is 16 to 64 * 16 * ENC_PIPE_CHUNKS bytes, of at most 64 entries
-constexpr uint32_t ENC_PIPE_CHUNKS = 6;
 __global__ void k_encode(EncodeArgs A);
-__global__ void k_encode_big(EncodeArgs A);  // the blocks k_encode leaves (over 5 KiB or 64 entries)
+// the blocks k_encode leaves: those listed in list[0, nlist), or (list null)
+// every block off the pipelined path
+__global__ void k_encode_big(EncodeArgs A, const uint64_t* list, uint64_t nlist);
 struct FilterArgs {
   const JobDesc* jobs;
   OutBlocks ob;

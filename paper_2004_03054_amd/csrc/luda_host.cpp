@@ -961,8 +961,10 @@ void set_file(luda_file& x, const PlanOut& O, uint64_t f, uint64_t base) {
 
 // the encoder over nblk output blocks (A.blk gives their destinations);
 // `big`: some block is off the pipelined path (over 5 KiB of message, over
-// 64 entries, or under 16 bytes), so k_encode_big runs after k_encode
-void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk, bool big) {
+// 64 entries, or under 16 bytes), so k_encode_big runs after k_encode, over
+// the nlist blocks of `list` when there is one, else over every block
+void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk, bool big, const uint64_t* list = nullptr,
+                   uint64_t nlist = 0) {
   const int waves = (int)c->tp.encode_waves;
   int occ = 0;
   HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_encode, waves * 64, 0));
@@ -977,9 +979,10 @@ void launch_encode(luda_ctx* c, const EncodeArgs& A, uint64_t nblk, bool big) {
   c->counters.emplace_back("encode_groups", (double)grid);
   c->counters.emplace_back("encode_groups_per_cu", (double)occ);
   if (big) {
-    const uint32_t gb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nblk + 7) / 8, (uint64_t)c->n_cu * 3));
+    const uint64_t items = list ? nlist : nblk;
+    const uint32_t gb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((items + 7) / 8, (uint64_t)c->n_cu * 3));
     KTimer kb(c, "k_encode_big");
-    hipLaunchKernelGGL(k_encode_big, dim3(gb), dim3(512), 0, c->stream, A);
+    hipLaunchKernelGGL(k_encode_big, dim3(gb), dim3(512), 0, c->stream, A, list, nlist);
     LAUNCH_CHECK();
     kb.stop();
   }
@@ -1196,18 +1199,20 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   uint64_t NBLK, NF, NW;
   uint32_t max_bsize;
   bool big_blocks = true;
+  uint64_t n_off = 0;  // blocks off the pipelined encoder's path
   {
     Mail m(c);
     const uint64_t* a = m.add(job_ob0 + J, 1);
     const uint64_t* b = m.add(job_f0 + J, 1);
     const uint64_t* w = m.add(of.w0 + FC, 1);
-    const uint32_t* x = m.add(stats, 3);
+    const uint32_t* x = m.add(stats, 4);
     m.flush();
     NBLK = *a;
     NF = *b;
     NW = *w;
     max_bsize = x[0];
-    big_blocks = (uint64_t)x[0] + 1 > 64 * 16 * ENC_PIPE_CHUNKS || x[1] > 64 || x[2] != 0;
+    big_blocks = x[3] != 0;
+    n_off = x[3];
     c->counters.emplace_back("max_block_bytes", (double)max_bsize);
   }
 
@@ -1248,7 +1253,17 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
                      (const uint8_t*)ztype);
   LAUNCH_CHECK();
   BlockRec* brec = dbuf<BlockRec>(c, "blk_rec", NBLK);
-  hipLaunchKernelGGL(k_block_dst, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.d_jobs, job_ob0 + J, NBLK, brec);
+  // a few blocks off the pipelined path are listed, so that k_encode_big
+  // need not look at every block; when they are many it looks at every block
+  uint64_t* off_list = nullptr;
+  uint32_t* off_n = nullptr;
+  if (!P.compress && n_off && n_off <= NBLK / 8) {
+    off_list = dbuf<uint64_t>(c, "enc_off_list", n_off);
+    off_n = dbuf<uint32_t>(c, "enc_off_n", 1);
+    fill_u32(c, off_n, 0, 1);
+  }
+  hipLaunchKernelGGL(k_block_dst, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.d_jobs, job_ob0 + J, NBLK, brec,
+                     off_list, off_n);
   LAUNCH_CHECK();
   O.file_out.assign(NF + 1, 0);
   O.file_size.assign(NF, 0);
@@ -1312,7 +1327,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, NBLK * 16)), dim3(256), 0, st, A);  // 16 threads per block
     LAUNCH_CHECK();
     kg.stop();
-    launch_encode(c, A, NBLK, big_blocks);
+    launch_encode(c, A, NBLK, big_blocks, off_list, n_off);
   }
   mark(c, "encode");
   if (NW) {
