@@ -333,16 +333,17 @@ __device__ __forceinline__ uint32_t crc_chunk_plain(const CrcLds* T, uint4 v) {
 // Raw CRC (first 4 message bytes complemented) of message bytes
 // [s0, s0 + len) of a message that starts at msg; len is a multiple of 16 or
 // s0 <= 0 (a segment starting before the message counts only its bytes
-// inside it).  Chunks are aligned to the segment end.  A lane takes its
-// chunks first to last; the ones that reach below message position 4 come
-// first and are folded by the edge rules, the rest plainly, CRC_Q chunks at
-// a time with all their loads issued before the first fold.  Every lane
-// must call.
+// inside it).  Chunks are aligned to the segment end; those wholly before
+// the message are leading zeros, which leave the raw CRC unchanged, and are
+// skipped.  A lane takes its chunks first to last; the ones that reach below
+// message position 4 come first and are folded by the edge rules, the rest
+// plainly, CRC_Q chunks at a time with all their loads issued before the
+// first fold.  Every lane must call.
 constexpr int CRC_Q = 5;
 __device__ __forceinline__ uint32_t wave_raw_crc(const CrcLds* T, const uint8_t* msg, int64_t s0, uint64_t len) {
   const uint32_t l = lane_id();
   const int64_t send = s0 + (int64_t)len;
-  const int64_t J = (int64_t)((len + 15) / 16);
+  const int64_t J = min((int64_t)((len + 15) / 16), (send + 15) / 16);
   uint32_t acc = 0;
   const int64_t c_first = 63 - (int64_t)l;
   int64_t c = c_first < J ? c_first + 64 * ((J - 1 - c_first) / 64) : -1;

@@ -277,12 +277,9 @@ struct IndexMsgs {
   __device__ void empty(uint32_t m) const { ok[m] = 0; }
 };
 
-template __global__ void k_crc_multi<IndexMsgs>(IndexMsgs, const uint32_t*, uint32_t*, uint32_t*);
-
 void launch_crc_index(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
-                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_crc_multi<IndexMsgs>, dim3(grid), dim3(1024), 0, st, IndexMsgs{ws, in, ok, err}, g_crc, part,
-                     ticket);
+                      uint64_t cap, uint32_t* part, uint64_t* mseg, uint32_t grid, hipStream_t st) {
+  launch_crc_msgs(IndexMsgs{ws, in, ok, err}, cap, g_crc, part, mseg, grid, st);
 }
 
 // interval -> block map: the block of interval i is the last b with

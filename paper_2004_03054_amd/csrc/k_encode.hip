@@ -680,31 +680,90 @@ __global__ void k_filter_offsets(OutFiles of, const uint64_t* nwin, const uint32
   for (int k = 0; k < 4; k++) dst[k] = (uint8_t)(v >> (8 * k));
 }
 
-__global__ void k_index_write(OutBlocks ob, OutFiles of, Tuples tu, const uint32_t* surv, const uint64_t* ie_off,
-                              const uint64_t* nblocks, uint32_t kw8, uint64_t cap, uint8_t* out) {
-  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= cap || b >= *nblocks) return;
-  const uint32_t f = ob.file[b];
-  const uint64_t b0 = of.b0[f];
-  const uint64_t rel = ie_off[b] - ie_off[b0];
-  uint8_t* base = out + of.out[f] + of.index_off[f];
-  uint8_t* d = base + rel;
-  const uint32_t e = surv[ob.s0[b] + ob.cnt[b] - 1];
-  const uint32_t ulen = tu.ulen[e];
-  const uint32_t klen = ulen + 8;
-  const uint64_t boff = ob.off[b];
-  const uint32_t bsz = ob.size[b];
-  const uint32_t hlen = varint_len(boff) + varint_len(bsz);
+// One thread per data block: its index entry (shared 0, key length, handle
+// length, the block's last internal key, the handle) and its restart slot.
+// The entries of a wave's 64 blocks are one contiguous range when the blocks
+// belong to one file: they are assembled in LDS, at the range's alignment,
+// and stored as whole 16-byte lines (bytes at the two ends one at a time).
+// Otherwise each thread writes its entry directly.
+constexpr uint32_t IW_WAVES = 4;     // waves per workgroup (the launch bound)
+constexpr uint32_t IW_CAP = 4096;    // staged bytes per wave
+
+__device__ inline uint32_t put_index_entry(uint8_t* d, uint32_t klen, uint32_t hlen, const uint8_t* slot,
+                                           uint32_t ulen, uint64_t tag, uint64_t boff, uint32_t bsz) {
   uint32_t p = 0;
   d[p++] = 0;
   p += put_varint(d + p, klen);
   p += put_varint(d + p, hlen);
-  const uint8_t* slot = (const uint8_t*)(tu.heap + (uint64_t)e * kw8);
   for (uint32_t i = 0; i < ulen; i++) d[p++] = slot[i];
-  const uint64_t tag = tu.tag[e];
   for (int i = 0; i < 8; i++) d[p++] = (uint8_t)(tag >> (8 * i));
   p += put_varint(d + p, boff);
   p += put_varint(d + p, bsz);
+  return p;
+}
+
+__global__ void __launch_bounds__(IW_WAVES * 64) k_index_write(OutBlocks ob, OutFiles of, Tuples tu,
+                                                               const uint32_t* surv, const uint64_t* ie_off,
+                                                               const uint64_t* nblocks, uint32_t kw8, uint64_t cap,
+                                                               uint8_t* out) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage_all[IW_WAVES][IW_CAP];
+  uint8_t* S = stage_all[threadIdx.x / WAVE];
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = b < cap && b < *nblocks;  // the valid lanes of a wave are a prefix of it
+  uint32_t f = 0, klen = 0, hlen = 0, ulen = 0, bsz = 0, len = 0;
+  uint64_t b0 = 0, rel = 0, boff = 0, tag = 0;
+  uint8_t* base = nullptr;
+  const uint8_t* slot = nullptr;
+  if (in) {
+    f = ob.file[b];
+    b0 = of.b0[f];
+    rel = ie_off[b] - ie_off[b0];
+    base = out + of.out[f] + of.index_off[f];
+    const uint32_t e = surv[ob.s0[b] + ob.cnt[b] - 1];
+    ulen = tu.ulen[e];
+    klen = ulen + 8;
+    boff = ob.off[b];
+    bsz = ob.size[b];
+    hlen = varint_len(boff) + varint_len(bsz);
+    slot = (const uint8_t*)(tu.heap + (uint64_t)e * kw8);
+    tag = tu.tag[e];
+    len = 1 + varint_len(klen) + varint_len(hlen) + klen + hlen;
+  }
+  const uint64_t act = __ballot(in);
+  if (!act) return;
+  const int last = 63 - __builtin_clzll(act);
+  const uint32_t f0 = (uint32_t)__shfl((int)f, 0, WAVE);
+  const uint64_t lo = ((uint64_t)(uint32_t)__shfl((int)(rel >> 32), 0, WAVE) << 32) |
+                      (uint32_t)__shfl((int)(uint32_t)rel, 0, WAVE);
+  const uint64_t end = rel + len;
+  const uint64_t hi = ((uint64_t)(uint32_t)__shfl((int)(end >> 32), last, WAVE) << 32) |
+                      (uint32_t)__shfl((int)(uint32_t)end, last, WAVE);
+  const uint64_t gb = (uint64_t)(uintptr_t)base;
+  const uint64_t gbase = ((uint64_t)(uint32_t)__shfl((int)(gb >> 32), 0, WAVE) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)gb, 0, WAVE);
+  const uint64_t dst0 = gbase + lo;
+  const uint32_t a = (uint32_t)(dst0 & 15);
+  const bool one_file = __ballot(in && f != f0) == 0;
+  if (one_file && a + (hi - lo) <= IW_CAP) {
+    if (in) put_index_entry(S + a + (rel - lo), klen, hlen, slot, ulen, tag, boff, bsz);
+    wave_sync();
+    const uint64_t line0 = dst0 - a;  // 16-byte aligned
+    const uint32_t nl = (uint32_t)((a + (hi - lo) + 15) / 16);
+    for (uint32_t i = lane_id(); i < nl; i += WAVE) {
+      uint8_t* g = (uint8_t*)(uintptr_t)(line0 + 16ull * i);
+      const uint32_t k0 = 16 * i, k1 = k0 + 16;
+      if (k0 >= a && k1 <= a + (uint32_t)(hi - lo)) {
+        *(uint4*)g = *(const uint4*)(S + k0);
+      } else {
+        for (uint32_t k = k0; k < k1; k++)
+          if (k >= a && k < a + (uint32_t)(hi - lo)) g[k - k0] = S[k];
+      }
+    }
+    wave_sync();
+  } else if (in) {
+    put_index_entry(base + rel, klen, hlen, slot, ulen, tag, boff, bsz);
+  }
+  if (!in) return;
   // restart array slot
   const uint64_t entries = ie_off[b0 + of.nb[f]] - ie_off[b0];
   uint8_t* r = base + entries + 4 * (b - b0);
@@ -779,12 +838,9 @@ struct FileMsgs {
   __device__ void empty(uint32_t) const {}
 };
 
-template __global__ void k_crc_multi<FileMsgs>(FileMsgs, const uint32_t*, uint32_t*, uint32_t*);
-
 void launch_crc_files(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
-                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_crc_multi<FileMsgs>, dim3(grid), dim3(1024), 0, st, FileMsgs{of, nfiles, cap, out}, g_crc,
-                     part, ticket);
+                      uint32_t* part, uint64_t* mseg, uint32_t grid, hipStream_t st) {
+  launch_crc_msgs(FileMsgs{of, nfiles, cap, out}, 3 * cap, g_crc, part, mseg, grid, st);
 }
 
 }  // namespace luda

@@ -385,12 +385,9 @@ struct ZBlockMsgs {
   __device__ void empty(uint32_t) const {}
 };
 
-template __global__ void k_crc_multi<ZBlockMsgs>(ZBlockMsgs, const uint32_t*, uint32_t*, uint32_t*);
-
 void launch_crc_zblocks(const BlockRec* br, const uint64_t* nblocks, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
-                        uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_crc_multi<ZBlockMsgs>, dim3(grid), dim3(1024), 0, st, ZBlockMsgs{br, nblocks, cap, out}, g_crc,
-                     part, ticket);
+                        uint32_t* part, uint64_t* mseg, uint32_t grid, hipStream_t st) {
+  launch_crc_msgs(ZBlockMsgs{br, nblocks, cap, out}, cap, g_crc, part, mseg, grid, st);
 }
 
 // Per file whose first data block is stored compressed: its smallest

@@ -88,8 +88,9 @@ __global__ void k_unsnappy(WalkSet ws, Inputs in, uint8_t* ok, const uint64_t* z
 __global__ void k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
                            unsigned long long* bytes_total);
 // checksums of the inputs' index blocks against their trailers
+// (at most cap index blocks; part and mseg as for k_crc_multi)
 void launch_crc_index(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok, unsigned long long* err,
-                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
+                      uint64_t cap, uint32_t* part, uint64_t* mseg, uint32_t grid, hipStream_t st);
 __global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev, uint32_t* iblk);
 template <int KIND, int MODE>
 __global__ void k_walk(WalkArgs A);
@@ -271,9 +272,9 @@ __global__ void k_ingest(const uint8_t* keys, const uint64_t* koff, const uint64
                          const uint64_t* voff, uint64_t n, Tuples tu, uint32_t kw8, uint32_t* surv);
 __global__ void k_check_sorted(Tuples tu, uint32_t kw8, uint64_t n, uint32_t* bad);
 // checksums of every file's filter, metaindex and index blocks (trailers
-// written); part and ticket as for k_crc_multi
+// written); part and mseg (3 cap + 1 slots) as for k_crc_multi
 void launch_crc_files(OutFiles of, const uint64_t* nfiles, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
-                      uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
+                      uint32_t* part, uint64_t* mseg, uint32_t grid, hipStream_t st);
 
 // compressed output blocks (k_snappy.hip)
 __global__ void k_zprep(OutBlocks ob, const uint64_t* nblocks, uint64_t cap, uint32_t* zraw, uint64_t* zstride);
@@ -284,7 +285,7 @@ __global__ void k_zsnappy(OutBlocks ob, const JobDesc* jobs, const uint64_t* nbl
 __global__ void k_zplace(const BlockRec* br, const uint64_t* nblocks, const uint8_t* stage, const uint8_t* zbuf,
                          const uint64_t* zoff, const uint8_t* ztype, uint8_t* out);
 void launch_crc_zblocks(const BlockRec* br, const uint64_t* nblocks, uint64_t cap, uint8_t* out, const uint32_t* g_crc,
-                        uint32_t* part, uint32_t* ticket, uint32_t grid, hipStream_t st);
+                        uint32_t* part, uint64_t* mseg, uint32_t grid, hipStream_t st);
 __global__ void k_zslots(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint8_t* ztype,
                          const uint64_t* nfiles, uint64_t cap, uint64_t* stride);
 __global__ void k_zkeys(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint8_t* ztype,

@@ -395,25 +395,13 @@ T* dbuf(luda_ctx* c, const std::string& name, size_t count) {
   return (T*)b.p;
 }
 
-// counters that the kernels leave at zero: zero-filled when (re)allocated
 void fill_u32(luda_ctx* c, void* p, uint32_t v, uint64_t n);
-uint32_t* ticket_buf(luda_ctx* c, const std::string& name, uint64_t n) {
-  if (c->arena) {  // the scratch array keeps whatever the last call left there
-    uint32_t* p = dbuf<uint32_t>(c, name, n);
-    fill_u32(c, p, 0, n);
-    return p;
-  }
-  const DBuf before = c->bufs[name];
-  uint32_t* p = dbuf<uint32_t>(c, name, n);
-  const DBuf& now = c->bufs[name];
-  if (now.p != before.p || now.cap != before.cap) fill_u32(c, p, 0, now.cap / 4);
-  return p;
-}
 
 // grid of the multi-workgroup checksum over messages of at most `bytes`
 // bytes in total (segments of CRC_SEG_BYTES, one per message at least)
 uint32_t crc_multi_grid(const luda_ctx* c, uint64_t bytes, uint64_t msgs) {
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bytes / CRC_SEG_BYTES + msgs, 2ull * c->n_cu));
+  // a wave per segment, 16 waves per workgroup
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((bytes / CRC_SEG_BYTES + msgs + 15) / 16, 2ull * c->n_cu));
 }
 
 inline uint32_t blocks_for(uint64_t n, uint32_t t = 256) {
@@ -1307,8 +1295,8 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     LAUNCH_CHECK();
     const uint64_t segs = dout / CRC_SEG_BYTES + NBLK + 1;
     uint32_t* part = dbuf<uint32_t>(c, "zw_crc_part", segs);
-    uint32_t* ticket = ticket_buf(c, "zw_crc_ticket", NBLK);
-    launch_crc_zblocks(brec, job_ob0 + J, NBLK, out, c->d_crc, part, ticket, crc_multi_grid(c, dout, NBLK), st);
+    uint64_t* mseg = dbuf<uint64_t>(c, "zw_crc_mseg", NBLK + 1);
+    launch_crc_zblocks(brec, job_ob0 + J, NBLK, out, c->d_crc, part, mseg, crc_multi_grid(c, dout, NBLK), st);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_zkeys, dim3(blocks_for(NF)), dim3(256), 0, st, of, ob, P.d_surv, P.tu, ztype, P.kw8, NF,
                        out);
@@ -1379,8 +1367,8 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     KTimer kt(c, "k_crc_tables");
     const uint64_t segs = O.total_bytes / CRC_SEG_BYTES + 3 * NF + 1;
     uint32_t* part = dbuf<uint32_t>(c, "of_crc_part", segs);
-    uint32_t* ticket = ticket_buf(c, "of_crc_ticket", 3 * NF);
-    launch_crc_files(of, job_f0 + J, NF, out, c->d_crc, part, ticket, crc_multi_grid(c, O.total_bytes, 3 * NF), st);
+    uint64_t* mseg = dbuf<uint64_t>(c, "of_crc_mseg", 3 * NF + 1);
+    launch_crc_files(of, job_f0 + J, NF, out, c->d_crc, part, mseg, crc_multi_grid(c, O.total_bytes, 3 * NF), st);
     LAUNCH_CHECK();
     kt.stop();
   }
@@ -1568,8 +1556,8 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     {
       const uint64_t segs = total_in / CRC_SEG_BYTES + NG + 1;
       uint32_t* part = dbuf<uint32_t>(c, "ix_crc_part", segs);
-      uint32_t* ticket = ticket_buf(c, "ix_crc_ticket", NG);
-      launch_crc_index(ix, in, c->d_crc, IX.ok, err, part, ticket, crc_multi_grid(c, total_in, NG), st);
+      uint64_t* mseg = dbuf<uint64_t>(c, "ix_crc_mseg", (uint64_t)NG + 1);
+      launch_crc_index(ix, in, c->d_crc, IX.ok, err, NG, part, mseg, crc_multi_grid(c, total_in, NG), st);
       LAUNCH_CHECK();
     }
 

@@ -26,8 +26,8 @@ enum FooterPhase : uint32_t { FP_SHORT = 0, FP_REL = 1 };
 constexpr uint64_t ERR_NONE = ~0ull;
 constexpr uint64_t TABLE_MAGIC = 0xdb4775248b80fb57ull;
 constexpr uint32_t FILTER_BASE_LG = 11;
-// bytes of one segment of a long block's checksum (one workgroup step)
-constexpr uint32_t CRC_SEG_BYTES = 16384;
+// bytes of one segment of a long block's checksum (one wave step)
+constexpr uint32_t CRC_SEG_BYTES = 4096;
 
 struct JobDesc {
   uint32_t block_size;
