@@ -464,63 +464,111 @@ __global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out) {
 // ---------------------------------------------------------------------------
 // output blocks
 
-__global__ void k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s, const JobDesc* jobs,
-                             const uint32_t* seg_first, const uint32_t* sz_r, const uint32_t* sz_n,
-                             const EncRec* rec, uint64_t cap, OutBlocks ob, uint32_t* ent_off, EntL* entl,
-                             uint32_t* gapcnt) {
+// One thread per output block: its record (first entry, count, contents
+// size, job), each entry's offset in the block and the value interior of
+// each entry in the chunk grid of the block message (contents and type
+// byte): the whole chunks between the first grid position at or after the
+// value start and the last one at or before its end.  The entries of a
+// wave's 64 consecutive blocks are one contiguous range; their offsets and
+// interiors are assembled in LDS and stored contiguously (a range past
+// BM_CAP entries, or one that is not contiguous, is stored directly).
+constexpr uint32_t BM_WAVES = 4;   // waves per workgroup (the launch bound)
+constexpr uint32_t BM_CAP = 256;   // staged entries per wave
+
+struct BmStage {
+  EntL e[BM_CAP];
+  uint32_t off[BM_CAP];
+};
+
+__global__ void __launch_bounds__(BM_WAVES * 64) k_block_meta(const uint64_t* job_ob0, uint32_t J, const SegJob* sj_s,
+                                                              const JobDesc* jobs, const uint32_t* seg_first,
+                                                              const uint32_t* sz_r, const uint32_t* sz_n,
+                                                              const EncRec* rec, uint64_t cap, OutBlocks ob,
+                                                              uint32_t* ent_off, EntL* entl, uint32_t* gapcnt) {
+  __shared__ BmStage stage_all[BM_WAVES];
+  BmStage& S = stage_all[threadIdx.x / WAVE];
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= cap) return;
-  if (b >= job_ob0[J]) {
+  const uint64_t nb = job_ob0[J];
+  if (b < cap && b >= nb) {
     ob.full[b] = 0;
     gapcnt[b] = 0;
-    return;
   }
-  const uint32_t j = job_of(job_ob0, J, b);
-  const uint64_t sbase = sj_s[j].base;
-  const uint32_t m = sj_s[j].m;
-  const uint32_t first = seg_first[b];
-  const uint32_t end = (b + 1 < job_ob0[j + 1]) ? seg_first[b + 1] : m;
-  const uint32_t R = jobs[j].restart_interval;
-  const uint32_t cnt = end - first;
-  uint64_t E = 0;
-  uint32_t r = 0;
-  for (uint32_t t = first; t < end; t++) {
-    ent_off[sbase + t] = (uint32_t)E;
-    E += (r == 0) ? sz_r[sbase + t] : sz_n[sbase + t];
-    if (++r == R) r = 0;
+  const bool in = b < cap && b < nb;  // the valid lanes of a wave are a prefix of it
+  uint32_t j = 0, first = 0, end = 0, R = 1;
+  uint64_t sbase = 0;
+  if (in) {
+    j = job_of(job_ob0, J, b);
+    sbase = sj_s[j].base;
+    first = seg_first[b];
+    end = (b + 1 < job_ob0[j + 1]) ? seg_first[b + 1] : sj_s[j].m;
+    R = jobs[j].restart_interval;
   }
-  const uint64_t content = E + 4ull * ((cnt + R - 1) / R) + 4;
-  ob.s0[b] = sbase + first;
-  ob.cnt[b] = cnt;
-  ob.size[b] = content;
-  ob.full[b] = content + 5;
-  ob.job[b] = j;
-  // value interiors in the chunk grid of the block message (contents and
-  // type byte): the whole chunks between the first grid position at or
-  // after the value start and the last one at or before its end
-  const uint32_t n = (uint32_t)content + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
-  uint32_t cum = 0;
-  for (uint32_t t = first; t < end; t++) {
-    const uint64_t s = sbase + t;
-    const EncRec rc = rec[s];
-    const uint32_t i = t - first;
-    const uint32_t sh = (i % R == 0) ? 0u : rc.shared;
-    const uint32_t ns = rc.ulen + 8 - sh;
-    const uint32_t vs = ent_off[s] + varint_len(sh) + varint_len(ns) + varint_len(rc.vlen) + ns;
-    const uint32_t en = vs + rc.vlen;
-    const uint32_t ia = (vs + gshift + 15) / 16;  // first grid position >= vs is 16 ia - gshift
-    const uint32_t iz = (en + gshift) / 16;       // last grid position <= en is 16 iz - gshift
-    const uint32_t pieces = iz > ia ? iz - ia : 0;
-    EntL L;
-    L.vsrc = rc.vp - (uint64_t)vs - (uint64_t)gshift;
-    L.ia = ia;
-    L.pieces = pieces;
-    L.cum = cum;
-    L.pad = 0;
-    entl[s] = L;
-    cum += pieces;
+  const uint64_t s0 = sbase + first, s1 = sbase + end;  // this block's entries [s0, s1)
+  if (!__ballot(in)) return;
+  // staged when the wave's entries are contiguous and few enough
+  const uint64_t prev_end = ((uint64_t)(uint32_t)__shfl_up((int)(s1 >> 32), 1, WAVE) << 32) |
+                            (uint32_t)__shfl_up((int)(uint32_t)s1, 1, WAVE);
+  const bool gap = in && lane_id() > 0 && prev_end != s0;
+  const int last = 63 - __builtin_clzll(__ballot(in));
+  const uint64_t lo = ((uint64_t)(uint32_t)__shfl((int)(s0 >> 32), 0, WAVE) << 32) |
+                      (uint32_t)__shfl((int)(uint32_t)s0, 0, WAVE);
+  const uint64_t hi = ((uint64_t)(uint32_t)__shfl((int)(s1 >> 32), last, WAVE) << 32) |
+                      (uint32_t)__shfl((int)(uint32_t)s1, last, WAVE);
+  const bool staged = !__ballot(gap) && hi - lo <= BM_CAP;
+  if (in) {
+    const uint32_t cnt = end - first;
+    uint64_t E = 0;
+    uint32_t r = 0;
+    for (uint64_t s = s0; s < s1; s++) {
+      E += (r == 0) ? sz_r[s] : sz_n[s];
+      if (++r == R) r = 0;
+    }
+    const uint64_t content = E + 4ull * ((cnt + R - 1) / R) + 4;
+    ob.s0[b] = s0;
+    ob.cnt[b] = cnt;
+    ob.size[b] = content;
+    ob.full[b] = content + 5;
+    ob.job[b] = j;
+    const uint32_t n = (uint32_t)content + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
+    uint32_t cum = 0, off = 0;
+    for (uint64_t s = s0; s < s1; s++) {
+      const EncRec rc = rec[s];
+      const uint32_t i = (uint32_t)(s - s0);
+      const bool restart = i % R == 0;
+      const uint32_t sh = restart ? 0u : rc.shared;
+      const uint32_t ns = rc.ulen + 8 - sh;
+      const uint32_t vs = off + varint_len(sh) + varint_len(ns) + varint_len(rc.vlen) + ns;
+      const uint32_t en = vs + rc.vlen;
+      const uint32_t ia = (vs + gshift + 15) / 16;  // first grid position >= vs is 16 ia - gshift
+      const uint32_t iz = (en + gshift) / 16;       // last grid position <= en is 16 iz - gshift
+      const uint32_t pieces = iz > ia ? iz - ia : 0;
+      EntL L;
+      L.vsrc = rc.vp - (uint64_t)vs - (uint64_t)gshift;
+      L.ia = ia;
+      L.pieces = pieces;
+      L.cum = cum;
+      L.pad = 0;
+      if (staged) {
+        S.e[s - lo] = L;
+        S.off[s - lo] = off;
+      } else {
+        entl[s] = L;
+        ent_off[s] = off;
+      }
+      cum += pieces;
+      off += restart ? sz_r[s] : sz_n[s];
+    }
+    gapcnt[b] = J16 - cum + 1;  // and the head slot
   }
-  gapcnt[b] = J16 - cum + 1;  // and the head slot
+  if (staged) {
+    wave_sync();
+    const uint32_t m = (uint32_t)(hi - lo);
+    for (uint32_t q = lane_id(); q < m; q += WAVE) {
+      entl[lo + q] = S.e[q];
+      ent_off[lo + q] = S.off[q];
+    }
+    wave_sync();
+  }
 }
 
 // per output file: block range, data bytes, filter window count
