@@ -313,7 +313,7 @@ __global__ void k_imap(WalkSet ws, const uint64_t* ibase, const uint64_t* ni_dev
 // contiguous, whole-line writes; a lane walking its interval would otherwise
 // write each record field to 64 scattered places per instruction.  Records
 // past EMIT_CAP in the range are stored directly.
-constexpr uint32_t EMIT_CAP = 256;
+constexpr uint32_t EMIT_CAP = 512;
 constexpr uint32_t EMIT_WAVES = 4;  // waves per workgroup (the launch bound)
 
 template <uint32_t CAP>
