@@ -92,23 +92,30 @@ struct BlockNext {
   const SegJob* sj;
   const uint32_t* sz_r;
   const uint32_t* sz_n;
+  // (4 items per step, their loads issued first; indices clamped to the
+  // job's last item, extras unused)
   __device__ uint32_t operator()(uint32_t j, uint32_t i) const {
     const uint64_t base = sj[j].base;
     const uint32_t m = sj[j].m;
     const uint32_t R = jobs[j].restart_interval;
     const uint64_t bs = jobs[j].block_size;
     uint64_t E = 0;
-    uint32_t r = 0;  // (t - i) % R
     uint64_t nrest = 0;
-    for (uint32_t t = i; t < m; t++) {
-      if (r == 0) {
-        E += sz_r[base + t];
-        nrest++;
-      } else {
-        E += sz_n[base + t];
+    for (uint32_t t4 = i; t4 < m; t4 += 4) {
+      uint32_t a[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++) {
+        const uint32_t t = min(t4 + q, m - 1);
+        a[q] = ((t - i) % R == 0 ? sz_r : sz_n)[base + t];
       }
-      if (++r == R) r = 0;
-      if (E + 4 * nrest + 4 >= bs) return t + 1;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++) {
+        const uint32_t t = t4 + q;
+        if (t >= m) break;
+        if ((t - i) % R == 0) nrest++;
+        E += a[q];
+        if (E + 4 * nrest + 4 >= bs) return t + 1;
+      }
     }
     return m;
   }
@@ -474,6 +481,7 @@ __global__ void k_small_scan(const uint32_t* v, uint32_t J, uint64_t* out) {
 // BM_CAP entries, or one that is not contiguous, is stored directly).
 constexpr uint32_t BM_WAVES = 4;   // waves per workgroup (the launch bound)
 constexpr uint32_t BM_CAP = 256;   // staged entries per wave
+constexpr uint32_t BM_U = 4;       // entries per loop step
 
 struct BmStage {
   EntL e[BM_CAP];
@@ -517,11 +525,19 @@ __global__ void __launch_bounds__(BM_WAVES * 64) k_block_meta(const uint64_t* jo
   const bool staged = !__ballot(gap) && hi - lo <= BM_CAP;
   if (in) {
     const uint32_t cnt = end - first;
+    // the loops take BM_U entries per step with all their loads issued
+    // first (indices clamped to the block's last entry, extras unused)
     uint64_t E = 0;
-    uint32_t r = 0;
-    for (uint64_t s = s0; s < s1; s++) {
-      E += (r == 0) ? sz_r[s] : sz_n[s];
-      if (++r == R) r = 0;
+    for (uint64_t s = s0; s < s1; s += BM_U) {
+      uint32_t a[BM_U];
+#pragma unroll
+      for (uint32_t q = 0; q < BM_U; q++) {
+        const uint64_t t = min(s + q, s1 - 1);
+        a[q] = ((t - s0) % R == 0 ? sz_r : sz_n)[t];
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < BM_U; q++)
+        if (s + q < s1) E += a[q];
     }
     const uint64_t content = E + 4ull * ((cnt + R - 1) / R) + 4;
     ob.s0[b] = s0;
@@ -531,32 +547,45 @@ __global__ void __launch_bounds__(BM_WAVES * 64) k_block_meta(const uint64_t* jo
     ob.job[b] = j;
     const uint32_t n = (uint32_t)content + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
     uint32_t cum = 0, off = 0;
-    for (uint64_t s = s0; s < s1; s++) {
-      const EncRec rc = rec[s];
-      const uint32_t i = (uint32_t)(s - s0);
-      const bool restart = i % R == 0;
-      const uint32_t sh = restart ? 0u : rc.shared;
-      const uint32_t ns = rc.ulen + 8 - sh;
-      const uint32_t vs = off + varint_len(sh) + varint_len(ns) + varint_len(rc.vlen) + ns;
-      const uint32_t en = vs + rc.vlen;
-      const uint32_t ia = (vs + gshift + 15) / 16;  // first grid position >= vs is 16 ia - gshift
-      const uint32_t iz = (en + gshift) / 16;       // last grid position <= en is 16 iz - gshift
-      const uint32_t pieces = iz > ia ? iz - ia : 0;
-      EntL L;
-      L.vsrc = rc.vp - (uint64_t)vs - (uint64_t)gshift;
-      L.ia = ia;
-      L.pieces = pieces;
-      L.cum = cum;
-      L.pad = 0;
-      if (staged) {
-        S.e[s - lo] = L;
-        S.off[s - lo] = off;
-      } else {
-        entl[s] = L;
-        ent_off[s] = off;
+    for (uint64_t s4 = s0; s4 < s1; s4 += BM_U) {
+      EncRec rq[BM_U];
+      uint32_t zq[BM_U];
+#pragma unroll
+      for (uint32_t q = 0; q < BM_U; q++) {
+        const uint64_t t = min(s4 + q, s1 - 1);
+        rq[q] = rec[t];
+        zq[q] = ((t - s0) % R == 0 ? sz_r : sz_n)[t];
       }
-      cum += pieces;
-      off += restart ? sz_r[s] : sz_n[s];
+#pragma unroll
+      for (uint32_t q = 0; q < BM_U; q++) {
+        const uint64_t s = s4 + q;
+        if (s >= s1) break;
+        const EncRec rc = rq[q];
+        const uint32_t i = (uint32_t)(s - s0);
+        const bool restart = i % R == 0;
+        const uint32_t sh = restart ? 0u : rc.shared;
+        const uint32_t ns = rc.ulen + 8 - sh;
+        const uint32_t vs = off + varint_len(sh) + varint_len(ns) + varint_len(rc.vlen) + ns;
+        const uint32_t en = vs + rc.vlen;
+        const uint32_t ia = (vs + gshift + 15) / 16;  // first grid position >= vs is 16 ia - gshift
+        const uint32_t iz = (en + gshift) / 16;       // last grid position <= en is 16 iz - gshift
+        const uint32_t pieces = iz > ia ? iz - ia : 0;
+        EntL L;
+        L.vsrc = rc.vp - (uint64_t)vs - (uint64_t)gshift;
+        L.ia = ia;
+        L.pieces = pieces;
+        L.cum = cum;
+        L.pad = 0;
+        if (staged) {
+          S.e[s - lo] = L;
+          S.off[s - lo] = off;
+        } else {
+          entl[s] = L;
+          ent_off[s] = off;
+        }
+        cum += pieces;
+        off += zq[q];
+      }
     }
     gapcnt[b] = J16 - cum + 1;  // and the head slot
   }
