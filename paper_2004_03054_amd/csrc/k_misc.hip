@@ -14,6 +14,10 @@ __global__ void k_mail(MailSegs m, uint8_t* mail) {
   for (uint32_t i = threadIdx.x; i < m.bytes[s]; i += blockDim.x) dst[i] = src[i];
 }
 
+__global__ void k_mail_flag(uint64_t* flag, uint64_t seq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // scatter host-staged bytes (pinned host memory) to device buffers
 __global__ void k_upload(UpSegs u, const uint8_t* up) {
   const uint32_t s = blockIdx.x;

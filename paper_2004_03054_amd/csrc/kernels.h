@@ -253,6 +253,8 @@ struct MailSegs {
   uint32_t n;
 };
 __global__ void k_mail(MailSegs m, uint8_t* mail);
+// the readback's sequence number, written after k_mail into pinned memory
+__global__ void k_mail_flag(uint64_t* flag, uint64_t seq);
 struct UpSegs {
   uint64_t dst[16];
   uint32_t bytes[16];

@@ -210,7 +210,8 @@ struct luda_ctx {
   Arena* arena = nullptr;
   luda_allocator alloc{};  // caller's device allocator (luda_set_allocator); alloc.alloc == NULL: hipMalloc
   // pinned host memory: readbacks (written by k_mail) and staged uploads
-  uint8_t* mail = nullptr;
+  uint8_t* mail = nullptr;  // mail_cap bytes, then the readback flag (8 bytes)
+  uint64_t mail_seq = 0;
   size_t mail_cap = 0;
   uint8_t* stage = nullptr;
   size_t stage_cap = 0, stage_used = 0;
@@ -483,6 +484,11 @@ struct Mail {
     m.n++;
     return (const T*)(c->mail + off);
   }
+  // When every range is in the mailbox, the host polls the flag that a
+  // last kernel writes after the ranges, for at most 2 ms, instead of
+  // waiting in a stream synchronisation; past that (a long stage, or a
+  // failed one: its error is reported by the synchronisation) it
+  // synchronises the stream.
   void flush() {
     up_flush(c);
     for (auto& m : segs)
@@ -493,6 +499,20 @@ struct Mail {
     for (auto& b : big)
       if (b.first)
         HIPCK(hipMemcpyAsync(b.second.data(), b.first, b.second.size(), hipMemcpyDeviceToHost, c->stream));
+    if (!big.empty()) {
+      sync(c);
+      return;
+    }
+    const uint64_t seq = ++c->mail_seq;
+    uint64_t* flag = (uint64_t*)(c->mail + c->mail_cap);
+    hipLaunchKernelGGL(k_mail_flag, dim3(1), dim3(64), 0, c->stream, flag, seq);
+    LAUNCH_CHECK();
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t k = 0;; k++) {
+      if (__atomic_load_n((volatile uint64_t*)flag, __ATOMIC_ACQUIRE) == seq) return;
+      if ((k & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+      __builtin_ia32_pause();
+    }
     sync(c);
   }
 };
@@ -2132,7 +2152,8 @@ int luda_ctx_create(int device, luda_ctx** out) {
     HIPCK(hipMalloc((void**)&c->d_crc, sizeof(CrcTables)));
     HIPCK(hipMemcpy(c->d_crc, &T, sizeof(CrcTables), hipMemcpyHostToDevice));
     c->mail_cap = 8u << 20;
-    HIPCK(hipHostMalloc((void**)&c->mail, c->mail_cap, hipHostMallocCoherent));
+    HIPCK(hipHostMalloc((void**)&c->mail, c->mail_cap + 64, hipHostMallocCoherent));
+    *(volatile uint64_t*)(c->mail + c->mail_cap) = 0;
     c->stage_cap = 16u << 20;
     HIPCK(hipHostMalloc((void**)&c->stage, c->stage_cap, hipHostMallocCoherent));
     c->timing = getenv("LUDA_STAGE_TIMES") != nullptr;
