@@ -82,7 +82,7 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
 
 // encoder records of the output blocks (after the file layout)
 __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
-                            BlockRec* br, uint64_t* big_list, uint32_t* big_n) {
+                            BlockRec* br, uint64_t* big_list, uint32_t* big_n, uint64_t big_cap) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = b < cap && b < *nblocks;
   BlockRec r{};
@@ -103,7 +103,8 @@ __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, cons
   uint32_t base = 0;
   if (lane_id() == (uint32_t)__builtin_ctzll(m)) base = atomicAdd(big_n, (uint32_t)__popcll(m));
   base = (uint32_t)__shfl((int)base, __builtin_ctzll(m), WAVE);
-  if (big) big_list[base + __popcll(m & ((1ull << lane_id()) - 1))] = b;
+  const uint64_t at = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1));
+  if (big && at < big_cap) big_list[at] = b;
 }
 
 // Per file: its entry count, and where its smallest and largest internal

@@ -192,9 +192,10 @@ __host__ __device__ constexpr bool enc_pipelined(uint32_t size, uint32_t cnt) {
   return size + 1 >= 16 && size + 1 <= 64 * 16 * ENC_PIPE_CHUNKS && cnt <= 64;
 }
 // big_list (optional): the ids of the blocks off the pipelined path, in any
-// order, counted in big_n (room for exactly as many as there are)
+// order, counted in big_n (room for big_cap: as many as the planning
+// statistics counted; ids past it are not stored)
 __global__ void k_block_dst(OutBlocks ob, OutFiles of, const JobDesc* jobs, const uint64_t* nblocks, uint64_t cap,
-                            BlockRec* br, uint64_t* big_list, uint32_t* big_n);
+                            BlockRec* br, uint64_t* big_list, uint32_t* big_n, uint64_t big_cap);
 struct EncodeArgs {
   const JobDesc* jobs;
   OutBlocks ob;

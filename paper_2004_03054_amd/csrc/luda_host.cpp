@@ -457,8 +457,26 @@ void up(luda_ctx* c, void* dev, const void* host, size_t bytes) {
   u.n++;
 }
 
+// Waits for the work queued so far on the context's stream: a last kernel
+// writes a sequence number into pinned memory and the host polls it for at
+// most 2 ms; past that (a long stage, or a failed one, whose error the
+// synchronisation reports) it synchronises the stream.
+void wait_stream(luda_ctx* c) {
+  const uint64_t seq = ++c->mail_seq;
+  uint64_t* flag = (uint64_t*)(c->mail + c->mail_cap);
+  hipLaunchKernelGGL(k_mail_flag, dim3(1), dim3(64), 0, c->stream, flag, seq);
+  LAUNCH_CHECK();
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t k = 0;; k++) {
+    if (__atomic_load_n((volatile uint64_t*)flag, __ATOMIC_ACQUIRE) == seq) return;
+    if ((k & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+    __builtin_ia32_pause();
+  }
+  sync(c);
+}
+
 // --- readbacks: device ranges gathered into the pinned mailbox by one
-// kernel per 12 ranges, then one stream sync
+// kernel per 12 ranges, then a wait for the stream
 struct Mail {
   luda_ctx* c;
   std::vector<MailSegs> segs;
@@ -484,11 +502,6 @@ struct Mail {
     m.n++;
     return (const T*)(c->mail + off);
   }
-  // When every range is in the mailbox, the host polls the flag that a
-  // last kernel writes after the ranges, for at most 2 ms, instead of
-  // waiting in a stream synchronisation; past that (a long stage, or a
-  // failed one: its error is reported by the synchronisation) it
-  // synchronises the stream.
   void flush() {
     up_flush(c);
     for (auto& m : segs)
@@ -499,21 +512,8 @@ struct Mail {
     for (auto& b : big)
       if (b.first)
         HIPCK(hipMemcpyAsync(b.second.data(), b.first, b.second.size(), hipMemcpyDeviceToHost, c->stream));
-    if (!big.empty()) {
-      sync(c);
-      return;
-    }
-    const uint64_t seq = ++c->mail_seq;
-    uint64_t* flag = (uint64_t*)(c->mail + c->mail_cap);
-    hipLaunchKernelGGL(k_mail_flag, dim3(1), dim3(64), 0, c->stream, flag, seq);
-    LAUNCH_CHECK();
-    const auto t0 = std::chrono::steady_clock::now();
-    for (uint32_t k = 0;; k++) {
-      if (__atomic_load_n((volatile uint64_t*)flag, __ATOMIC_ACQUIRE) == seq) return;
-      if ((k & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
-      __builtin_ia32_pause();
-    }
-    sync(c);
+    if (big.empty()) wait_stream(c);
+    else sync(c);
   }
 };
 
@@ -1271,7 +1271,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     fill_u32(c, off_n, 0, 1);
   }
   hipLaunchKernelGGL(k_block_dst, dim3(blocks_for(NBLK)), dim3(256), 0, st, ob, of, P.d_jobs, job_ob0 + J, NBLK, brec,
-                     off_list, off_n);
+                     off_list, off_n, n_off);
   LAUNCH_CHECK();
   O.file_out.assign(NF + 1, 0);
   O.file_size.assign(NF, 0);
@@ -1968,7 +1968,7 @@ void run_batch(luda_ctx* c, const luda_job* jobs, uint32_t J, bool dev_inputs, l
     }
   }
   mark(c, "d2h");
-  sync(c);
+  wait_stream(c);
   const double ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
   // device outputs: the output buffer is handed over to the results
   DevBlock* dblk = nullptr;
