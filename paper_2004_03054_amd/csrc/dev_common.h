@@ -67,6 +67,13 @@ __device__ inline uint64_t ldg_u64_unaligned(const uint8_t* p) {
 }
 
 __device__ inline uint64_t bswap64(uint64_t x) { return __builtin_bswap64(x); }
+
+// i mod R and i / R for a restart interval R >= 1 (a power of two, the
+// usual case, takes a mask or a shift instead of a division)
+__device__ __forceinline__ uint32_t mod_r(uint32_t i, uint32_t R) { return (R & (R - 1)) == 0 ? i & (R - 1) : i % R; }
+__device__ __forceinline__ uint32_t div_r(uint32_t i, uint32_t R) {
+  return (R & (R - 1)) == 0 ? i >> __builtin_ctz(R) : i / R;
+}
 // 16 bytes at a global address of any alignment (one global_load_dwordx4)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // buffer load/store operand
 typedef uint4 __attribute__((aligned(1))) uint4_u1;

@@ -108,7 +108,7 @@ __device__ inline Ov overlap(int64_t p0, int64_t a, int64_t b) {
 template <class Ents>
 __device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, const Ents& X, int64_t p0, uint32_t i0) {
   const uint32_t R = B.R, cnt = B.cnt, size = B.size;
-  const uint32_t nrest = (cnt + R - 1) / R;
+  const uint32_t nrest = div_r(cnt + R - 1, R);
   const uint32_t data_end = size - 4 * nrest - 4;
   const uint32_t* off = A.ent_off + B.s0;
   u128 acc = 0;
@@ -118,7 +118,7 @@ __device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, const Ents& X
       const int64_t st = X.st(i);
       if (st >= pend) break;
       const EncRec r = X.rec(i);
-      const uint32_t sh = (i % R == 0) ? 0u : r.shared;
+      const uint32_t sh = mod_r(i, R) == 0 ? 0u : r.shared;
       const uint32_t ns = r.ulen + 8 - sh;
       uint32_t la, lb, lc;
       const uint64_t va = pack_varint(sh, &la), vb = pack_varint(ns, &lb), vc = pack_varint(r.vlen, &lc);

@@ -106,13 +106,13 @@ struct BlockNext {
 #pragma unroll
       for (uint32_t q = 0; q < 4; q++) {
         const uint32_t t = min(t4 + q, m - 1);
-        a[q] = ((t - i) % R == 0 ? sz_r : sz_n)[base + t];
+        a[q] = (mod_r(t - i, R) == 0 ? sz_r : sz_n)[base + t];
       }
 #pragma unroll
       for (uint32_t q = 0; q < 4; q++) {
         const uint32_t t = t4 + q;
         if (t >= m) break;
-        if ((t - i) % R == 0) nrest++;
+        if (mod_r(t - i, R) == 0) nrest++;
         E += a[q];
         if (E + 4 * nrest + 4 >= bs) return t + 1;
       }
@@ -533,13 +533,13 @@ __global__ void __launch_bounds__(BM_WAVES * 64) k_block_meta(const uint64_t* jo
 #pragma unroll
       for (uint32_t q = 0; q < BM_U; q++) {
         const uint64_t t = min(s + q, s1 - 1);
-        a[q] = ((t - s0) % R == 0 ? sz_r : sz_n)[t];
+        a[q] = (mod_r((uint32_t)(t - s0), R) == 0 ? sz_r : sz_n)[t];
       }
 #pragma unroll
       for (uint32_t q = 0; q < BM_U; q++)
         if (s + q < s1) E += a[q];
     }
-    const uint64_t content = E + 4ull * ((cnt + R - 1) / R) + 4;
+    const uint64_t content = E + 4ull * div_r(cnt + R - 1, R) + 4;
     ob.s0[b] = s0;
     ob.cnt[b] = cnt;
     ob.size[b] = content;
@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(BM_WAVES * 64) k_block_meta(const uint64_t* jo
       for (uint32_t q = 0; q < BM_U; q++) {
         const uint64_t t = min(s4 + q, s1 - 1);
         rq[q] = rec[t];
-        zq[q] = ((t - s0) % R == 0 ? sz_r : sz_n)[t];
+        zq[q] = (mod_r((uint32_t)(t - s0), R) == 0 ? sz_r : sz_n)[t];
       }
 #pragma unroll
       for (uint32_t q = 0; q < BM_U; q++) {
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(BM_WAVES * 64) k_block_meta(const uint64_t* jo
         if (s >= s1) break;
         const EncRec rc = rq[q];
         const uint32_t i = (uint32_t)(s - s0);
-        const bool restart = i % R == 0;
+        const bool restart = mod_r(i, R) == 0;
         const uint32_t sh = restart ? 0u : rc.shared;
         const uint32_t ns = rc.ulen + 8 - sh;
         const uint32_t vs = off + varint_len(sh) + varint_len(ns) + varint_len(rc.vlen) + ns;
