@@ -164,7 +164,6 @@ __device__ uint4 enc_bytes(const EncodeArgs& A, const BlockRec& B, const Ents& X
 // block's group takes its slots j, j + GAP_GROUP, ...  A block of at most
 // GAP_GROUP entries has its entries staged in LDS by the group first (one
 // round of loads), a larger one is read from global memory.
-constexpr uint32_t GAP_GROUP = 16;
 
 struct GapEnt {
   EncRec r;
@@ -214,17 +213,135 @@ __device__ __forceinline__ void gap_slot(const EncodeArgs& A, const BlockRec& B,
   A.gapbuf[g0 + g] = enc_bytes(A, B, X, p0, lo);
 }
 
+// Entry-major form of the gap chunks of a block of at most GAP_GROUP
+// entries, GAP_SLOTS gap slots and keys of at most GAP_KW8 words: the slots
+// are an LDS image of the block's gap bytes.  Message position p before
+// entry i's value interior lies in gap slot 1 + (p + gshift) / 16 - cum_i,
+// so its image byte is 16 (1 - cum_i) + gshift + p; after the interior it
+// is 16 pieces_i lower.  Each lane writes its entry's header, key delta and
+// value edges byte by byte (slot 0 also receives message bytes [0, 16),
+// interior ones included),
+// the lanes write the restart array and count, and the image is stored
+// whole.  Bytes no entry writes (before the message, the type byte) stay 0.
+
+__device__ __forceinline__ uint32_t byte_of(uint64_t lo, uint64_t hi, uint32_t k) {  // byte k (< 16) of hi:lo
+  return (uint32_t)((k < 8 ? lo >> (8 * k) : hi >> (8 * (k - 8))) & 0xFF);
+}
+
+// this lane's entry x (index i in block B) into the image I
+__device__ __forceinline__ void gap_entry_bytes(const EncodeArgs& A, const BlockRec& B, const GapEnt& x, uint32_t i,
+                                                uint32_t gshift, uint8_t* I) {
+  const EncRec& r = x.r;
+  const uint32_t sh = mod_r(i, B.R) == 0 ? 0u : r.shared;
+  const uint32_t klen = r.ulen + 8, nsk = klen - sh;
+  uint32_t la, lb, lc;
+  const uint64_t va = pack_varint(sh, &la), vb = pack_varint(nsk, &lb), vc = pack_varint(r.vlen, &lc);
+  const u128 H = (u128)va | ((u128)vb << (8 * la)) | ((u128)vc << (8 * (la + lb)));
+  const uint64_t h0 = (uint64_t)H, h1 = (uint64_t)(H >> 64);
+  const uint32_t hlen = la + lb + lc;
+  const int32_t bb = 16 * (1 - (int32_t)x.cum) + (int32_t)gshift, ba = bb - 16 * (int32_t)x.pieces;
+  const uint32_t st = x.st, ks = st + hlen, vs = ks + nsk, en = vs + r.vlen;
+  const uint32_t i0 = x.pieces ? 16 * x.ia - gshift : en, i1 = x.pieces ? 16 * (x.ia + x.pieces) - gshift : en;
+  auto put = [&](uint32_t p, int32_t base, uint32_t v) {
+    I[base + (int32_t)p] = (uint8_t)v;
+    if (p < 16) I[p] = (uint8_t)v;
+  };
+  for (uint32_t k = 0; k < hlen; k++) put(st + k, bb, byte_of(h0, h1, k));
+  // key delta: internal key bytes [sh, klen) (user key words, then the tag)
+  const uint64_t* slot = A.tu.heap + (uint64_t)r.e * A.kw8;
+  uint64_t kw[GAP_KW8];
+#pragma unroll
+  for (uint32_t w = 0; w < GAP_KW8; w++) kw[w] = w < A.kw8 ? slot[w] : 0ull;
+  for (uint32_t k = 0; k < nsk; k++) {
+    const uint32_t q = sh + k;
+    uint32_t v;
+    if (q < r.ulen) {
+      const uint32_t w = q >> 3;
+      const uint64_t word = w == 0 ? kw[0] : (w == 1 ? kw[1] : kw[2]);
+      v = (uint32_t)((word >> (8 * (q & 7))) & 0xFF);
+    } else {
+      v = (uint32_t)((r.tag >> (8 * (q - r.ulen))) & 0xFF);
+    }
+    put(ks + k, bb, v);
+  }
+  // value edges: [vs, i0) and [i1, en), at most 30 bytes with no interior
+  const uint8_t* vp = (const uint8_t*)r.vp;
+  const uint32_t nh = min(i0, en) - vs;
+  for (uint32_t k0 = 0; k0 < nh; k0 += 15) {
+    const uint32_t n = min(15u, nh - k0);
+    const u128 v = load_span(vp + k0, n);
+    const uint64_t v0 = (uint64_t)v, v1 = (uint64_t)(v >> 64);
+    for (uint32_t k = 0; k < n; k++) put(vs + k0 + k, bb, byte_of(v0, v1, k));
+  }
+  if (x.pieces && i0 < 16) {  // interior bytes below position 16: slot 0 only
+    const uint32_t nz = min(i1, 16u) - i0;
+    const u128 v = load_span(vp + (i0 - vs), nz);
+    const uint64_t v0 = (uint64_t)v, v1 = (uint64_t)(v >> 64);
+    for (uint32_t k = 0; k < nz; k++) I[i0 + k] = (uint8_t)byte_of(v0, v1, k);
+  }
+  if (x.pieces) {
+    const uint32_t nt = en - i1;
+    if (nt) {
+      const u128 v = load_span(vp + (i1 - vs), nt);
+      const uint64_t v0 = (uint64_t)v, v1 = (uint64_t)(v >> 64);
+      for (uint32_t k = 0; k < nt; k++) put(i1 + k, ba, byte_of(v0, v1, k));
+    }
+  }
+}
+
+// blocks whose gap chunks are written entry-major
+__device__ __forceinline__ bool gap_entry_major(const EncodeArgs& A, const BlockRec& B, uint64_t ns) {
+  return A.kw8 <= GAP_KW8 && gap_em_block(B.cnt, B.size, ns);
+}
+
+// EM = false: the blocks written chunk by chunk; EM = true: the others
+// (two kernels, so that each keeps its own register budget)
+template <bool EM>
 __global__ void __launch_bounds__(256) k_gaps(EncodeArgs A) {
-  __shared__ GapEnt lds[256 / GAP_GROUP][GAP_GROUP];
+  constexpr uint32_t G = EM ? GAP_EM_GROUP : GAP_GROUP;  // lanes per block
+  __shared__ GapEnt lds[EM ? 1 : 256 / GAP_GROUP][GAP_GROUP];
+  __shared__ uint4 img_all[EM ? 256 / GAP_EM_GROUP : 1][GAP_SLOTS];
   const uint64_t nb = *A.nblocks;
-  const uint64_t groups = (uint64_t)gridDim.x * blockDim.x / GAP_GROUP;
+  const uint64_t groups = (uint64_t)gridDim.x * blockDim.x / G;
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t j = threadIdx.x % GAP_GROUP;
-  GapEnt* L = lds[threadIdx.x / GAP_GROUP];
-  for (uint64_t b = tid / GAP_GROUP; b < nb; b += groups) {
+  const uint32_t j = threadIdx.x % G;
+  for (uint64_t b = tid / G; b < nb; b += groups) {
     const BlockRec B = A.blk[b];
     const uint64_t g0 = A.gap_base[b], ns = A.gap_base[b + 1] - g0;
-    if (B.cnt <= GAP_GROUP) {
+    if (gap_entry_major(A, B, ns) != EM) continue;
+    if constexpr (EM) {
+      uint4* img = img_all[threadIdx.x / G];
+      const uint32_t n = B.size + 1, J16 = (n + 15) / 16, gshift = 16 * J16 - n;
+      for (uint64_t g = j; g < ns; g += G) img[g] = make_uint4(0, 0, 0, 0);
+      wave_sync();
+      for (uint32_t i = j; i < B.cnt; i += G) {
+        const EntL e = A.entl[B.s0 + i];
+        GapEnt x;
+        x.r = A.rec[B.s0 + i];
+        x.st = A.ent_off[B.s0 + i];
+        x.ia = e.ia;
+        x.pieces = e.pieces;
+        x.cum = e.cum;
+        gap_entry_bytes(A, B, x, i, gshift, (uint8_t*)img);
+      }
+      // the restart array and the count follow every interior of the block
+      const uint32_t R = B.R, nrest = div_r(B.cnt + R - 1, R);
+      const uint32_t data_end = B.size - 4 * nrest - 4;
+      const int32_t bt = 16 * (1 - (int32_t)(J16 + 1 - (uint32_t)ns)) + (int32_t)gshift;
+      uint8_t* I = (uint8_t*)img;
+      for (uint32_t q = j; q <= nrest; q += G) {
+        const uint32_t v = q < nrest ? A.ent_off[B.s0 + (uint64_t)q * R] : nrest;
+        const uint32_t p = data_end + 4 * q;
+        for (uint32_t k = 0; k < 4; k++) {
+          I[bt + (int32_t)(p + k)] = (uint8_t)(v >> (8 * k));
+          if (p + k < 16) I[p + k] = (uint8_t)(v >> (8 * k));
+        }
+      }
+      wave_sync();
+      for (uint64_t g = j; g < ns; g += G) A.gapbuf[g0 + g] = img[g];
+      wave_sync();
+    } else if (B.cnt <= GAP_GROUP) {
+      GapEnt* L = lds[threadIdx.x / GAP_GROUP];
       if (j < B.cnt) {
         const EntL e = A.entl[B.s0 + j];
         GapEnt x;
@@ -245,6 +362,9 @@ __global__ void __launch_bounds__(256) k_gaps(EncodeArgs A) {
     }
   }
 }
+
+template __global__ void k_gaps<false>(EncodeArgs);
+template __global__ void k_gaps<true>(EncodeArgs);
 
 // ---------------------------------------------------------------------------
 // Encoder: one wave per output data block.  Lane l takes the chunks

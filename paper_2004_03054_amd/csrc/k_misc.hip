@@ -47,7 +47,8 @@ __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_
   if (j <= J) job_s0[j] = kpos[job_e0[j]];
 }
 
-__global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats) {
+__global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap,
+                             const uint32_t* gapcnt, uint32_t* stats) {
   __shared__ uint32_t m0, m1;
   if (threadIdx.x == 0) {
     m0 = 0;
@@ -55,7 +56,7 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
   }
   __syncthreads();
   const uint64_t nb = job_ob0[J];
-  uint32_t sz = 0, cn = 0, tiny = 0, off = 0;
+  uint32_t sz = 0, cn = 0, tiny = 0, off = 0, em = 0;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb && b < cap;
        b += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t s = ob.size[b], c = ob.cnt[b];
@@ -63,10 +64,13 @@ __global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, 
     cn = max(cn, c);
     if (s < 15) tiny = 1;  // a message (contents + type byte) under 16 bytes
     off += enc_pipelined(s, c) ? 0 : 1;
+    em += gap_em_block(c, s, gapcnt[b]) ? 1 : 0;
   }
   if (__ballot(tiny) && lane_id() == 0) atomicMax(&stats[2], 1u);
   off = wave_sum(off);
   if (off && lane_id() == 0) atomicAdd(&stats[3], off);
+  em = wave_sum(em);
+  if (em && lane_id() == 0) atomicAdd(&stats[4], em);
   sz = wave_max(sz);
   cn = wave_max(cn);
   if (lane_id() == 0) {

@@ -216,7 +216,20 @@ struct EncodeArgs {
   const uint64_t* gap_base; // first gap buffer slot of each block (and the total)
   uint4* gapbuf;            // gap chunks (16 bytes each)
 };
-__global__ void k_gaps(EncodeArgs A);
+// Gap chunks are written by groups of GAP_GROUP lanes per block, chunk by
+// chunk, or entry-major by groups of GAP_EM_GROUP lanes (an LDS image of the
+// block's gap slots) for blocks of GAP_EM_MIN to GAP_GROUP entries, at most
+// GAP_SLOTS gap slots and keys of at most GAP_KW8 words
+constexpr uint32_t GAP_GROUP = 16;
+constexpr uint32_t GAP_SLOTS = 64;
+constexpr uint32_t GAP_KW8 = 3;
+constexpr uint32_t GAP_EM_MIN = 4;  // fewer entries leave most of a group's lanes idle
+constexpr uint32_t GAP_EM_GROUP = 8;  // lanes per block in the entry-major form
+__host__ __device__ constexpr bool gap_em_block(uint32_t cnt, uint32_t size, uint64_t slots) {
+  return cnt <= GAP_GROUP && cnt >= GAP_EM_MIN && slots <= GAP_SLOTS && size + 1 >= 16;
+}
+template <bool EM>
+__global__ void k_gaps(EncodeArgs A);  // EM: the entry-major blocks (and A.kw8 <= GAP_KW8), else the others
 __global__ void k_encode(EncodeArgs A);
 // the blocks k_encode leaves: those listed in list[0, nlist), or (list null)
 // every block off the pipelined path
@@ -267,7 +280,11 @@ __global__ void k_gather_u64(const uint64_t* src, const uint64_t* idx, uint32_t 
 __global__ void k_ranges(const uint64_t* ient, const uint64_t* ibase, const uint64_t* blk0_of, uint32_t n,
                          uint64_t* out);
 __global__ void k_job_surv(const uint64_t* job_e0, const uint32_t* kpos, uint32_t J, uint64_t* job_s0);
-__global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap, uint32_t* stats);
+// stats: [0] largest block size, [1] most entries in a block, [2] a block
+// under 16 bytes, [3] blocks off the pipelined encoder, [4] blocks whose
+// gap chunks are written entry-major (gap_entry_major)
+__global__ void k_plan_stats(OutBlocks ob, const uint64_t* job_ob0, uint32_t J, uint64_t cap,
+                             const uint32_t* gapcnt, uint32_t* stats);
 __global__ void k_file_entries(OutFiles of, OutBlocks ob, const uint32_t* surv, Tuples tu, const uint64_t* ie_off,
                                uint64_t nf, const uint8_t* ztype);
 __global__ void k_ingest_max(const uint64_t* koff, uint64_t n, uint32_t* maxlen);

@@ -1132,7 +1132,8 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     A.out = zstage;
     A.blk = zrec;
     A.gapbuf = dbuf<uint4>(c, "gap_buf", zbytes / 16 + 2 * OB + 1);
-    hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, OB * 16)), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_gaps<false>, dim3(stride_grid(c, OB * 16)), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_gaps<true>, dim3(stride_grid(c, OB * 16)), dim3(256), 0, st, A);
     LAUNCH_CHECK();
     launch_encode(c, A, OB, true);
     KTimer kz(c, "k_zsnappy");
@@ -1199,21 +1200,22 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
   launch_scan<uint64_t, uint64_t>(of.nwin, FC, nullptr, of.w0, scan_tmp, st);
   LAUNCH_CHECK();
   // sizes needed to allocate window arrays and the encoder's LDS
-  uint32_t* stats = dbuf<uint32_t>(c, "plan_stats", 4);
-  fill_u32(c, stats, 0, 4);
+  uint32_t* stats = dbuf<uint32_t>(c, "plan_stats", 5);
+  fill_u32(c, stats, 0, 5);
   hipLaunchKernelGGL(k_plan_stats, dim3(std::min<uint32_t>(stride_grid(c, OB), c->n_cu)), dim3(256), 0, st, ob, job_ob0, J, OB,
-                     stats);
+                     gapcnt, stats);
   LAUNCH_CHECK();
   uint64_t NBLK, NF, NW;
   uint32_t max_bsize;
   bool big_blocks = true;
   uint64_t n_off = 0;  // blocks off the pipelined encoder's path
+  uint64_t n_em = 0;   // blocks whose gap chunks are written entry-major
   {
     Mail m(c);
     const uint64_t* a = m.add(job_ob0 + J, 1);
     const uint64_t* b = m.add(job_f0 + J, 1);
     const uint64_t* w = m.add(of.w0 + FC, 1);
-    const uint32_t* x = m.add(stats, 4);
+    const uint32_t* x = m.add(stats, 5);
     m.flush();
     NBLK = *a;
     NF = *b;
@@ -1221,6 +1223,7 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     max_bsize = x[0];
     big_blocks = x[3] != 0;
     n_off = x[3];
+    n_em = P.kw8 <= GAP_KW8 ? x[4] : 0;
     c->counters.emplace_back("max_block_bytes", (double)max_bsize);
   }
 
@@ -1332,7 +1335,9 @@ void plan_and_write(luda_ctx* c, PlanIn& P, PlanOut& O) {
     const uint64_t slots = dout / 16 + 2 * NBLK + 1;
     A.gapbuf = dbuf<uint4>(c, "gap_buf", slots);
     KTimer kg(c, "k_gaps");
-    hipLaunchKernelGGL(k_gaps, dim3(stride_grid(c, NBLK * 16)), dim3(256), 0, st, A);  // 16 threads per block
+    // 16 threads per block; each kernel only when it has blocks
+    if (n_em < NBLK) hipLaunchKernelGGL(k_gaps<false>, dim3(stride_grid(c, NBLK * 16)), dim3(256), 0, st, A);
+    if (n_em) hipLaunchKernelGGL(k_gaps<true>, dim3(stride_grid(c, NBLK * GAP_EM_GROUP)), dim3(256), 0, st, A);
     LAUNCH_CHECK();
     kg.stop();
     launch_encode(c, A, NBLK, big_blocks, off_list, n_off);
