@@ -7,9 +7,9 @@
 //
 //   k_footer     one thread per input: footer magic, index handle
 //   k_blk_nr     one thread per block: restart count
-//   k_crc_wave   one wave per block: masked CRC32C and block type
-//   k_crc_multi  index blocks: 16 KiB segments over the grid, joined by the
-//                last workgroup of each block
+//   k_crc_wave   16 lanes per block: masked CRC32C and block type
+//   k_crc_multi  index blocks: one wave per 4 KiB segment; k_crc_join
+//                joins the segments of each block
 //   k_imap       one thread per restart interval: its block (binary search)
 //   k_walk       one thread per restart interval: walks the interval's
 //                entries (count pass, then emit pass after a prefix sum)
@@ -136,12 +136,20 @@ __device__ inline void finish_crc(const WalkSet& ws, const Inputs& in, uint32_t 
   ok[b] = good;
 }
 
-// One wave per data block.  Block handles are loaded two blocks ahead and
-// a lane's first CRC_Q chunks one block ahead, so that the loads of the next
-// block are in flight while the current one is folded.  Every load of the
-// loop is issued by every lane (a lane with nothing to load reads a fixed
-// valid address and drops the data): the wait for one load then never has
-// to wait for the loads issued after it.
+// Data block checksums.  A block's message (contents and type byte) is cut
+// into 16-byte chunks aligned to its end, and the chunks into rounds of
+// CRC_GL * CRC_RUN chunks (512 B) counted from the end; the top round may
+// reach before the message start.  A wave takes CRC_GPW blocks at a time,
+// one group of CRC_GL lanes per block.  In each round lane j of a group
+// takes CRC_RUN consecutive chunks (the lanes in address order) and runs the
+// table CRC through them from state 0 with no shift in between; the lane
+// adds that to its sum over the rounds by Horner's rule (one shift by a
+// round per round), and the group joins its lanes' sums in log2(CRC_GL)
+// steps, step l shifting by CRC_RUN * 2^l chunks.  Against one wave per
+// block with one chunk per lane per step this halves the round shifts, joins
+// in four steps instead of six, and leaves less of the top round idle on
+// blocks of 4-5 KiB.  Leading zero bytes leave the raw CRC unchanged, so
+// chunks wholly before the message are zeros and need no load.
 struct CrcBlk {
   const uint8_t* p;
   uint64_t n;  // message bytes (contents + type byte); 0: none
@@ -158,40 +166,30 @@ __device__ __forceinline__ CrcBlk crc_blk(const WalkSet& ws, uint64_t b, uint64_
   return r;
 }
 
-// masked CRC32C of (contents || type byte) against the trailer, type 0
+// masked CRC32C of (contents || type byte) against the trailer, type 0 or 1
+// (called by one lane per block)
 __device__ inline uint8_t check_crc(const WalkSet& ws, const Inputs& in, uint32_t b, uint32_t raw, uint32_t stored,
                                     uint32_t type, unsigned long long* err) {
   if ((raw ^ 0xFFFFFFFFu) != crc_unmask(stored)) {
-    if (lane_id() == 0) blk_err(ws, in, b, P_TRAILER, 0, EC_CHECKSUM, err);
+    blk_err(ws, in, b, P_TRAILER, 0, EC_CHECKSUM, err);
     return 0;
   }
   if (type > 1) {  // 0: stored raw; 1: a Snappy stream, decompressed later
-    if (lane_id() == 0) blk_err(ws, in, b, P_TRAILER, 0, EC_UNSUPPORTED, err);
+    blk_err(ws, in, b, P_TRAILER, 0, EC_UNSUPPORTED, err);
     return 0;
   }
   return 1;
 }
 
-// A lane's chunks of a message of n bytes (16-byte chunks aligned to the
-// message end, lane l taking c = 63 - l + 64 i, first to last).
-__device__ __forceinline__ int64_t crc_top_chunk(uint64_t n) {
-  const int64_t J = (int64_t)((n + 15) / 16), c0 = 63 - (int64_t)lane_id();
-  return c0 < J ? c0 + 64 * ((J - 1 - c0) / 64) : -1;
-}
-
-// The first CRC_Q chunks of this lane.  A chunk that starts before the
-// message is read from the message start (the bytes before it are shifted
-// in by the fold): a data block and its trailer are followed by at least the
-// 48-byte footer of their table, so 16 bytes from any block start are
-// readable.
-__device__ __forceinline__ void crc_load_first(const CrcBlk& k, uint64_t safe, uint4 (&v)[CRC_Q]) {
-  const int64_t ct = crc_top_chunk(k.n);
-#pragma unroll
-  for (int q = 0; q < CRC_Q; q++) {
-    const int64_t c = ct - 64 * q, p = (int64_t)k.n - 16 * (c + 1);
-    v[q] = ldg16(c >= 0 ? (uint64_t)(uintptr_t)k.p + (uint64_t)(p > 0 ? p : 0) : safe);
-  }
-}
+constexpr uint32_t CRC_GL = 16;                     // lanes per block
+constexpr uint32_t CRC_GPW = WAVE / CRC_GL;         // blocks per wave
+constexpr uint32_t CRC_RUN = 2;                     // consecutive chunks per lane per round
+constexpr uint32_t CRC_RB = CRC_GL * CRC_RUN * 16;  // bytes per round
+constexpr uint32_t CRC_RQ = 2;                      // rounds whose loads are issued together
+constexpr int CRC_SH_RUN = 1;                       // sh[k] shifts by 2^k chunks
+constexpr int CRC_SH_ROUND = 5;
+static_assert(CRC_RUN == (1u << CRC_SH_RUN) && CRC_GL * CRC_RUN == (1u << CRC_SH_ROUND), "shift tables");
+static_assert(CRC_RQ >= 2, "the first load batch must hold both rounds that can reach below position 4");
 
 __device__ __forceinline__ uint4 bytes_up(uint4 v, uint32_t s) {  // byte k <- byte k - s, zeros below s
   unsigned __int128 x = ((unsigned __int128)(((uint64_t)v.w << 32) | v.z) << 64) | (((uint64_t)v.y << 32) | v.x);
@@ -199,30 +197,59 @@ __device__ __forceinline__ uint4 bytes_up(uint4 v, uint32_t s) {  // byte k <- b
   return make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
 }
 
-// this lane's Horner sum over its chunks; v holds the first CRC_Q of them.
-// Only a lane's first chunk can reach below message position 4.
-__device__ __forceinline__ uint32_t crc_fold(const CrcLds11* T, const CrcBlk& k, const uint4 (&v)[CRC_Q]) {
-  const int64_t ct = crc_top_chunk(k.n), n = (int64_t)k.n;
-  uint32_t acc = 0;
-  if (ct >= 0) {
-    const int64_t p0 = n - 16 * (ct + 1);
-    if (p0 < 4) acc = crc_chunk(&T->b, p0 < 0 ? bytes_up(v[0], (uint32_t)-p0) : v[0], p0);
-    else acc = crc_chunk11(T, v[0]);
+// the chunk at message position p < 4 as the raw CRC sees it (bytes before
+// the message zero, positions 0..3 complemented); it was loaded from
+// position max(p, 0), or not at all when p <= -16
+__device__ __forceinline__ uint4 crc_edge_chunk(uint4 v, int64_t p) {
+  if (p <= -16) return make_uint4(0, 0, 0, 0);
+  if (p < 0) v = bytes_up(v, (uint32_t)-p);
+  v.x = crc_edge(v.x, p);
+  v.y = crc_edge(v.y, p + 4);
+  v.z = crc_edge(v.z, p + 8);
+  v.w = crc_edge(v.w, p + 12);
+  return v;
+}
+
+// loads of a lane's chunks in rounds i .. i + CRC_RQ - 1 (its run of round i
+// starts at message position P0 + CRC_RB i); rounds past R and chunks wholly
+// before the message read a fixed valid address instead.  EDGE: the rounds
+// may reach below message position 4 (only the top two rounds can).
+template <bool EDGE>
+__device__ __forceinline__ void crc_loads(const CrcBlk& k, int64_t P0, uint32_t R, uint32_t i, uint64_t safe,
+                                          uint4 (&v)[CRC_RQ][CRC_RUN]) {
+#pragma unroll
+  for (uint32_t q = 0; q < CRC_RQ; q++) {
+    const int64_t pr = P0 + (int64_t)CRC_RB * (i + q);
+#pragma unroll
+    for (uint32_t s = 0; s < CRC_RUN; s++) {
+      const int64_t p = pr + 16 * s;
+      uint64_t a = (uint64_t)(uintptr_t)k.p + (uint64_t)(EDGE ? (p > 0 ? p : 0) : p);
+      if (i + q >= R || (EDGE && p <= -16)) a = safe;
+      v[q][s] = ldg16(a);
+    }
   }
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void crc_rounds(const CrcLds11* T, int64_t P0, uint32_t R, uint32_t i,
+                                           const uint4 (&v)[CRC_RQ][CRC_RUN], uint32_t& acc) {
 #pragma unroll
-  for (int q = 1; q < CRC_Q; q++)
-    if (ct - 64 * q >= 0) acc = crc_shift(T->b.sh[6], acc) ^ crc_chunk11(T, v[q]);
-  const uint8_t* e = k.p + n;  // chunk c is [e - 16 (c + 1), e - 16 c)
-  for (int64_t c = ct - 64 * CRC_Q; c >= 0; c -= 64 * CRC_Q) {
-    uint4 w[CRC_Q];
+  for (uint32_t q = 0; q < CRC_RQ; q++) {
+    if (i + q < R) {
+      const int64_t pr = P0 + (int64_t)CRC_RB * (i + q);
+      uint32_t r = 0;
 #pragma unroll
-    for (int q = 0; q < CRC_Q; q++)
-      if (c - 64 * q >= 0) w[q] = ldg16((uint64_t)(uintptr_t)(e - 16 * (c - 64 * q + 1)));
-#pragma unroll
-    for (int q = 0; q < CRC_Q; q++)
-      if (c - 64 * q >= 0) acc = crc_shift(T->b.sh[6], acc) ^ crc_chunk11(T, w[q]);
+      for (uint32_t s = 0; s < CRC_RUN; s++) {
+        uint4 x = v[q][s];
+        if (EDGE && pr + 16 * (int64_t)s < 4) x = crc_edge_chunk(x, pr + 16 * (int64_t)s);
+        r = crc_dword11(T, r, x.x);
+        r = crc_dword11(T, r, x.y);
+        r = crc_dword11(T, r, x.z);
+        r = crc_dword11(T, r, x.w);
+      }
+      acc = (EDGE && q == 0) ? r : crc_shift(T->b.sh[CRC_SH_ROUND], acc) ^ r;
+    }
   }
-  return acc;
 }
 
 __global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const uint32_t* g_crc, uint8_t* ok,
@@ -233,33 +260,52 @@ __global__ void __launch_bounds__(1024) k_crc_wave(WalkSet ws, Inputs in, const 
   const uint64_t nb = *ws.n_dev;
   if (nb == 0) return;
   const uint32_t waves = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
-  const uint64_t stride = (uint64_t)gridDim.x * waves;
+  const uint32_t j = lane_id() % CRC_GL, g = lane_id() / CRC_GL;
+  const uint64_t stride = (uint64_t)gridDim.x * waves * CRC_GPW;
   const uint64_t safe = (uint64_t)(uintptr_t)g_crc;
   uint64_t bytes = 0;
-  uint64_t b = (uint64_t)blockIdx.x * waves + wv;
-  CrcBlk k = crc_blk(ws, b, nb), kn = crc_blk(ws, b + stride, nb);
-  uint4 v[CRC_Q];
-  crc_load_first(k, safe, v);
-  for (; b < nb; b += stride) {
-    const CrcBlk knn = crc_blk(ws, b + 2 * stride, nb);
-    const uint64_t ta = k.n ? (uint64_t)(uintptr_t)(k.p + k.n - 1) : safe;  // type byte, then the stored CRC
-    const uint32_t type = ldg_u8(ta);
-    const uint32_t stored = ldg_u8(ta + 1) | (ldg_u8(ta + 2) << 8) | (ldg_u8(ta + 3) << 16) | (ldg_u8(ta + 4) << 24);
-    uint4 vn[CRC_Q];
-    crc_load_first(kn, safe, vn);
-    uint8_t good = 0;
-    if (!k.skip) {
-      const uint32_t raw = crc_wave_join(&T.b, crc_fold(&T, k, v));
-      good = check_crc(ws, in, (uint32_t)b, raw, stored, type, err);
-      bytes += k.n + 4;
-    }
-    ok[b] = good;
+  uint64_t b = ((uint64_t)blockIdx.x * waves + wv) * CRC_GPW + g;
+  CrcBlk kn = crc_blk(ws, b, nb);
+  for (; b - g < nb; b += stride) {
+    const CrcBlk k = kn;
+    kn = crc_blk(ws, b + stride, nb);
+    const int64_t n = (int64_t)k.n;
+    const uint32_t R = (uint32_t)((k.n + CRC_RB - 1) / CRC_RB);
+    uint32_t Rw = R;  // the wave's most rounds
 #pragma unroll
-    for (int q = 0; q < CRC_Q; q++) v[q] = vn[q];
-    k = kn;
-    kn = knn;
+    for (uint32_t m = CRC_GL; m < WAVE; m <<= 1) Rw = max(Rw, (uint32_t)__shfl_xor((int)Rw, (int)m, WAVE));
+    uint32_t type = 0, stored = 0;
+    if (j == 0 && n) {  // type byte, then the stored CRC
+      const uint64_t ta = (uint64_t)(uintptr_t)(k.p + n - 1);
+      type = ldg_u8(ta);
+      stored = ldg_u8(ta + 1) | (ldg_u8(ta + 2) << 8) | (ldg_u8(ta + 3) << 16) | (ldg_u8(ta + 4) << 24);
+    }
+    const int64_t P0 = n - (int64_t)CRC_RB * R + 16 * CRC_RUN * (int64_t)j;
+    uint32_t acc = 0;
+    uint4 v[CRC_RQ][CRC_RUN];
+    if (Rw) {
+      crc_loads<true>(k, P0, R, 0, safe, v);
+      crc_rounds<true>(&T, P0, R, 0, v, acc);
+    }
+    for (uint32_t i = CRC_RQ; i < Rw; i += CRC_RQ) {
+      crc_loads<false>(k, P0, R, i, safe, v);
+      crc_rounds<false>(&T, P0, R, i, v, acc);
+    }
+#pragma unroll
+    for (int l = 0; (1u << l) < CRC_GL; l++) {  // lane j + 2^l's sum follows lane j's by CRC_RUN 2^l chunks
+      const uint32_t other = __shfl_down(acc, 1u << l, WAVE);
+      acc = crc_shift(T.b.sh[CRC_SH_RUN + l], acc) ^ other;
+    }
+    if (j == 0 && b < nb) {
+      uint8_t good = 0;
+      if (!k.skip) {
+        good = check_crc(ws, in, (uint32_t)b, acc, stored, type, err);
+        bytes += k.n + 4;
+      }
+      ok[b] = good;
+    }
   }
-  if (lane_id() == 0 && bytes) atomicAdd(bytes_total, (unsigned long long)bytes);
+  if (j == 0 && bytes) atomicAdd(bytes_total, (unsigned long long)bytes);
 }
 
 // index blocks of the inputs, checked against their trailers
