@@ -63,6 +63,12 @@ TINY_VARIANTS = [
          target_file_size=1 << 20),
     dict(entries=1500, key_alphabet=6, key_len=(2, 8), val_len=(0, 40), block_size=65536, restart_interval=500,
          target_file_size=1 << 20),
+    # one entry per block, blocks of 20 B to 2.3 KiB: the data block checksum
+    # runs over one to five 512-byte rounds, the message start at many
+    # offsets of its round (below and above a chunk edge, in the top round
+    # and in the one after it)
+    dict(entries=1200, key_alphabet=5, key_len=(4, 12), val_len=(0, 2300), block_size=1, restart_interval=1,
+         target_file_size=4 << 20),
     # blocks larger than the encoder's LDS stage (encoded from registers)
     dict(entries=150, key_alphabet=5, key_len=(4, 12), val_len=(1500, 5000), block_size=1 << 20, restart_interval=16,
          target_file_size=4 << 20),
@@ -77,7 +83,7 @@ def test_tiny_variants(vi):
 
 
 def test_long_index_blocks():
-    """Index blocks of about 3 MB (over 64 checksum segments of 16 KiB, so the
+    """Index blocks of about 3 MB (hundreds of 4 KiB checksum segments, so the
     segment join folds several segments per lane), in the inputs and in the
     outputs."""
     job = tiny_job(7, n_inputs=2, entries=150000, key_alphabet=20, key_len=(6, 10), val_len=(0, 6), block_size=40,
