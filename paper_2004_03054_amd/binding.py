@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import struct
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -178,6 +179,73 @@ def options(d: dict) -> LudaOptions:
     return o
 
 
+_JOB_DTYPE = None
+
+
+def _job_dtype() -> np.dtype:
+    """numpy layout of one C job record (offsets taken from the ctypes
+    structures, so the two cannot disagree)."""
+    global _JOB_DTYPE
+    if _JOB_DTYPE is None:
+        fields = [("inputs", "<u8", LudaJob.inputs.offset), ("n_inputs", "<u4", LudaJob.n_inputs.offset)]
+        base = LudaJob.options.offset
+        for name, ct in LudaOptions._fields_:
+            fields.append((name, "<u8" if C.sizeof(ct) == 8 else "<u4", base + getattr(LudaOptions, name).offset))
+        _JOB_DTYPE = np.dtype({"names": [f[0] for f in fields], "formats": [f[1] for f in fields],
+                               "offsets": [f[2] for f in fields], "itemsize": C.sizeof(LudaJob)})
+    return _JOB_DTYPE
+
+
+_OPT_KEYS = ("block_size", "restart_interval", "bloom_bits_per_key", "bottommost", "target_file_size")
+
+
+def batch_records(jobs: Sequence, device_inputs: bool) -> tuple:
+    """The C job records of a batch, (array, keep-alive list): the buffer
+    lists of all jobs in one array of (pointer, size) pairs and the records
+    filled column by column with numpy, the same bytes options() and one
+    buffer list per job would give.  Device inputs are torch tensors, host
+    inputs bytes / bytearray / numpy uint8 arrays."""
+    J = len(jobs)
+    cjobs = (LudaJob * max(1, J))()
+    counts = np.fromiter((len(inp) for inp, _ in jobs), dtype=np.int64, count=J)
+    n = int(counts.sum())
+    flat = np.zeros((max(1, n), 2), dtype=np.uint64)
+    keep = [flat]
+    if device_inputs:
+        ts = [t for inp, _ in jobs for t in inp]
+        sizes = [t.numel() for t in ts]
+        ptrs = [t.data_ptr() if k else 0 for t, k in zip(ts, sizes)]
+    else:
+        arrs = []
+        for inp, _ in jobs:
+            for b in inp:
+                a = b if isinstance(b, np.ndarray) else np.frombuffer(bytes(b), dtype=np.uint8)
+                arrs.append(np.ascontiguousarray(a, dtype=np.uint8))
+        keep.append(arrs)
+        sizes = [a.size for a in arrs]
+        ptrs = [a.ctypes.data if a.size else 0 for a in arrs]
+    if n:
+        flat[:, 0] = ptrs
+        flat[:, 1] = sizes
+    if J:
+        rec = np.frombuffer((C.c_uint8 * C.sizeof(cjobs)).from_address(C.addressof(cjobs)), dtype=_job_dtype())
+        first = np.concatenate(([0], np.cumsum(counts)[:-1]))
+        rec["inputs"][:J] = flat.ctypes.data + 16 * np.minimum(first, max(n - 1, 0)).astype(np.uint64)
+        rec["n_inputs"][:J] = counts
+        opts = [o for _, o in jobs]
+        for k in _OPT_KEYS:
+            rec[k][:J] = [int(o[k]) for o in opts]
+        rec["compression"][:J] = [int(o.get("compression", 0)) for o in opts]
+        for j, o in enumerate(opts):
+            snaps = o.get("snapshots", ())
+            if len(snaps):
+                arr = (C.c_uint64 * len(snaps))(*[int(x) for x in snaps])
+                keep.append(arr)
+                rec["snapshots"][j] = C.addressof(arr)
+                rec["n_snapshots"][j] = len(snaps)
+    return cjobs, keep
+
+
 @dataclass
 class Error:
     status: int
@@ -286,6 +354,66 @@ def _take(ctx, r: LudaResult, device: bool, materialize: bool = True) -> Result:
     return res
 
 
+_RES_DTYPE = None
+
+
+def _np_format(ct) -> str:
+    if ct is C.c_double:
+        return "<f8"
+    if ct is C.c_int32:
+        return "<i4"
+    return "<u8" if C.sizeof(ct) == 8 else "<u4"
+
+
+def _res_dtype() -> np.dtype:
+    """numpy layout of one C result record, the error record's fields
+    flattened as e_<name> (offsets taken from the ctypes structures)."""
+    global _RES_DTYPE
+    if _RES_DTYPE is None:
+        fields = []
+        for name, ct in LudaResult._fields_:
+            off = getattr(LudaResult, name).offset
+            if ct is LudaError:
+                for en, et in LudaError._fields_:
+                    fields.append(("e_" + en, _np_format(et), off + getattr(LudaError, en).offset))
+            else:
+                fields.append((name, _np_format(ct), off))
+        _RES_DTYPE = np.dtype({"names": [f[0] for f in fields], "formats": [f[1] for f in fields],
+                               "offsets": [f[2] for f in fields], "itemsize": C.sizeof(LudaResult)})
+    return _RES_DTYPE
+
+
+_ERR_KEYS = ("e_status", "e_input", "e_where", "e_phase", "e_block", "e_offset")
+_RES_KEYS = ("entries_in", "entries_out", "dropped_shadowed", "dropped_tombstones", "bytes_in", "bytes_out",
+             "ms_total")
+
+
+def take_records(res, J: int, free) -> List[Result]:
+    """Results of a batch without their output bytes (what _take gives with
+    materialize=False): the records' fields read column by column, each
+    job's file records unpacked at once; free(res[j]) then hands job j's
+    buffers back to the library."""
+    if J == 0:
+        return []
+    rec = np.frombuffer((C.c_uint8 * C.sizeof(res)).from_address(C.addressof(res)), dtype=_res_dtype())[:J]
+    col = {n: rec[n].tolist() for n in ("status", "num_files", "files") + _ERR_KEYS + _RES_KEYS}
+    errs = zip(*(col[k] for k in _ERR_KEYS))
+    vals = zip(*(col[k] for k in _RES_KEYS))  # Result's fields after files and file_entries, in order
+    out = []
+    for j, (st, nf, fa, e, v) in enumerate(zip(col["status"], col["num_files"], col["files"], errs, vals)):
+        r = Result(st, Error(*e), [], [], *v)
+        if st == 0 and nf:
+            n7 = 7 * nf  # a file record is seven uint64 fields
+            w = struct.unpack_from("<%dQ" % n7, C.string_at(fa, 8 * n7))
+            r.key_ranges = [(w[i + 3] - w[i], w[i + 4], w[i + 5] - w[i], w[i + 6]) for i in range(0, n7, 7)]
+            r.files = [None] * nf
+            r.file_entries = list(w[2::7])
+            r.file_sizes = list(w[1::7])
+        free(res[j])
+        out.append(r)
+    return out
+
+
 def _bufs(inputs) -> tuple:
     """Host inputs: bytes / bytearray / numpy uint8 arrays (kept alive by the caller)."""
     arrs = []
@@ -380,25 +508,13 @@ class Context:
     def compact_batch(self, jobs: Sequence, device_inputs: bool, materialize: bool = True) -> List[Result]:
         """jobs: sequence of (inputs, options dict)."""
         J = len(jobs)
-        cjobs = (LudaJob * max(1, J))()
-        keep = []
-        if device_inputs:
-            _torch_sync()  # once for the whole batch
-        for j, (inputs, opts) in enumerate(jobs):
-            if device_inputs:
-                bufs = _dev_bufs(inputs, sync=False)
-            else:
-                bufs, arrs = _bufs(inputs)
-                keep.append(arrs)
-            keep.append(bufs)
-            cjobs[j].inputs = C.cast(bufs, C.POINTER(LudaBuf))
-            cjobs[j].n_inputs = len(inputs)
-            o = options(opts)
-            keep.append(o)  # its snapshot array must outlive the call
-            cjobs[j].options = o
+        cjobs, _keep = self._jobs(jobs, device_inputs)
         res = (LudaResult * max(1, J))()
         rc = lib().luda_compact_batch(self._h, cjobs, J, 1 if device_inputs else 0, res)
-        out = [_take(self._h, res[j], device=device_inputs, materialize=materialize) for j in range(J)]
+        if materialize is False:
+            out = take_records(res, J, lambda r: lib().luda_result_free(self._h, C.byref(r)))
+        else:
+            out = [_take(self._h, res[j], device=device_inputs, materialize=materialize) for j in range(J)]
         if rc != 0 and J:
             for o in out:
                 if o.status == 0:
@@ -406,24 +522,9 @@ class Context:
         return out
 
     def _jobs(self, jobs: Sequence, device_inputs: bool):
-        J = len(jobs)
-        cjobs = (LudaJob * max(1, J))()
-        keep = []
         if device_inputs:
             _torch_sync()  # once for the whole batch
-        for j, (inputs, opts) in enumerate(jobs):
-            if device_inputs:
-                bufs = _dev_bufs(inputs, sync=False)
-            else:
-                bufs, arrs = _bufs(inputs)
-                keep.append(arrs)
-            keep.append(bufs)
-            cjobs[j].inputs = C.cast(bufs, C.POINTER(LudaBuf))
-            cjobs[j].n_inputs = len(inputs)
-            o = options(opts)
-            keep.append(o)  # its snapshot array must outlive the call
-            cjobs[j].options = o
-        return cjobs, keep
+        return batch_records(jobs, device_inputs)
 
     def set_mem_limit(self, nbytes: int):
         """Most device bytes the context's buffers may hold at once (0: none)."""
