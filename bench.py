@@ -149,9 +149,9 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="table size scale (1.0 = the stated sizes)")
-    ap.add_argument("--config", type=int, choices=[0, 1, 2], default=1,
-                    help="plain mode: 0 = small (3 x 10k entries), 1 = large (11 x 64 MiB), 2 = variable-size keys "
-                         "and values (7 x 32 MiB)")
+    ap.add_argument("--workload", choices=["small", "large", "variable"], default="large",
+                    help="plain mode: small (3 x 10k entries), large (11 x 64 MiB), variable-size keys and values "
+                         "(7 x 32 MiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: bytes copied per launch (MiB)")
@@ -205,7 +205,7 @@ def main():
         return coopsort_main(args)
     if args.mode == "batchpass":
         return batchpass_main(args)
-    out = plain_record(args, args.config, args.scale, args.steps, args.warmup, not args.no_cpu_baseline,
+    out = plain_record(args, args.workload, args.scale, args.steps, args.warmup, not args.no_cpu_baseline,
                        args.e2e_steps)
     print(json.dumps(out), flush=True)
 
@@ -242,17 +242,18 @@ def roofline_of(kavg: dict, alg: dict, traffic=None) -> tuple:
     return roof, other
 
 
-def plain_record(args, config, scale, steps, warmup, cpu_baseline=True, e2e_steps=3):
+def plain_record(args, workload, scale, steps, warmup, cpu_baseline=True, e2e_steps=3):
     """One plain compaction of a plain workload, inputs resident in HBM,
     timed over `steps` calls; end to end and the oracle beside it."""
     import numpy as np
     import torch
     from paper_2004_03054_amd import Context
-    from workload import config0, config1, config2
+    from workload import plain_small, plain_large, plain_variable
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.time()
-    job = {0: lambda: config0(), 1: lambda: config1(scale=scale), 2: lambda: config2(scale=scale)}[config]()
+    job = {"small": lambda: plain_small(), "large": lambda: plain_large(scale=scale),
+           "variable": lambda: plain_variable(scale=scale)}[workload]()
     log(f"[bench] generated {job.name}: {sum(r.n for r in job.runs)} entries in {time.time() - t0:.1f}s")
     ctx = Context(0)
     tables = device_tables(ctx, job)
@@ -286,7 +287,7 @@ def plain_record(args, config, scale, steps, warmup, cpu_baseline=True, e2e_step
     names = sorted(set(k for kt in ktimes for k in kt))
     kavg = {n: float(np.mean([kt.get(n, 0.0) for kt in ktimes])) for n in names}
     # the committed counters were taken on the large workload only
-    traffic = measured_traffic if (config == 1 and scale == 1.0) else None
+    traffic = measured_traffic if (workload == "large" and scale == 1.0) else None
     roofline, other = roofline_of(kavg, plain_alg_bytes(counters), traffic)
     roofline["path"] = path_roofline(in_bytes, res.bytes_out, ms_step)
 
@@ -364,11 +365,11 @@ def path_roofline(in_bytes: float, out_bytes: float, ms: float) -> dict:
 
 def build_batch_pool(ctx, n_jobs, scale):
     """The batch workload's jobs written as device tables (resident in HBM)."""
-    from workload import config3_job
+    from workload import batch_job
     jobs, tables, in_bytes = [], [], 0
     t0 = time.time()
     for j in range(n_jobs):
-        job = config3_job(j, scale=scale)
+        job = batch_job(j, scale=scale)
         tabs = device_tables(ctx, job)
         tables.append(tabs)
         jobs.append((job.name, job.options()))
@@ -391,7 +392,7 @@ def oracle_on_batch_jobs(ctx, tables, scale, n_oracle, threads):
     also checked byte for byte against the GPU."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
-    from workload import config3_job as mk
+    from workload import batch_job as mk
 
     def prep(j):
         job = mk(j, scale=scale)
@@ -504,7 +505,7 @@ def headline_main(args):
     ctx.close()
     del tables
     torch.cuda.empty_cache()
-    plain = plain_record(args, 1, 1.0, args.steps, args.warmup, not args.no_cpu_baseline, args.e2e_steps)
+    plain = plain_record(args, "large", 1.0, args.steps, args.warmup, not args.no_cpu_baseline, args.e2e_steps)
     out = {
         "metric": "compaction input GB/s (batched vs plain, bit-exact SSTs); p99 job latency",
         "value": round(b["value"], 2),
@@ -592,10 +593,10 @@ def coopsort_main(args):
     import numpy as np
     import torch
     from paper_2004_03054_amd import Context
-    from workload import config1
+    from workload import plain_large
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    job = config1(scale=args.scale)
+    job = plain_large(scale=args.scale)
     ctx = Context(0)
     tables = device_tables(ctx, job)
     in_bytes = sum(int(t.numel()) for t in tables)

@@ -7,7 +7,7 @@ import pytest
 import oracle
 import sstcheck
 from gpu_util import assert_same_files, ctx, say
-from workload import config0, config3_job, tiny_job
+from workload import plain_small, batch_job, tiny_job
 
 pytestmark = pytest.mark.gpu
 
@@ -50,9 +50,9 @@ def first_last_keys(f: bytes):
     return ents[0].ikey, ients[-1].ikey
 
 
-@pytest.mark.parametrize("which", ["config0", "tiny-variants"])
+@pytest.mark.parametrize("which", ["plain_small", "tiny-variants"])
 def test_file_key_ranges(which):
-    jobs = [config0()] if which == "config0" else [
+    jobs = [plain_small()] if which == "plain_small" else [
         tiny_job(300 + s, entries=400, key_alphabet=5, key_len=(1, 30), val_len=(0, 300), block_size=200,
                  target_file_size=1500, restart_interval=3) for s in range(3)]
     for k, job in enumerate(jobs):
@@ -72,7 +72,7 @@ def test_file_key_ranges(which):
 def test_torch_allocator_gives_the_same_bytes():
     import torch
     from paper_2004_03054_amd import Context
-    job = config3_job(2, scale=1 / 64)
+    job = batch_job(2, scale=1 / 64)
     ins = oracle.build_input_tables(job)
     ref = oracle.compact(ins, job.options())
     c = Context(0)
@@ -99,7 +99,7 @@ def test_torch_allocator_gives_the_same_bytes():
 
 def test_memory_limit():
     from paper_2004_03054_amd import Context
-    job = config0()
+    job = plain_small()
     ins = oracle.build_input_tables(job)
     ref = oracle.compact(ins, job.options())
     c = Context(0)
@@ -124,7 +124,7 @@ def test_memory_limit():
 
 def test_server_refuses_a_job_over_the_budget():
     from paper_2004_03054_amd import Server
-    big = config3_job(8, scale=1 / 16)
+    big = batch_job(8, scale=1 / 16)
     small = [tiny_job(s, mode="l0") for s in range(3)]
     ins_big = oracle.build_input_tables(big)
     ins_small = [oracle.build_input_tables(j) for j in small]
@@ -146,7 +146,7 @@ def test_server_refuses_a_job_over_the_budget():
 
 def test_server_cancel():
     from paper_2004_03054_amd import Server
-    jobs = [config3_job(3, scale=1 / 32)] + [tiny_job(20 + s, mode="leveled") for s in range(5)]
+    jobs = [batch_job(3, scale=1 / 32)] + [tiny_job(20 + s, mode="leveled") for s in range(5)]
     ins = [oracle.build_input_tables(j) for j in jobs]
     # one worker, one job per pass, a budget for one job at a time: the later
     # jobs wait in the queue while the first runs

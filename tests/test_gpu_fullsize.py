@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 from gpu_util import say
-from workload import config3_job
+from workload import batch_job
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def dev_digest(tensors):
 def prepare(j):
     """Job j of the batch workload at full size: input tables, the oracle's
     result as digests (the output bytes themselves are not kept)."""
-    job = config3_job(j)
+    job = batch_job(j)
     ins = oracle.build_input_tables(job)
     ref = oracle.compact(ins, job.options())
     meta = (job.name, job.options())  # the generated entries themselves are dropped

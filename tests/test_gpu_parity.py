@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from gpu_util import assert_same_files, ctx, err_tuple, say
-from workload import config0, config1, config2, config3_job, tiny_job
+from workload import plain_small, plain_large, plain_variable, batch_job, tiny_job
 
 pytestmark = pytest.mark.gpu
 
@@ -104,32 +104,32 @@ def test_empty_and_all_dropped():
     assert res.files == [] and ref.files == []
 
 
-def test_config0():
-    run_both(config0(), "config0")
+def test_plain_small():
+    run_both(plain_small(), "plain_small")
 
 
-def test_config0_device_inputs():
-    run_both(config0(), "config0-dev", device=True)
-
-
-@pytest.mark.parametrize("scale", [1 / 64, 1 / 16])
-def test_config1_scaled(scale):
-    run_both(config1(scale=scale), f"config1x{scale}")
+def test_plain_small_device_inputs():
+    run_both(plain_small(), "plain_small-dev", device=True)
 
 
 @pytest.mark.parametrize("scale", [1 / 64, 1 / 16])
-def test_config2_scaled(scale):
-    run_both(config2(scale=scale), f"config2x{scale}")
+def test_plain_large_scaled(scale):
+    run_both(plain_large(scale=scale), f"plain_large-x{scale}")
+
+
+@pytest.mark.parametrize("scale", [1 / 64, 1 / 16])
+def test_plain_variable_scaled(scale):
+    run_both(plain_variable(scale=scale), f"plain_variable-x{scale}")
 
 
 @pytest.mark.parametrize("job", [0, 1, 7])
-def test_config3_jobs_scaled(job):
-    run_both(config3_job(job, scale=1 / 32), f"config3-job{job}")
+def test_batch_jobs_scaled(job):
+    run_both(batch_job(job, scale=1 / 32), f"batch-job{job}")
 
 
 def test_batch_matches_alone():
     jobs = [tiny_job(s, mode=("l0", "leveled")[s % 2], bottommost=s % 2) for s in range(10)]
-    jobs += [config3_job(2, scale=1 / 64), config0()]
+    jobs += [batch_job(2, scale=1 / 64), plain_small()]
     ins = [oracle.build_input_tables(j) for j in jobs]
     say(f"[gpu] batch of {len(jobs)} jobs")
     out = ctx().compact_batch([(i, j.options()) for i, j in zip(ins, jobs)], device_inputs=False)
@@ -142,7 +142,7 @@ def test_batch_matches_alone():
 
 
 # full sizes of the benchmark-class workloads: every output byte compared
-@pytest.mark.parametrize("make,label", [(lambda: config1(), "config1-full"), (lambda: config2(), "config2-full")])
+@pytest.mark.parametrize("make,label", [(lambda: plain_large(), "plain_large-full"), (lambda: plain_variable(), "plain_variable-full")])
 def test_full_size(make, label):
     res, ref = run_both(make(), label, device=True)
     say(f"[gpu] {label}: {len(ref.files)} files, {res.entries_in} entries in, {res.entries_out} out")
@@ -150,7 +150,7 @@ def test_full_size(make, label):
 
 def test_launch_params_do_not_change_bytes():
     """Every launch setting the autotuner may pick gives the same outputs."""
-    job = config3_job(6, scale=1 / 64)
+    job = batch_job(6, scale=1 / 64)
     ins = oracle.build_input_tables(job)
     ref = oracle.compact(ins, job.options())
     c = ctx()
@@ -177,9 +177,9 @@ def test_host_sort_gives_the_same_bytes():
     try:
         for seed in range(4):
             run_both(tiny_job(seed, mode=("l0", "leveled")[seed % 2], bottommost=seed % 2), f"hostsort-tiny-{seed}")
-        run_both(config0(), "hostsort-config0")
-        run_both(config1(scale=1 / 64), "hostsort-config1x1/64")
-        jobs = [tiny_job(20 + s, bottommost=s % 2) for s in range(5)] + [config3_job(3, scale=1 / 64)]
+        run_both(plain_small(), "hostsort-plain_small")
+        run_both(plain_large(scale=1 / 64), "hostsort-plain_large-x1/64")
+        jobs = [tiny_job(20 + s, bottommost=s % 2) for s in range(5)] + [batch_job(3, scale=1 / 64)]
         ins = [oracle.build_input_tables(j) for j in jobs]
         out = c.compact_batch([(i, j.options()) for i, j in zip(ins, jobs)], device_inputs=False)
         for k, (j, i, r) in enumerate(zip(jobs, ins, out)):
@@ -198,7 +198,7 @@ def test_in_place_reads_of_host_and_device_outputs():
     import numpy as np
     import torch
     c = ctx()
-    jobs = [tiny_job(40 + s, bottommost=s % 2) for s in range(3)] + [config0()]
+    jobs = [tiny_job(40 + s, bottommost=s % 2) for s in range(3)] + [plain_small()]
     ins = [oracle.build_input_tables(j) for j in jobs]
     for k, (j, i) in enumerate(zip(jobs, ins)):
         ref = c.compact(i, j.options())
@@ -220,7 +220,7 @@ def test_pooled_output_buffers_are_reused_and_trimmed():
     import torch
     from paper_2004_03054_amd import pool_trim
     c = ctx()
-    j = config0()
+    j = plain_small()
     i = oracle.build_input_tables(j)
     ref = oracle.compact(i, j.options())
     dev = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to("cuda") for b in i]
@@ -241,7 +241,7 @@ def test_contexts_on_threads_share_the_pools():
     give every call the oracle's bytes."""
     import threading
     from paper_2004_03054_amd import Context
-    jobs = [config1(scale=1 / 16), config2(scale=1 / 16)]  # inputs of 4 MiB or more: the staged path
+    jobs = [plain_large(scale=1 / 16), plain_variable(scale=1 / 16)]  # inputs of 4 MiB or more: the staged path
     ins = [oracle.build_input_tables(j) for j in jobs]
     refs = [oracle.compact(i, j.options()) for i, j in zip(ins, jobs)]
     errors = []
@@ -281,8 +281,8 @@ def test_library_before_torch_in_a_fresh_process():
         "from paper_2004_03054_amd import Context\n"
         "c = Context(0)\n"
         "import torch, oracle\n"
-        "from workload import config0\n"
-        "j = config0(); ins = oracle.build_input_tables(j)\n"
+        "from workload import plain_small\n"
+        "j = plain_small(); ins = oracle.build_input_tables(j)\n"
         "dev = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to('cuda') for b in ins]\n"
         "r = c.compact_dev(dev, j.options())\n"
         "ok = [t.cpu().numpy().tobytes() for t in r.files] == oracle.compact(ins, j.options()).files\n"

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from gpu_util import assert_same_files, ctx, err_tuple, say
-from workload import config0, config3_job, tiny_job
+from workload import plain_small, batch_job, tiny_job
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +27,7 @@ def corrupt(blob: bytes, at: int) -> bytes:
 def test_served_mix_matches_oracle(budget, workers, max_batch):
     from paper_2004_03054_amd import Server
     jobs = [tiny_job(s, mode=("l0", "leveled")[s % 2], bottommost=s % 2) for s in range(8)]
-    jobs += [config3_job(4, scale=1 / 64), config0(), config3_job(5, scale=1 / 128)]
+    jobs += [batch_job(4, scale=1 / 64), plain_small(), batch_job(5, scale=1 / 128)]
     ins = [oracle.build_input_tables(j) for j in jobs]
     # one job with a corrupted data block: only it fails
     bad = 3

@@ -5,8 +5,8 @@
   stored raw and with outputs compressed.
 * With compression on, the GPU writer's tables equal the oracle's byte for
   byte: the same streams, the same type per block, the same cuts and
-  handles.  Cases span tiny blocks, 4 and 16 KiB blocks (configs 0-2 with
-  compressible values), blocks past the decoder's LDS share (global path)
+  handles.  Cases span tiny blocks, 4 and 16 KiB blocks (the three plain
+  workloads with compressible values), blocks past the decoder's LDS share (global path)
   and past one 64 KiB compression fragment.
 * A broken stream gives the oracle's error tuple.
 * Each file's smallest and largest internal keys, read from the result,
@@ -20,7 +20,7 @@ import sstcheck
 from gpu_util import assert_same_files, ctx, err_tuple, say
 from test_oracle_errors import handles, reseal
 from test_oracle_snappy import _first_copy
-from workload import compressible, config0, config1, config2, config3_job, tiny_job
+from workload import compressible, plain_small, plain_large, plain_variable, batch_job, tiny_job
 
 pytestmark = pytest.mark.gpu
 
@@ -76,24 +76,24 @@ def test_tiny_compressed_in_and_out(k):
     run_both(job, f"tiny {seed}, raw out", out_compression=0)
 
 
-def test_config0_compressed():
-    job = compressible(config0())
-    ins, ref = run_both(job, "config 0", device=True)
+def test_plain_small_compressed():
+    job = compressible(plain_small())
+    ins, ref = run_both(job, "plain_small", device=True)
     types = [f[b.offset + b.size] for f in ref.files for b in sstcheck.check_table(f, 16, compression=1).blocks]
     assert types.count(1) and types.count(0), "expected both stored forms among the outputs"
-    run_both(job, "config 0, raw out", out_compression=0)
+    run_both(job, "plain_small, raw out", out_compression=0)
 
 
-def test_config1_scaled_compressed():
-    run_both(compressible(config1(scale=1 / 16)), "config 1 at 1/16", device=True)
+def test_plain_large_scaled_compressed():
+    run_both(compressible(plain_large(scale=1 / 16)), "plain_large at 1/16", device=True)
 
 
-def test_config2_scaled_compressed():
-    run_both(compressible(config2(scale=1 / 8)), "config 2 at 1/8", device=True)
+def test_plain_variable_scaled_compressed():
+    run_both(compressible(plain_variable(scale=1 / 8)), "plain_variable at 1/8", device=True)
 
 
 def test_raw_inputs_compressed_outputs():
-    job = config3_job(3, scale=1 / 64)
+    job = batch_job(3, scale=1 / 64)
     job.compression = 1  # random values: nearly every block stays raw
     run_both(job, "batch job 3 at 1/64, random values")
 
@@ -110,7 +110,7 @@ def test_batch_mixes_compressed_and_raw_jobs():
 
 
 def test_broken_stream_error_tuple():
-    job = compressible(config0())
+    job = compressible(plain_small())
     ts = [bytearray(t) for t in oracle.build_input_tables(job)]
     _, hs = handles(bytes(ts[1]))
     k = next(i for i, (bo, bs) in enumerate(hs) if ts[1][bo + bs] == 1 and i > 3)

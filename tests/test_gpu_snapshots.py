@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from gpu_util import assert_same_files, ctx, say
-from workload import config0, config1, tiny_job
+from workload import plain_small, plain_large, tiny_job
 
 pytestmark = pytest.mark.gpu
 
@@ -44,18 +44,18 @@ def test_tiny_with_snapshots(seed):
         both(job, opts, f"tiny{seed}-k{k}")
 
 
-def test_config0_with_snapshots():
-    job = config0()
+def test_plain_small_with_snapshots():
+    job = plain_small()
     s = seqs_of(job)
     opts = dict(job.options(), snapshots=[s[len(s) // 5], s[len(s) // 2], s[-2]])
-    both(job, opts, "config0-snaps")
+    both(job, opts, "plain_small-snaps")
 
 
-def test_config1_scaled_with_snapshots():
-    job = config1(scale=1 / 64)
+def test_plain_large_scaled_with_snapshots():
+    job = plain_large(scale=1 / 64)
     s = seqs_of(job)
     opts = dict(job.options(), snapshots=[s[k * len(s) // 9] for k in range(1, 9)])
-    both(job, opts, "config1x1/64-snaps")
+    both(job, opts, "plain_large-x1/64-snaps")
 
 
 def test_batch_mixes_snapshot_rules():

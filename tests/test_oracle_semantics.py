@@ -16,7 +16,7 @@ from hypothesis import given, settings, strategies as st, HealthCheck
 
 import oracle
 from sstcheck import check_output
-from workload import tiny_job, config0, config1, config2, config3_job
+from workload import tiny_job, plain_small, plain_large, plain_variable, batch_job
 
 
 def replay(job):
@@ -85,8 +85,8 @@ def test_zero_inputs_and_all_dropped():
     assert res.files == [] and res.entries_out == 0
 
 
-def test_config0_shape():
-    job = config0()
+def test_plain_small_shape():
+    job = plain_small()
     res = check_job_fast(job)
     assert res.entries_in == 30000
     assert 100 < res.dropped_shadowed < 300
@@ -94,7 +94,7 @@ def test_config0_shape():
 
 
 def check_job_fast(job):
-    """Like check_job but with a vectorised replay (for the larger configs)."""
+    """Like check_job but with a vectorised replay (for the larger workloads)."""
     ins = oracle.build_input_tables(job)
     res = oracle.compact(ins, job.options())
     assert res.status == 0, res.error
@@ -124,7 +124,7 @@ def check_job_fast(job):
     return res
 
 
-@pytest.mark.parametrize("make", [lambda: config1(scale=1 / 256), lambda: config2(scale=1 / 256),
-                                  lambda: config3_job(0, scale=1 / 256), lambda: config3_job(1, scale=1 / 256)])
-def test_scaled_configs(make):
+@pytest.mark.parametrize("make", [lambda: plain_large(scale=1 / 256), lambda: plain_variable(scale=1 / 256),
+                                  lambda: batch_job(0, scale=1 / 256), lambda: batch_job(1, scale=1 / 256)])
+def test_scaled_workloads(make):
     check_job_fast(make())

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import sstcheck
-from workload import compressible, config0, tiny_job
+from workload import compressible, plain_small, tiny_job
 
 
 def varint(v: int) -> bytes:
@@ -190,7 +190,7 @@ def _blocks(table: bytes):
 
 
 def test_compressed_tables_store_a_block_compressed_iff_it_saves_an_eighth():
-    job = compressible(config0())
+    job = compressible(plain_small())
     ins = oracle.build_input_tables(job)
     types = [x[3] for t in ins for x in _blocks(t)]
     assert 0 < types.count(1) < len(types), "the variant should mix compressed and raw blocks"
@@ -203,7 +203,7 @@ def test_compressed_tables_store_a_block_compressed_iff_it_saves_an_eighth():
                 assert t[off:off + size] == z
 
 
-@pytest.mark.parametrize("make", [lambda: compressible(config0()),
+@pytest.mark.parametrize("make", [lambda: compressible(plain_small()),
                                   lambda: compressible(tiny_job(3, entries=400, val_len=(0, 300),
                                                                 block_size=512, target_file_size=4096), 3)])
 def test_compaction_with_compression_reads_back_the_same(make):
@@ -254,7 +254,7 @@ def _first_copy(z: bytes) -> int:
 
 
 def test_a_bad_copy_in_a_data_block_is_reported_at_its_element():
-    job = compressible(config0())
+    job = compressible(plain_small())
     t = bytearray(oracle.build_input_tables(job)[1])
     blocks = sstcheck.check_table(bytes(t), 16, compression=1).blocks
     k = next(i for i, b in enumerate(blocks) if t[b.offset + b.size] == 1 and i > 2)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from gpu_util import say
-from workload import config0, tiny_job
+from workload import plain_small, tiny_job
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def host(tensors):
 def test_noalloc_matches_compact_dev_on_two_calls():
     import torch
     from paper_2004_03054_amd import Context
-    jobs = [config0(), tiny_job(5, mode="l0", bottommost=0)]  # the second is smaller
+    jobs = [plain_small(), tiny_job(5, mode="l0", bottommost=0)]  # the second is smaller
     c = Context(0)
     try:
         out = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")
@@ -59,7 +59,7 @@ def test_noalloc_rejects_sizes_past_its_limits():
     from paper_2004_03054_amd import Context
     c = Context(0)
     try:
-        job = config0()
+        job = plain_small()
         ins = oracle.build_input_tables(job)
         dev = to_dev(ins)
         small_out = torch.empty(4096, dtype=torch.uint8, device="cuda")

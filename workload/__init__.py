@@ -7,6 +7,6 @@ library consume what it draws; each encodes or decodes tables on its own.
 """
 from .generate import (  # noqa: F401
     Run, Job, TYPE_DELETION, TYPE_VALUE,
-    config0, config1, config2, config3_job, config3_sizes, tiny_job, job_input_bytes_estimate,
+    plain_small, plain_large, plain_variable, batch_job, batch_job_sizes, tiny_job, job_input_bytes_estimate,
     compressible,
 )

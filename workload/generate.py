@@ -13,7 +13,7 @@ table's entries as sorted, typed key/value records; turning it into table bytes
 is the job of whichever side consumes it (the oracle's table writer, or the GPU
 library's own writer).
 
-Conventions shared by every configuration:
+Conventions shared by every workload:
 
 * internal key order inside a run: user key ascending (bytewise, shorter key
   first on a common prefix), then tag descending, where
@@ -41,8 +41,10 @@ MiB = 1 << 20
 _U64 = np.uint64
 
 
-def config_seed(config: int, job: int = 0) -> int:
-    return SEED_BASE ^ (config << 32) ^ job
+def workload_seed(workload: int, job: int = 0) -> int:
+    """Default seed of a workload (0 plain small, 1 plain large, 2 plain
+    variable, 3 batch) and of one job of it."""
+    return SEED_BASE ^ (workload << 32) ^ job
 
 
 @dataclass
@@ -225,17 +227,17 @@ def _sorted_key16(ids: np.ndarray, salt: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# configuration 0: plain single compaction, small
+# plain small: one compaction of three small tables
 
 
-def config0(seed: Optional[int] = None) -> Job:
+def plain_small(seed: Optional[int] = None) -> Job:
     """1 upper table (10,000 entries) + 2 disjoint lower tables (10,000 each).
 
     Ids uniform over [0, 2**20) so upper/lower duplicates occur; 100-byte
     values; 5% tombstones; 4 KiB blocks, restart interval 16, 10 bits/key;
     output split at 2 MiB; bottom level (tombstones dropped).
     """
-    seed = config_seed(0) if seed is None else seed
+    seed = workload_seed(0) if seed is None else seed
     rng = np.random.default_rng(seed)
     salt = int(rng.integers(0, 2**63))
     lower_ids = rng.choice(1 << 20, 20000, replace=False)
@@ -248,7 +250,7 @@ def config0(seed: Optional[int] = None) -> Job:
 
 
 # ----------------------------------------------------------------------------
-# configuration 1: plain large (Zipf 0.99 over 2**32, 1 KiB values)
+# plain large: Zipf 0.99 over 2**32, 1 KiB values
 
 
 def _draw_distinct_zipf(rng, count: int, salt32: int, exclude=None) -> np.ndarray:
@@ -262,7 +264,7 @@ def _draw_distinct_zipf(rng, count: int, salt32: int, exclude=None) -> np.ndarra
     return rng.choice(got, count, replace=False)
 
 
-def config1(seed: Optional[int] = None, scale: float = 1.0) -> Job:
+def plain_large(seed: Optional[int] = None, scale: float = 1.0) -> Job:
     """1 upper + 10 lower tables of ~64 MiB each (~700 MiB input).
 
     16-byte keys whose ids are Zipf(0.99)-distributed ranks over [1, 2**32]
@@ -270,7 +272,7 @@ def config1(seed: Optional[int] = None, scale: float = 1.0) -> Job:
     not the bottom level (tombstones kept); 4 KiB blocks; 64 MiB output files.
     ``scale`` shrinks the table sizes for quick runs.
     """
-    seed = config_seed(1) if seed is None else seed
+    seed = workload_seed(1) if seed is None else seed
     rng = np.random.default_rng(seed)
     salt = int(rng.integers(0, 2**63))
     salt32 = int(rng.integers(0, 2**32))
@@ -287,7 +289,7 @@ def config1(seed: Optional[int] = None, scale: float = 1.0) -> Job:
 
 
 # ----------------------------------------------------------------------------
-# configuration 2: variable-size keys and values
+# plain variable: variable-size keys and values
 
 
 def _var_keys(rng, n: int, prefixes: np.ndarray, lmin: int, lmax: int):
@@ -358,12 +360,12 @@ def _var_level(rng, n_target_bytes: List[int], prefixes, seq_base, p_tomb):
     return runs
 
 
-def config2(seed: Optional[int] = None, scale: float = 1.0) -> Job:
+def plain_variable(seed: Optional[int] = None, scale: float = 1.0) -> Job:
     """1 upper + 6 lower tables of ~32 MiB; keys 8-64 B sharing 1,024 8-byte
     prefixes; lognormal values (median 256 B, clipped to [16, 4096]); 10%
     tombstones; 16 KiB blocks, restart interval 16; bottom level; 32 MiB files.
     """
-    seed = config_seed(2) if seed is None else seed
+    seed = workload_seed(2) if seed is None else seed
     rng = np.random.default_rng(seed)
     prefixes = np.frombuffer(rng.bytes(1024 * 8), dtype=np.uint8).reshape(1024, 8)
     size = max(4096, int(32 * MiB * scale))
@@ -374,25 +376,25 @@ def config2(seed: Optional[int] = None, scale: float = 1.0) -> Job:
 
 
 # ----------------------------------------------------------------------------
-# configuration 3: a batch of uneven jobs
+# batch: uneven jobs
 
 
-def config3_sizes(job: int, seed: Optional[int] = None):
+def batch_job_sizes(job: int, seed: Optional[int] = None):
     """(n_lower, [upper MiB, lower MiB...]) for batch job `job`."""
-    seed = config_seed(3, job) if seed is None else seed
+    seed = workload_seed(3, job) if seed is None else seed
     rng = np.random.default_rng(seed)
     n_lower = int(rng.integers(1, 13))
     sizes = [int(s) for s in rng.integers(2, 65, n_lower + 1)]
     return n_lower, sizes
 
 
-def config3_job(job: int, seed: Optional[int] = None, scale: float = 1.0) -> Job:
+def batch_job(job: int, seed: Optional[int] = None, scale: float = 1.0) -> Job:
     """Batch job: 1 upper + U{1..12} lower tables of U{2..64} MiB each; 16-byte
     keys over a per-job salted id space of 2**22; values U{100..1024} B; 5%
     tombstones; 4 KiB blocks; 64 MiB output files; bottom level on even jobs.
     """
-    seed = config_seed(3, job) if seed is None else seed
-    n_lower, sizes = config3_sizes(job, seed)
+    seed = workload_seed(3, job) if seed is None else seed
+    n_lower, sizes = batch_job_sizes(job, seed)
     rng = np.random.default_rng(seed ^ 0x5EED)
     salt = int(rng.integers(0, 2**63))
     est = 16 + 8 + 562 + 4
