@@ -1,6 +1,7 @@
 """Host-side logic of bench.py (no GPU): the one-GPU guard, the output
-fingerprints that compare served and plain results, and the host record of
-the oracle's timing."""
+fingerprints that compare served and plain results, the host record of
+the oracle's timing, and the gate that reports counter-measured traffic
+only for the sources it was measured on."""
 import os
 import subprocess
 import sys
@@ -35,3 +36,23 @@ def test_host_fingerprint_tells_outputs_apart():
 def test_host_info_names_the_cores():
     h = bench.host_info()
     assert h["nproc"] == os.cpu_count() and isinstance(h["cpu_model"], str)
+
+
+def test_traffic_is_reported_only_for_the_sources_it_was_measured_on(tmp_path):
+    """measured_traffic gives the committed per-launch bytes while the
+    encoder's sources hash to the recorded sha256, and None for another
+    hash, another kernel or a missing file."""
+    import hashlib
+    csrc = os.path.join(os.path.dirname(bench.__file__), "paper_2004_03054_amd", "csrc")
+    h = hashlib.sha256()
+    for f in bench.TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    good = tmp_path / "good.md"
+    good.write_text(f"notes\n\ntraffic k_encode bytes_per_launch=12345 sources_sha256={h.hexdigest()}\n")
+    assert bench.measured_traffic("k_encode", str(good)) == 12345.0
+    assert bench.measured_traffic("k_gaps", str(good)) is None
+    stale = tmp_path / "stale.md"
+    stale.write_text("traffic k_encode bytes_per_launch=12345 sources_sha256=" + "0" * 64 + "\n")
+    assert bench.measured_traffic("k_encode", str(stale)) is None
+    assert bench.measured_traffic("k_encode", str(tmp_path / "missing.md")) is None
